@@ -1,0 +1,142 @@
+/*
+ * bf.h -- C ABI of libbf.so, the MI355X (gfx950) implementation of the
+ * accelerated shiftable O(1) Gaussian bilateral filter (Chaudhury,
+ * "Acceleration of the shiftable O(1) algorithm for bilateral filtering and
+ * non-local means").
+ *
+ * The filter computed is Algorithm 2 of the paper:
+ *   1. window radius R (a factor of sigma_s, Section 2: R = 3 sigma_s),
+ *   2. the dynamic range T of eq. (bound) by Algorithm 1 (row then column
+ *      MAX-FILTER of the Appendix) or a caller-given global T,
+ *   3. the order N = 0.405 (T/sigma_r)^2 (Section 1.3, Table 1),
+ *   4. the truncation M by the sigma_r bands of Algorithm 2 step 4 with eqs.
+ *      (trunc) and (Chernoff),
+ *   5. the truncated raised-cosine range kernel of eq. (approx),
+ *   6. SHIFTABLE-BF (Section 1.2): for every kept frequency the images
+ *      f cos(w f), f sin(w f), cos(w f), sin(w f) are smoothed by a separable
+ *      spatial Gaussian (eq. (GF)) and combined by eqs. (f1), (f2).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns bf_status; nothing throws across the ABI.
+ *  - Device pointers are HIP device addresses on the current device; the
+ *    caller owns them and keeps them alive until the stream work completes.
+ *  - `hip_stream` is a hipStream_t (NULL = the null stream).  All device work
+ *    of a call is enqueued on it; calls return without synchronising unless a
+ *    report is requested.
+ *  - All argument checks run before any launch: a call that returns an error
+ *    has enqueued no work and written no output.
+ *  - Images are row-major, `in_pitch`/`out_pitch` elements between rows.
+ *    Input: uint8, uint16 or float32.  Output: always float32, same units as
+ *    the input.
+ *  - A plan is not re-entrant: one stream at a time per plan.  Separate plans
+ *    on separate streams are independent.
+ */
+#ifndef BF_H_
+#define BF_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BF_OK = 0,
+  BF_ERR_INVALID_ARG = 1,   /* a parameter is out of its documented range     */
+  BF_ERR_UNSUPPORTED = 2,   /* valid but beyond this build's limits           */
+  BF_ERR_OUT_OF_MEMORY = 3, /* a device or host allocation failed             */
+  BF_ERR_DEVICE = 4,        /* a HIP call failed (see bf_last_error_detail)   */
+  BF_ERR_NOT_FINITE = 5,    /* float input held NaN or Inf (report requested) */
+  BF_ERR_RANGE = 6          /* input exceeded value_range (report requested)  */
+} bf_status;
+
+typedef enum { BF_U8 = 0, BF_U16 = 1, BF_F32 = 2 } bf_dtype;
+
+/* How T is obtained (Algorithm 2 step 2). */
+typedef enum {
+  BF_T_GLOBAL = 0, /* T = t_value (0 => value_range), as in the original SHIFTABLE-BF */
+  BF_T_LOCAL = 1   /* T from Algorithm 1 over the (2R+1)^2 square window          */
+} bf_trange;
+
+/* Spatial smoother of SHIFTABLE-BF step 3. */
+typedef enum {
+  BF_BLUR_AUTO = 0,            /* autotuner picks among variants that meet the error gate */
+  BF_BLUR_IIR_F32 = 1,         /* Young-van Vliet recursive Gaussian, FP32 scans          */
+  BF_BLUR_TOEPLITZ_F16 = 2,    /* FIR taps exp(-j^2/2 s^2), |j|<=R, FP16 MFMA, FP32 acc   */
+  BF_BLUR_TOEPLITZ_BF16 = 3,   /* same FIR, BF16 MFMA, FP32 accumulation                  */
+  BF_BLUR_TOEPLITZ_F16X2 = 4,  /* same FIR, FP16 hi+lo split operands, FP32 accumulation  */
+  BF_BLUR_TOEPLITZ_BF16X2 = 5  /* same FIR, BF16 hi+lo split operands, FP32 accumulation  */
+} bf_blur;
+
+typedef struct {
+  int32_t height, width;   /* >= 1                                                   */
+  int64_t in_pitch;        /* elements between input rows; 0 => width               */
+  int64_t out_pitch;       /* elements between output rows; 0 => width              */
+  bf_dtype dtype;
+  double sigma_s;          /* spatial sigma in pixels (> 0; >= 0.5 for the IIR)     */
+  double sigma_r;          /* range sigma in intensity units (> 0)                  */
+  double eps;              /* truncation tolerance, 0 < eps < 1 (fraction of peak)  */
+  int32_t radius;          /* window R, 0 => ceil(3 sigma_s); also the FIR radius   */
+  bf_trange t_mode;
+  double t_value;          /* GLOBAL only: T; 0 => value_range                      */
+  double value_range;      /* intensities lie in [0, value_range]; 0 => 255 for u8
+                              and f32, 65535 for u16.  Sets the T table size and
+                              the sigma_r bands (given in 8-bit units) of step 4. */
+  bf_blur blur;
+} bf_params;
+
+/* Per-image result summary (filled only when requested; requesting it makes
+ * the call synchronise its stream). */
+typedef struct {
+  double T;          /* dynamic range used (raw maximum for float input)      */
+  int32_t T_used;    /* integer T indexing the order table (ceil for floats)   */
+  int32_t N, M;      /* order and truncation                                   */
+  int32_t kept;      /* kept terms N - 2M + 1                                  */
+  int32_t pairs;     /* frequency pairs blurred (with the zero frequency)      */
+  int32_t variant;   /* bf_blur actually run                                   */
+  int32_t flags;     /* bit0 non-finite input, bit1 T above value_range        */
+  int64_t q_nonpos;  /* pixels whose denominator (f2) was <= 0 (output = input) */
+  float ms;          /* device time of the call                                */
+} bf_report;
+
+typedef struct bf_plan_s *bf_plan_t;
+
+/* Build a plan for n_images images; params[i] describes image i.  Host-side
+ * FP64 order/coefficient tables for every integer T in [0, value_range] and
+ * the operator constants are computed and uploaded; the workspace is
+ * allocated on the current device.  No image data is read.
+ * Errors: BF_ERR_INVALID_ARG (bad params, n_images < 1, NULL pointers),
+ * BF_ERR_UNSUPPORTED (order or width beyond the build limits),
+ * BF_ERR_OUT_OF_MEMORY, BF_ERR_DEVICE.  On error *out is set to NULL. */
+bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out);
+
+/* Filter image 0 of the plan: d_in (dtype, in_pitch) -> d_out (float32,
+ * out_pitch).  Enqueued on hip_stream; rep (nullable) receives the summary and
+ * makes the call synchronise.  BF_ERR_NOT_FINITE / BF_ERR_RANGE can only be
+ * returned when rep is given (they need the device flags). */
+bf_status bf_filter(bf_plan_t plan, const void *d_in, float *d_out, void *hip_stream,
+                    bf_report *rep);
+
+/* Filter images 0..n-1 of the plan (n <= n_images) in one graph launch of the
+ * batched kernels: d_in[i] / d_out[i] are device pointers to image i (host
+ * arrays of n pointers).  reps (nullable) has n entries. */
+bf_status bf_filter_batch(bf_plan_t plan, int32_t n, const void *const *d_in, float *const *d_out,
+                          void *hip_stream, bf_report *reps);
+
+/* Algorithm 1 alone for image 0: writes the dynamic range T (raw, before any
+ * ceil) to *T_out after synchronising hip_stream. */
+bf_status bf_dynamic_range(bf_plan_t plan, const void *d_in, void *hip_stream, double *T_out);
+
+/* Release the plan.  The caller synchronises the plan's streams first. */
+void bf_plan_destroy(bf_plan_t plan);
+
+/* Static description of a status code. */
+const char *bf_status_string(bf_status s);
+
+/* Detail of the last BF_ERR_DEVICE / BF_ERR_UNSUPPORTED on this thread. */
+const char *bf_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BF_H_ */

@@ -1,0 +1,382 @@
+// Plan runtime and C ABI of libbf.so (declared in include/bf.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bf_device.h"
+#include "bf_internal.h"
+
+using namespace bfi;
+
+namespace {
+
+thread_local std::string g_detail;
+
+bf_status fail(bf_status s, const std::string &why) {
+  g_detail = why;
+  return s;
+}
+
+bf_status dev_fail(hipError_t e, const char *what) {
+  g_detail = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? BF_ERR_OUT_OF_MEMORY : BF_ERR_DEVICE;
+}
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+};
+
+// Everything one image needs on the device.
+struct ImagePlan {
+  bf_params p{};
+  int R = 0;
+  double range = 0.0;
+  int32_t T_cap = 0;
+  int32_t T_global = 0;    // GLOBAL mode: table index
+  double T_global_raw = 0.0;
+  Geom g{};
+  OrderTable tab;
+  int KC = 0;              // frequency pairs per launch of the blur passes
+  int variant = BF_BLUR_IIR_F32;
+  // device memory
+  int32_t *d_idx = nullptr;
+  OrderEntry *d_ent = nullptr;
+  int32_t *d_pm = nullptr;
+  float *d_pc = nullptr;
+  float *d_iir = nullptr;
+  void *d_state = nullptr;  // T_used, flags, T_raw, q_nonpos
+};
+
+size_t elem_size(bf_dtype d) { return d == BF_U8 ? 1 : (d == BF_U16 ? 2 : 4); }
+
+}  // namespace
+
+struct bf_plan_s {
+  int device = 0;
+  std::vector<ImagePlan> im;
+  // workspace shared by the images of the plan (they run one after another)
+  void *d_rowmax = nullptr;
+  float4 *d_cb = nullptr;
+  float4 *d_Z = nullptr;
+  float2 *d_PQ = nullptr;
+  size_t rowmax_bytes = 0, cb_bytes = 0, Z_bytes = 0, PQ_bytes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+DevState state_of(const ImagePlan &ip) {
+  DevState st;
+  char *b = (char *)ip.d_state;
+  st.T_used = (int32_t *)(b + 0);
+  st.flags = (int32_t *)(b + 4);
+  st.T_raw = (unsigned long long *)(b + 8);
+  st.q_nonpos = (unsigned long long *)(b + 16);
+  return st;
+}
+
+DevTables tables_of(const ImagePlan &ip) {
+  DevTables t;
+  t.idx_of_T = ip.d_idx;
+  t.ent = ip.d_ent;
+  t.pm = ip.d_pm;
+  t.pc = ip.d_pc;
+  t.T_cap = ip.T_cap;
+  return t;
+}
+
+bf_status check_params(const bf_params &p) {
+  if (p.height < 1 || p.width < 1) return fail(BF_ERR_INVALID_ARG, "height and width must be >= 1");
+  if (p.in_pitch < 0 || (p.in_pitch > 0 && p.in_pitch < p.width))
+    return fail(BF_ERR_INVALID_ARG, "in_pitch must be 0 or >= width");
+  if (p.out_pitch < 0 || (p.out_pitch > 0 && p.out_pitch < p.width))
+    return fail(BF_ERR_INVALID_ARG, "out_pitch must be 0 or >= width");
+  if (p.dtype != BF_U8 && p.dtype != BF_U16 && p.dtype != BF_F32)
+    return fail(BF_ERR_INVALID_ARG, "unknown dtype");
+  if (!(p.sigma_s > 0.0) || !std::isfinite(p.sigma_s)) return fail(BF_ERR_INVALID_ARG, "sigma_s must be > 0");
+  if (!(p.sigma_r > 0.0) || !std::isfinite(p.sigma_r)) return fail(BF_ERR_INVALID_ARG, "sigma_r must be > 0");
+  if (!(p.eps > 0.0 && p.eps < 1.0)) return fail(BF_ERR_INVALID_ARG, "eps must lie in (0, 1)");
+  if (p.radius < 0) return fail(BF_ERR_INVALID_ARG, "radius must be >= 0");
+  if (p.t_mode != BF_T_GLOBAL && p.t_mode != BF_T_LOCAL) return fail(BF_ERR_INVALID_ARG, "unknown t_mode");
+  if (p.t_value < 0.0 || !std::isfinite(p.t_value)) return fail(BF_ERR_INVALID_ARG, "t_value must be >= 0");
+  if (p.value_range < 0.0 || !std::isfinite(p.value_range))
+    return fail(BF_ERR_INVALID_ARG, "value_range must be >= 0");
+  if (p.blur < BF_BLUR_AUTO || p.blur > BF_BLUR_TOEPLITZ_BF16X2) return fail(BF_ERR_INVALID_ARG, "unknown blur");
+  return BF_OK;
+}
+
+bf_status upload(void **dst, const void *src, size_t bytes) {
+  hipError_t e = hipMalloc(dst, bytes ? bytes : 16);
+  if (e != hipSuccess) return dev_fail(e, "hipMalloc(table)");
+  if (bytes) {
+    e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return dev_fail(e, "hipMemcpy(table)");
+  }
+  return BF_OK;
+}
+
+bf_status prepare_image(const bf_params &p, ImagePlan &ip) {
+  ip.p = p;
+  const double full = p.dtype == BF_U16 ? 65535.0 : 255.0;
+  ip.range = p.value_range > 0.0 ? p.value_range : full;
+  if (p.dtype == BF_U8 && ip.range > 255.0) return fail(BF_ERR_INVALID_ARG, "value_range above 255 for u8");
+  if (p.dtype == BF_U16 && ip.range > 65535.0) return fail(BF_ERR_INVALID_ARG, "value_range above 65535 for u16");
+  ip.R = p.radius > 0 ? p.radius : (int)std::ceil(3.0 * p.sigma_s);
+  if (ip.R > 1024) return fail(BF_ERR_UNSUPPORTED, "radius above 1024");
+  if (p.width > kMaxWidth) return fail(BF_ERR_UNSUPPORTED, "width above 8192");
+  double Tg = p.t_value > 0.0 ? p.t_value : ip.range;
+  double cap = std::ceil(ip.range);
+  if (p.t_mode == BF_T_GLOBAL) cap = std::max(cap, std::ceil(Tg));
+  if (cap > 4194304.0) return fail(BF_ERR_UNSUPPORTED, "value range above 2^22");
+  ip.T_cap = (int32_t)cap;
+  ip.T_global = (int32_t)std::ceil(Tg);
+  ip.T_global_raw = Tg;
+  int variant = p.blur == BF_BLUR_AUTO ? BF_BLUR_IIR_F32 : p.blur;
+  if (variant != BF_BLUR_IIR_F32) return fail(BF_ERR_UNSUPPORTED, "blur variant not built");
+  ip.variant = variant;
+  std::string err;
+  if (!build_order_table(p.sigma_r, p.eps, ip.range, ip.T_cap, ip.tab, err)) return fail(BF_ERR_UNSUPPORTED, err);
+  std::vector<float> iir;
+  if (!build_iir_consts(p.sigma_s, iir, err)) return fail(BF_ERR_INVALID_ARG, err);
+  // geometry
+  Geom &g = ip.g;
+  g.H = p.height;
+  g.W = p.width;
+  g.pitch = p.in_pitch > 0 ? p.in_pitch : p.width;
+  g.opitch = p.out_pitch > 0 ? p.out_pitch : p.width;
+  int S = 1, logS = 0;
+  while (S * kC < g.W) { S <<= 1; logS++; }
+  g.S = S;
+  g.logS = logS;
+  g.Spos = S * kC;
+  g.nc = (g.H + kB - 1) / kB;
+  g.center = (float)(0.5 * ip.range);
+  // device tables
+  bf_status st;
+  if ((st = upload((void **)&ip.d_idx, ip.tab.idx_of_T.data(), ip.tab.idx_of_T.size() * 4))) return st;
+  if ((st = upload((void **)&ip.d_ent, ip.tab.ent.data(), ip.tab.ent.size() * sizeof(OrderEntry)))) return st;
+  if ((st = upload((void **)&ip.d_pm, ip.tab.pm.data(), ip.tab.pm.size() * 4))) return st;
+  if ((st = upload((void **)&ip.d_pc, ip.tab.pc.data(), ip.tab.pc.size() * 4))) return st;
+  if ((st = upload((void **)&ip.d_iir, iir.data(), iir.size() * 4))) return st;
+  hipError_t e = hipMalloc(&ip.d_state, 64);
+  if (e != hipSuccess) return dev_fail(e, "hipMalloc(state)");
+  // pairs per launch: bounded by a workspace budget for the smoothed images
+  size_t per_pair = (size_t)g.H * g.Spos * sizeof(float4);
+  size_t budget = (size_t)16 << 30;
+  if (const char *b = std::getenv("BF_Z_BUDGET_MB")) budget = (size_t)std::atoll(b) << 20;
+  size_t kc = budget / per_pair;
+  if (kc < 1) kc = 1;
+  ip.KC = (int)std::min<size_t>(kc, (size_t)ip.tab.K_max);
+  return BF_OK;
+}
+
+void free_image(ImagePlan &ip) {
+  (void)hipFree(ip.d_idx);
+  (void)hipFree(ip.d_ent);
+  (void)hipFree(ip.d_pm);
+  (void)hipFree(ip.d_pc);
+  (void)hipFree(ip.d_iir);
+  (void)hipFree(ip.d_state);
+}
+
+bf_status ensure(void **ptr, size_t &have, size_t need) {
+  if (need <= have) return BF_OK;
+  if (*ptr) (void)hipFree(*ptr);
+  *ptr = nullptr;
+  have = 0;
+  if (std::getenv("BF_FAIL_ALLOC")) return fail(BF_ERR_OUT_OF_MEMORY, "allocation failure requested by BF_FAIL_ALLOC");
+  hipError_t e = hipMalloc(ptr, need);
+  if (e != hipSuccess) return dev_fail(e, "hipMalloc(workspace)");
+  have = need;
+  return BF_OK;
+}
+
+// Enqueue the whole of Algorithm 2 for one image.
+bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out, hipStream_t s) {
+  const Geom &g = ip.g;
+  DevState st = state_of(ip);
+  DevTables tab = tables_of(ip);
+  hipError_t e;
+  if (ip.p.t_mode == BF_T_LOCAL) {
+    e = launch_reset(s, st, 0, 0.0);
+    if (e != hipSuccess) return dev_fail(e, "reset");
+    e = launch_range(s, ip.p.dtype, d_in, g, ip.R, pl->d_rowmax, st, ip.T_cap);
+    if (e != hipSuccess) return dev_fail(e, "dynamic range");
+  } else {
+    e = launch_reset(s, st, ip.T_global, ip.T_global_raw);
+    if (e != hipSuccess) return dev_fail(e, "reset");
+  }
+  const int Kmax = ip.tab.K_max;
+  for (int k0 = 0; k0 < Kmax; k0 += ip.KC) {
+    const int kcount = std::min(ip.KC, Kmax - k0);
+    e = launch_iir_chunk(s, ip.p.dtype, d_in, d_out, g, tab, st, ip.d_iir, k0, kcount, pl->d_cb, pl->d_Z,
+                         pl->d_PQ, k0 == 0, k0 + ip.KC >= Kmax);
+    if (e != hipSuccess) return dev_fail(e, "blur");
+  }
+  return BF_OK;
+}
+
+bf_status fill_report(ImagePlan &ip, bf_report *rep, float ms) {
+  unsigned char buf[24];
+  hipError_t e = hipMemcpy(buf, ip.d_state, 24, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return dev_fail(e, "read report");
+  int32_t Tu, flags;
+  unsigned long long traw, qn;
+  std::memcpy(&Tu, buf + 0, 4);
+  std::memcpy(&flags, buf + 4, 4);
+  std::memcpy(&traw, buf + 8, 8);
+  std::memcpy(&qn, buf + 16, 8);
+  double T;
+  std::memcpy(&T, &traw, 8);
+  int Tc = Tu < 0 ? 0 : (Tu > ip.T_cap ? ip.T_cap : Tu);
+  const OrderEntry &oe = ip.tab.ent[ip.tab.idx_of_T[Tc]];
+  rep->T = T;
+  rep->T_used = Tu;
+  rep->N = oe.N;
+  rep->M = oe.M;
+  rep->kept = oe.N - 2 * oe.M + 1;
+  rep->pairs = oe.K;
+  rep->variant = ip.variant;
+  rep->flags = flags;
+  rep->q_nonpos = (int64_t)qn;
+  rep->ms = ms;
+  if (flags & 1) return fail(BF_ERR_NOT_FINITE, "input holds NaN or Inf");
+  if (flags & 2) return fail(BF_ERR_RANGE, "dynamic range above value_range");
+  return BF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bf_status_string(bf_status s) {
+  switch (s) {
+    case BF_OK: return "ok";
+    case BF_ERR_INVALID_ARG: return "invalid argument";
+    case BF_ERR_UNSUPPORTED: return "unsupported";
+    case BF_ERR_OUT_OF_MEMORY: return "out of memory";
+    case BF_ERR_DEVICE: return "device error";
+    case BF_ERR_NOT_FINITE: return "non-finite input";
+    case BF_ERR_RANGE: return "input outside value_range";
+  }
+  return "unknown status";
+}
+
+const char *bf_last_error_detail(void) { return g_detail.c_str(); }
+
+bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out) {
+  if (!out) return fail(BF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!params || n_images < 1) return fail(BF_ERR_INVALID_ARG, "params NULL or n_images < 1");
+  for (int i = 0; i < n_images; i++) {
+    bf_status s = check_params(params[i]);
+    if (s) return s;
+  }
+  bf_plan_s *pl = new bf_plan_s();
+  (void)hipGetDevice(&pl->device);
+  pl->im.resize(n_images);
+  size_t rowmax = 0, cb = 0, Z = 0, PQ = 0;
+  for (int i = 0; i < n_images; i++) {
+    bf_status s = prepare_image(params[i], pl->im[i]);
+    if (s) {
+      bf_plan_destroy(pl);
+      return s;
+    }
+    const ImagePlan &ip = pl->im[i];
+    const Geom &g = ip.g;
+    rowmax = std::max(rowmax, (size_t)g.H * g.W * elem_size(ip.p.dtype));
+    cb = std::max(cb, (size_t)ip.KC * g.nc * 6 * g.Spos * sizeof(float4));
+    Z = std::max(Z, (size_t)ip.KC * g.H * g.Spos * sizeof(float4));
+    PQ = std::max(PQ, (size_t)g.H * g.W * sizeof(float2));
+  }
+  bf_status s;
+  if ((s = ensure(&pl->d_rowmax, pl->rowmax_bytes, rowmax)) || (s = ensure((void **)&pl->d_cb, pl->cb_bytes, cb)) ||
+      (s = ensure((void **)&pl->d_Z, pl->Z_bytes, Z)) || (s = ensure((void **)&pl->d_PQ, pl->PQ_bytes, PQ))) {
+    bf_plan_destroy(pl);
+    return s;
+  }
+  if (hipEventCreate(&pl->ev0) != hipSuccess || hipEventCreate(&pl->ev1) != hipSuccess) {
+    bf_plan_destroy(pl);
+    return fail(BF_ERR_DEVICE, "hipEventCreate");
+  }
+  *out = pl;
+  return BF_OK;
+}
+
+void bf_plan_destroy(bf_plan_t pl) {
+  if (!pl) return;
+  for (auto &ip : pl->im) free_image(ip);
+  (void)hipFree(pl->d_rowmax);
+  (void)hipFree(pl->d_cb);
+  (void)hipFree(pl->d_Z);
+  (void)hipFree(pl->d_PQ);
+  if (pl->ev0) (void)hipEventDestroy(pl->ev0);
+  if (pl->ev1) (void)hipEventDestroy(pl->ev1);
+  delete pl;
+}
+
+bf_status bf_filter(bf_plan_t pl, const void *d_in, float *d_out, void *hip_stream, bf_report *rep) {
+  if (!pl || !d_in || !d_out) return fail(BF_ERR_INVALID_ARG, "NULL plan or buffer");
+  hipStream_t s = (hipStream_t)hip_stream;
+  ImagePlan &ip = pl->im[0];
+  if (rep) (void)hipEventRecord(pl->ev0, s);
+  bf_status st = run_image(pl, ip, d_in, d_out, s);
+  if (st) return st;
+  if (!rep) return BF_OK;
+  (void)hipEventRecord(pl->ev1, s);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
+  return fill_report(ip, rep, ms);
+}
+
+bf_status bf_filter_batch(bf_plan_t pl, int32_t n, const void *const *d_in, float *const *d_out, void *hip_stream,
+                          bf_report *reps) {
+  if (!pl || !d_in || !d_out) return fail(BF_ERR_INVALID_ARG, "NULL plan or pointer array");
+  if (n < 1 || n > (int32_t)pl->im.size()) return fail(BF_ERR_INVALID_ARG, "n outside [1, n_images]");
+  for (int i = 0; i < n; i++)
+    if (!d_in[i] || !d_out[i]) return fail(BF_ERR_INVALID_ARG, "NULL image pointer");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (reps) (void)hipEventRecord(pl->ev0, s);
+  for (int i = 0; i < n; i++) {
+    bf_status st = run_image(pl, pl->im[i], d_in[i], d_out[i], s);
+    if (st) return st;
+  }
+  if (!reps) return BF_OK;
+  (void)hipEventRecord(pl->ev1, s);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
+  bf_status first = BF_OK;
+  for (int i = 0; i < n; i++) {
+    bf_status st = fill_report(pl->im[i], &reps[i], ms);
+    if (st && !first) first = st;
+  }
+  return first;
+}
+
+bf_status bf_dynamic_range(bf_plan_t pl, const void *d_in, void *hip_stream, double *T_out) {
+  if (!pl || !d_in || !T_out) return fail(BF_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  ImagePlan &ip = pl->im[0];
+  DevState st = state_of(ip);
+  hipError_t e = launch_reset(s, st, 0, 0.0);
+  if (e == hipSuccess) e = launch_range(s, ip.p.dtype, d_in, ip.g, ip.R, pl->d_rowmax, st, ip.T_cap);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_fail(e, "dynamic range");
+  unsigned long long traw;
+  e = hipMemcpy(&traw, (char *)ip.d_state + 8, 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return dev_fail(e, "read T");
+  std::memcpy(T_out, &traw, 8);
+  return BF_OK;
+}
+
+}  // extern "C"

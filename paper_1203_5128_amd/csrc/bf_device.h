@@ -1,0 +1,48 @@
+// Device-side views shared by the kernels and the plan runtime of libbf.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bf_internal.h"
+
+namespace bfi {
+
+// Order table on the device (uploaded copy of OrderTable).
+struct DevTables {
+  const int32_t *idx_of_T;
+  const OrderEntry *ent;
+  const int32_t *pm;
+  const float *pc;
+  int32_t T_cap;
+};
+
+// Per-image scalars written by the range stage and read by every later stage.
+struct DevState {
+  int32_t *T_used;            // integer T indexing the table (ceil for floats)
+  unsigned long long *T_raw;  // bit pattern of the raw T as a non-negative double
+  int32_t *flags;             // bit0 non-finite input, bit1 T above the table
+  unsigned long long *q_nonpos;  // pixels whose denominator was not positive
+};
+
+// Geometry of one image inside the blocked recursive filter.
+struct Geom {
+  int H, W;
+  int64_t pitch;      // input pitch (elements)
+  int64_t opitch;     // output pitch (elements)
+  int S, logS;        // threads per row in the horizontal pass (power of two)
+  int Spos;           // S * kC positions per padded row
+  int nc;             // vertical chunks of kB rows
+  float center;       // intensity subtracted from f in the f*cos, f*sin images
+};
+
+// ---- launch wrappers (bf_kernels.hip) ----
+hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw);
+hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,
+                        DevState st, int32_t T_cap);
+hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *out, const Geom &g,
+                            DevTables tab, DevState st, const float *iir, int k0, int kcount,
+                            float4 *cb, float4 *Z, float2 *PQ, bool first, bool last);
+
+}  // namespace bfi

@@ -1,0 +1,77 @@
+// Internal declarations shared by the host tables, the kernels and the plan
+// runtime of libbf.so.  Not part of the public ABI (that is include/bf.h).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bf.h"
+
+namespace bfi {
+
+// ---------------------------------------------------------------- geometry
+// Vertical pass: rows per chunk of the blocked recursive filter.
+constexpr int kB = 32;
+// Horizontal pass: pixels of a row owned by one thread.
+constexpr int kC = 32;
+// Threads per workgroup of the horizontal pass.
+constexpr int kHThreads = 256;
+// Threads per workgroup of the vertical passes.
+constexpr int kVThreads = 256;
+// Largest supported width: kC * kHThreads pixels in one row group.
+constexpr int kMaxWidth = kC * kHThreads;
+
+// ------------------------------------------------------- order tables (a1)
+// One entry per distinct order N reachable from T in [0, T_cap].
+struct OrderEntry {
+  int32_t N;         // order (Algorithm 2 step 3)
+  int32_t M;         // terms dropped per tail (step 4)
+  int32_t K;         // frequency pairs kept, the zero frequency included
+  int32_t off;       // first pair in the pair arrays
+  uint64_t qfix;     // frac(alpha / 2pi) * 2^64, alpha = 1 / (sqrt(N) sigma_r)
+  double alpha_turn; // alpha / 2pi, turns per intensity unit per unit of m
+};
+
+struct OrderTable {
+  int32_t T_cap = 0;
+  std::vector<int32_t> idx_of_T;  // T -> entry
+  std::vector<OrderEntry> ent;
+  std::vector<int32_t> pm;        // per pair: m = 2n - N (<= 0)
+  std::vector<float> pc;          // per pair: c' = 2^(1-N) C(N,n), or 2^-N C(N,N/2) for m = 0
+  int32_t K_max = 0;
+  int32_t N_max = 0;
+};
+
+int order_N(double T, double sigma_r);
+int trunc_M(int N, double sigma_r8, double eps);
+bool build_order_table(double sigma_r, double eps, double value_range, int32_t T_cap,
+                       OrderTable &out, std::string &err);
+
+// ------------------------------------------- recursive Gaussian constants
+// State of one direction of the cascade after element n: (s[n], w[n], w[n-1])
+// with s the first-order section and w the second-order section output.
+// Rows and columns are padded with zeros to a multiple of the chunk length and
+// the zero-extension boundary is applied at the padded end: the causal outputs
+// in the padding are exactly the continuation of the zero-extended signal, so
+// the result is the same as at the true end and no chunk is ever short.
+// Float layout of the constant block (offsets in floats):
+constexpr int kIirCoef = 0;                      // g1, g2, c2, 0
+constexpr int kIirMts = 4;                       // 3x3: end boundary (zero extension)
+constexpr int kIirApFull = kIirMts + 9;          // 3 x kB: chunk end state per input
+constexpr int kIirAeFull = kIirApFull + 3 * kB;  // 3 x kB: chunk head state per input
+constexpr int kIirPhiFull = kIirAeFull + 3 * kB; // 3x3: A^kB
+constexpr int kIirCmFull = kIirPhiFull + 9;      // 3x3: causal carry -> anticausal head
+constexpr int kIirApow = kIirCmFull + 9;         // 9 x (kC+1): A^v, v = 0..kC
+constexpr int kIirLane = kIirApow + 9 * (kC + 1);// 9 x 64: A^(kC*l), l = 0..63
+constexpr int kIirScan = kIirLane + 9 * 64;      // 9 x 8: A^(kC*2^k), k = 0..7
+constexpr int kIirWave = kIirScan + 9 * 8;       // 9: A^(64 kC)
+constexpr int kIirSize = kIirWave + 9;
+
+bool yvv_cascade(double sigma, double &g1, double &g2, double &c1, double &c2, std::string &err);
+bool build_iir_consts(double sigma_s, std::vector<float> &out, std::string &err);
+
+// FIR taps exp(-j^2 / (2 sigma^2)), j = -R..R (FP64 on the host).
+void build_fir_taps(double sigma_s, int R, std::vector<double> &taps);
+
+}  // namespace bfi

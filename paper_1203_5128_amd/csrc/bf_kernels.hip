@@ -1,0 +1,724 @@
+// gfx950 kernels of libbf.so: dynamic range (Algorithm 1), phase generation,
+// the blocked recursive Gaussian (Young-van Vliet cascade) and the fused
+// accumulate-and-normalise of eqs. (f1), (f2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+#include "bf_device.h"
+
+namespace bfi {
+
+// ------------------------------------------------------------ small helpers
+__device__ __forceinline__ float4 f4(float a) { return make_float4(a, a, a, a); }
+__device__ __forceinline__ float4 add4(float4 a, float4 b) {
+  return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+__device__ __forceinline__ float4 sub4(float4 a, float4 b) {
+  return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+}
+// acc + k * v
+__device__ __forceinline__ float4 fma4(float k, float4 v, float4 acc) {
+  return make_float4(fmaf(k, v.x, acc.x), fmaf(k, v.y, acc.y), fmaf(k, v.z, acc.z),
+                     fmaf(k, v.w, acc.w));
+}
+// r = M v for a row-major 3x3 M acting on three float4 (four planes at once)
+__device__ __forceinline__ void matvec3(const float *__restrict__ M, const float4 v[3], float4 r[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    float4 a = f4(0.0f);
+    a = fma4(M[3 * i + 0], v[0], a);
+    a = fma4(M[3 * i + 1], v[1], a);
+    a = fma4(M[3 * i + 2], v[2], a);
+    r[i] = a;
+  }
+}
+// v += M u
+__device__ __forceinline__ void matvec3_acc(const float *__restrict__ M, const float4 u[3], float4 v[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    v[i] = fma4(M[3 * i + 0], u[0], v[i]);
+    v[i] = fma4(M[3 * i + 1], u[1], v[i]);
+    v[i] = fma4(M[3 * i + 2], u[2], v[i]);
+  }
+}
+// dot of row 1 of a 3x3 M with u (the w-component response)
+__device__ __forceinline__ float4 row1dot(const float *__restrict__ M, const float4 u[3]) {
+  float4 a = f4(0.0f);
+  a = fma4(M[3], u[0], a);
+  a = fma4(M[4], u[1], a);
+  a = fma4(M[5], u[2], a);
+  return a;
+}
+
+__device__ __forceinline__ float4 shfl_up4(float4 v, int d, int w) {
+  return make_float4(__shfl_up(v.x, d, w), __shfl_up(v.y, d, w), __shfl_up(v.z, d, w),
+                     __shfl_up(v.w, d, w));
+}
+__device__ __forceinline__ float4 shfl_down4(float4 v, int d, int w) {
+  return make_float4(__shfl_down(v.x, d, w), __shfl_down(v.y, d, w), __shfl_down(v.z, d, w),
+                     __shfl_down(v.w, d, w));
+}
+
+template <typename Tin>
+__device__ __forceinline__ float fval(Tin v) {
+  return (float)v;
+}
+
+__device__ __forceinline__ const OrderEntry &lookup(const DevTables &tab, const int32_t *Tu) {
+  int T = *Tu;
+  T = T < 0 ? 0 : (T > tab.T_cap ? tab.T_cap : T);
+  return tab.ent[tab.idx_of_T[T]];
+}
+
+// ------------------------------------------------------- phase generation
+// Turn (fraction of 2 pi) of the angle m * alpha * v, as an unsigned 32-bit
+// fixed-point number.  For integer v the product m*v is exact and the turn is
+// reduced exactly modulo 1 in 64-bit arithmetic (qfix = frac(alpha/2pi) 2^64);
+// a float v is split into its integer part (same exact path) and a fraction
+// r in [0,1) whose small angle m*r*alpha is added in double precision.
+template <typename Tin>
+__device__ __forceinline__ uint32_t phase_turn(int32_t m, Tin v, uint64_t q, double at) {
+  if constexpr (std::is_same<Tin, float>::value) {
+    float fl = floorf(v);
+    float r = v - fl;
+    int64_t mv = (int64_t)m * (int64_t)fl;
+    uint32_t ti = (uint32_t)(((uint64_t)mv * q) >> 32);
+    double x = (double)m * (double)r * at;
+    x -= rint(x);
+    return ti + (uint32_t)(int64_t)(x * 4294967296.0);
+  } else {
+    int64_t mv = (int64_t)m * (int64_t)v;
+    return (uint32_t)(((uint64_t)mv * q) >> 32);
+  }
+}
+
+// cos and sin of 2 pi tau / 2^32: exact quarter-turn reduction on the integer
+// turn, then Taylor polynomials on |x| <= pi/4 (truncation below 2e-9).
+__device__ __forceinline__ void turn_sincos(uint32_t tau, float &c, float &s) {
+  uint32_t q = (tau + 0x20000000u) >> 30;
+  int32_t r = (int32_t)(tau - (q << 30));
+  float x = (float)r * 1.46291807926715968e-9f;  // 2 pi / 2^32
+  float x2 = x * x;
+  float sp = fmaf(x * x2,
+                  fmaf(x2, fmaf(x2, fmaf(x2, 2.7557319223985893e-6f, -1.9841269841269841e-4f),
+                                8.3333333333333333e-3f),
+                       -1.6666666666666667e-1f),
+                  x);
+  float cp = fmaf(
+      x2,
+      fmaf(x2,
+           fmaf(x2, fmaf(x2, fmaf(x2, -2.7557319223985888e-7f, 2.4801587301587302e-5f),
+                         -1.3888888888888889e-3f),
+                4.1666666666666667e-2f),
+           -0.5f),
+      1.0f);
+  float cc = (q & 1u) ? -sp : cp;
+  float ss = (q & 1u) ? cp : sp;
+  if (q & 2u) {
+    cc = -cc;
+    ss = -ss;
+  }
+  c = cc;
+  s = ss;
+}
+
+// The four images of one frequency at one pixel: (f-c) cos, (f-c) sin, cos, sin.
+template <typename Tin>
+__device__ __forceinline__ float4 planes(Tin v, int32_t m, uint64_t q, double at, float center) {
+  float c, s;
+  turn_sincos(phase_turn<Tin>(m, v, q, at), c, s);
+  float d = fval(v) - center;
+  return make_float4(d * c, d * s, c, s);
+}
+
+// ------------------------------------------------------------------- reset
+__global__ void k_reset(DevState st, int32_t T_used, double T_raw) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *st.T_used = T_used;
+    *st.T_raw = (unsigned long long)__double_as_longlong(T_raw);
+    *st.flags = 0;
+    *st.q_nonpos = 0ull;
+  }
+}
+
+// ------------------------------------------------- Algorithm 1, row pass
+// MAX-FILTER (Appendix) along rows.  One wave per segment of kRowSeg outputs.
+// The segment's input [xs-R, xs+n+R) is indexed by e; partitions of length
+// 2R+1 start at e = 0.  Left running maxima l (reset at each partition start)
+// and right running maxima r (reset at each partition end) are segmented
+// scans done with wave shuffles, carried tile to tile; then
+// out(x) = max(r[e], l[e+2R]) with e = x - xs.
+constexpr int kRowSeg = 256;
+constexpr int kMaxR = 1024;
+
+template <typename Tin>
+__global__ __launch_bounds__(64) void k_rowmax(const Tin *__restrict__ f, int64_t pitch, int H, int W,
+                                               int R, Tin *__restrict__ rowmax, DevState st) {
+  __shared__ float sl[kRowSeg + 2 * kMaxR + 64];
+  __shared__ float sr[kRowSeg + 2 * kMaxR + 64];
+  const int y = blockIdx.y;
+  const int xs = blockIdx.x * kRowSeg;
+  if (xs >= W) return;
+  const int n_out = min(kRowSeg, W - xs);
+  const int L = n_out + 2 * R;
+  const int Wd = 2 * R + 1;
+  const int lane = threadIdx.x;
+  const Tin *frow = f + (int64_t)y * pitch;
+  bool bad = false;
+  float carry = -INFINITY;
+  for (int e0 = 0; e0 < L; e0 += 64) {
+    const int e = e0 + lane;
+    const int x = xs - R + e;
+    float v = -INFINITY;
+    if (e < L && x >= 0 && x < W) {
+      v = fval(frow[x]);
+      if (!isfinite(v)) { bad = true; v = -INFINITY; }
+    }
+    const int segs = e - e % Wd;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      float o = __shfl_up(v, d, 64);
+      if (lane >= d && e - d >= segs) v = fmaxf(v, o);
+    }
+    if (e0 > 0 && e0 - 1 >= segs) v = fmaxf(v, carry);
+    carry = __shfl(v, 63, 64);
+    if (e < L) sl[e] = v;
+  }
+  carry = -INFINITY;
+  for (int e0 = ((L - 1) / 64) * 64; e0 >= 0; e0 -= 64) {
+    const int e = e0 + lane;
+    const int x = xs - R + e;
+    float v = -INFINITY;
+    if (e < L && x >= 0 && x < W) {
+      v = fval(frow[x]);
+      if (!isfinite(v)) v = -INFINITY;
+    }
+    const int sege = e - e % Wd + Wd - 1;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      float o = __shfl_down(v, d, 64);
+      if (lane + d < 64 && e + d <= sege) v = fmaxf(v, o);
+    }
+    if (e0 + 64 <= sege) v = fmaxf(v, carry);
+    carry = __shfl(v, 0, 64);
+    if (e < L) sr[e] = v;
+  }
+  __syncthreads();
+  Tin *orow = rowmax + (int64_t)y * W + xs;
+  for (int i = lane; i < n_out; i += 64) orow[i] = (Tin)fmaxf(sr[i], sl[i + 2 * R]);
+  if (__any(bad) && lane == 0) atomicOr(st.flags, 1);
+}
+
+// ---------------------------------------- Algorithm 1, column pass and T
+// One lane per column, a band of kColBand rows per workgroup (with R rows of
+// halo each side).  Right running maxima of the band are built bottom-up into
+// LDS, left running maxima top-down, out = max(r, l) as in the row pass; then
+// T = max over the band of (out - f) (Prop. 2.1, sign read from its proof).
+constexpr int kColBand = 128;
+
+template <typename Tin>
+__global__ __launch_bounds__(64) void k_colmax_T(const Tin *__restrict__ f, int64_t pitch,
+                                                 const Tin *__restrict__ rowmax, int H, int W, int R,
+                                                 DevState st, int32_t T_cap) {
+  __shared__ float srb[kColBand][64];
+  const int lane = threadIdx.x;
+  const int x = blockIdx.x * 64 + lane;
+  const int y0 = blockIdx.y * kColBand;
+  const int nb = min(kColBand, H - y0);
+  const int L = nb + 2 * R;
+  const int Wd = 2 * R + 1;
+  double tmax = 0.0;
+  if (x < W) {
+    float r = -INFINITY;
+    int ph = (L - 1) % Wd;  // position of e inside its partition
+    for (int e = L - 1; e >= 0; e--) {
+      const int y = y0 - R + e;
+      float v = (y >= 0 && y < H) ? fval(rowmax[(int64_t)y * W + x]) : -INFINITY;
+      r = (ph == Wd - 1) ? v : fmaxf(r, v);
+      if (e < nb) srb[e][lane] = r;
+      ph = ph == 0 ? Wd - 1 : ph - 1;
+    }
+    float l = -INFINITY;
+    ph = 0;
+    for (int e = 0; e < L; e++) {
+      const int y = y0 - R + e;
+      float v = (y >= 0 && y < H) ? fval(rowmax[(int64_t)y * W + x]) : -INFINITY;
+      l = (ph == 0) ? v : fmaxf(l, v);
+      ph = ph == Wd - 1 ? 0 : ph + 1;
+      if (e >= 2 * R) {
+        const int i = e - 2 * R;
+        const float mx = fmaxf(srb[i][lane], l);
+        const float fv = fval(f[(int64_t)(y0 + i) * pitch + x]);
+        const double d = (double)mx - (double)fv;
+        tmax = d > tmax ? d : tmax;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_xor(tmax, off, 64);
+    tmax = o > tmax ? o : tmax;
+  }
+  if (lane == 0) {
+    double tc = ceil(tmax);
+    int ti = tc > 2147483647.0 ? 2147483647 : (int)tc;
+    atomicMax(st.T_used, ti);
+    atomicMax(st.T_raw, (unsigned long long)__double_as_longlong(tmax));
+    if (ti > T_cap) atomicOr(st.flags, 2);
+  }
+}
+
+// --------------------------------------------- blocked recursive Gaussian
+// Vertical pass over the images of one frequency, one lane per column.  The
+// padded column (nc chunks of kB rows) is filtered by the causal and the
+// anticausal cascade; chunk j needs the causal state entering it and the
+// anticausal state entering it from below.  Stage 1 sums, per chunk, the end
+// state and the anticausal head the chunk would produce from rest (both linear
+// in its input); stage 2 chains them down and up the column; stage 3 reruns
+// each chunk from its true states and writes the smoothed images.
+//
+// Positions p index the padded row in an interleaved order: p -> column
+// x = (p mod S) * kC + p / S, so that the horizontal pass, where thread t owns
+// columns [t kC, t kC + kC), reads consecutive addresses.
+
+template <typename Tin>
+__global__ __launch_bounds__(kVThreads) void k_iir_v_summary(const Tin *__restrict__ f, Geom g,
+                                                             DevTables tab, DevState st,
+                                                             const float *__restrict__ iir, int k0,
+                                                             float4 *__restrict__ cb) {
+  const int p = blockIdx.x * kVThreads + threadIdx.x;
+  const int j = blockIdx.y;
+  const int kl = blockIdx.z;
+  const OrderEntry &e = lookup(tab, st.T_used);
+  const int k = k0 + kl;
+  if (k >= e.K || p >= g.Spos) return;
+  const int x = (p & (g.S - 1)) * kC + (p >> g.logS);
+  if (x >= g.W) return;
+  const int32_t m = tab.pm[e.off + k];
+  const uint64_t q = e.qfix;
+  const double at = e.alpha_turn;
+  const float *Ap = iir + kIirApFull;
+  const float *Ae = iir + kIirAeFull;
+  float4 a0 = f4(0.f), a1 = f4(0.f), a2 = f4(0.f), b0 = f4(0.f), b1 = f4(0.f), b2 = f4(0.f);
+  const int y0 = j * kB;
+  const int n = min(kB, g.H - y0);
+#pragma unroll 4
+  for (int i = 0; i < n; i++) {
+    const Tin v = f[(int64_t)(y0 + i) * g.pitch + x];
+    const float4 xv = planes<Tin>(v, m, q, at, g.center);
+    a0 = fma4(Ap[0 * kB + i], xv, a0);
+    a1 = fma4(Ap[1 * kB + i], xv, a1);
+    a2 = fma4(Ap[2 * kB + i], xv, a2);
+    b0 = fma4(Ae[0 * kB + i], xv, b0);
+    b1 = fma4(Ae[1 * kB + i], xv, b1);
+    b2 = fma4(Ae[2 * kB + i], xv, b2);
+  }
+  const size_t base = ((size_t)kl * g.nc + j) * 6;
+  cb[(base + 0) * g.Spos + p] = a0;
+  cb[(base + 1) * g.Spos + p] = a1;
+  cb[(base + 2) * g.Spos + p] = a2;
+  cb[(base + 3) * g.Spos + p] = b0;
+  cb[(base + 4) * g.Spos + p] = b1;
+  cb[(base + 5) * g.Spos + p] = b2;
+}
+
+__global__ __launch_bounds__(kVThreads) void k_iir_v_fixup(Geom g, DevTables tab, DevState st,
+                                                           const float *__restrict__ iir, int k0,
+                                                           float4 *__restrict__ cb) {
+  const int p = blockIdx.x * kVThreads + threadIdx.x;
+  const int kl = blockIdx.y;
+  const OrderEntry &e = lookup(tab, st.T_used);
+  const int k = k0 + kl;
+  if (k >= e.K || p >= g.Spos) return;
+  const int x = (p & (g.S - 1)) * kC + (p >> g.logS);
+  if (x >= g.W) return;
+  const float *Phi = iir + kIirPhiFull;
+  const float *Cm = iir + kIirCmFull;
+  const float *Mts = iir + kIirMts;
+  float4 P[3] = {f4(0.f), f4(0.f), f4(0.f)};
+  for (int j = 0; j < g.nc; j++) {
+    const size_t base = ((size_t)kl * g.nc + j) * 6;
+    float4 pb[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) pb[r] = cb[(base + r) * g.Spos + p];
+#pragma unroll
+    for (int r = 0; r < 3; r++) cb[(base + r) * g.Spos + p] = P[r];  // causal state entering j
+    float4 np[3];
+    matvec3(Phi, P, np);
+#pragma unroll
+    for (int r = 0; r < 3; r++) P[r] = add4(pb[r], np[r]);
+  }
+  float4 E[3];
+  matvec3(Mts, P, E);  // zero extension below the padded column
+  for (int j = g.nc - 1; j >= 0; j--) {
+    const size_t base = ((size_t)kl * g.nc + j) * 6;
+    float4 eb[3], pin[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+      eb[r] = cb[(base + 3 + r) * g.Spos + p];
+      pin[r] = cb[(base + r) * g.Spos + p];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; r++) cb[(base + 3 + r) * g.Spos + p] = E[r];  // anticausal state entering j
+    float4 t1[3];
+    matvec3(Phi, E, t1);
+    matvec3_acc(Cm, pin, t1);
+#pragma unroll
+    for (int r = 0; r < 3; r++) E[r] = add4(eb[r], t1[r]);
+  }
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(kVThreads) void k_iir_v_final(const Tin *__restrict__ f, Geom g,
+                                                           DevTables tab, DevState st,
+                                                           const float *__restrict__ iir, int k0,
+                                                           const float4 *__restrict__ cb,
+                                                           float4 *__restrict__ Z) {
+  const int p = blockIdx.x * kVThreads + threadIdx.x;
+  const int j = blockIdx.y;
+  const int kl = blockIdx.z;
+  const OrderEntry &e = lookup(tab, st.T_used);
+  const int k = k0 + kl;
+  if (k >= e.K || p >= g.Spos) return;
+  const int x = (p & (g.S - 1)) * kC + (p >> g.logS);
+  const int y0 = j * kB;
+  float4 *Zk = Z + (size_t)kl * g.H * g.Spos;
+  if (x >= g.W) {  // padding columns of the horizontal pass hold zeros
+    for (int i = 0; i < kB; i++)
+      if (y0 + i < g.H) Zk[(size_t)(y0 + i) * g.Spos + p] = f4(0.f);
+    return;
+  }
+  const int32_t m = tab.pm[e.off + k];
+  const uint64_t q = e.qfix;
+  const double at = e.alpha_turn;
+  const float g1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
+  const size_t base = ((size_t)kl * g.nc + j) * 6;
+  float4 s = cb[(base + 0) * g.Spos + p];
+  float4 w1 = cb[(base + 1) * g.Spos + p];
+  float4 w2 = cb[(base + 2) * g.Spos + p];
+  float4 wv[kB];
+#pragma unroll
+  for (int i = 0; i < kB; i++) {
+    const int y = y0 + i;
+    float4 xv = f4(0.f);
+    if (y < g.H) xv = planes<Tin>(f[(int64_t)y * g.pitch + x], m, q, at, g.center);
+    s = fma4(g1, sub4(xv, s), s);
+    float4 w = fma4(g2, sub4(s, w1), w1);
+    w = fma4(-c2, sub4(w1, w2), w);
+    w2 = w1;
+    w1 = w;
+    wv[i] = w;
+  }
+  float4 a = cb[(base + 3) * g.Spos + p];
+  float4 z1 = cb[(base + 4) * g.Spos + p];
+  float4 z2 = cb[(base + 5) * g.Spos + p];
+#pragma unroll
+  for (int i = kB - 1; i >= 0; i--) {
+    a = fma4(g1, sub4(wv[i], a), a);
+    float4 z = fma4(g2, sub4(a, z1), z1);
+    z = fma4(-c2, sub4(z1, z2), z);
+    z2 = z1;
+    z1 = z;
+    const int y = y0 + i;
+    if (y < g.H) Zk[(size_t)y * g.Spos + p] = z;
+  }
+}
+
+// ------------------------------------ horizontal pass + accumulate (a4, a5)
+// One workgroup per image row; S threads per row group, NG = 256/S groups each
+// taking every NG-th frequency.  Thread t owns kC consecutive columns: a causal
+// sweep from rest, an inclusive scan of the chunk end states across the row
+// group (Hillis-Steele with powers of A^kC, across waves through LDS when the
+// row spans several waves), the correction w += h . carry; the same for the
+// anticausal sweep, seeded at the padded end with the zero-extension boundary.
+// The smoothed images are combined on the fly into the numerator and the
+// denominator (eqs. (f1), (f2)) with the phases regenerated at each pixel.
+template <int SW>
+__device__ __forceinline__ void scan_up(float4 v[3], const float *__restrict__ scanM, int ls) {
+#pragma unroll
+  for (int k = 0; (1 << k) < SW; k++) {
+    const int d = 1 << k;
+    float4 o[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) o[r] = shfl_up4(v[r], d, SW);
+    if (ls >= d) matvec3_acc(scanM + 9 * k, o, v);
+  }
+}
+template <int SW>
+__device__ __forceinline__ void scan_down(float4 v[3], const float *__restrict__ scanM, int ls) {
+#pragma unroll
+  for (int k = 0; (1 << k) < SW; k++) {
+    const int d = 1 << k;
+    float4 o[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) o[r] = shfl_down4(v[r], d, SW);
+    if (ls + d < SW) matvec3_acc(scanM + 9 * k, o, v);
+  }
+}
+
+template <typename Tin, int S>
+__global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict__ f,
+                                                           float *__restrict__ out, Geom g,
+                                                           DevTables tab, DevState st,
+                                                           const float *__restrict__ iir, int k0,
+                                                           int kcount, const float4 *__restrict__ Z,
+                                                           float2 *__restrict__ PQ, int first,
+                                                           int last) {
+  constexpr int NG = kHThreads / S;
+  constexpr int SW = S < 64 ? S : 64;
+  constexpr int NW = S > 64 ? S / 64 : 1;
+  constexpr int PAD = S * (kC + 1);  // LDS row of one group, one slot skipped per kC
+  __shared__ float sred[2][NG * PAD];
+  __shared__ float4 xw[NG][NW][3];
+  const int y = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int t = tid % S;
+  const int grp = tid / S;
+  const int ls = t % SW;
+  const int wig = t / 64;
+  const OrderEntry &e = lookup(tab, st.T_used);
+  const int kend = min(k0 + kcount, e.K);
+  const int niter = kend > k0 ? (kend - k0 + NG - 1) / NG : 0;
+  const float g1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
+  const float *Apow = iir + kIirApow;
+  const float *scanM = iir + kIirScan;
+  const Tin *frow = f + (int64_t)y * g.pitch;
+  const int x0 = t * kC;
+  float Pa[kC], Qa[kC];
+#pragma unroll
+  for (int i = 0; i < kC; i++) { Pa[i] = 0.f; Qa[i] = 0.f; }
+
+  for (int it = 0; it < niter; it++) {
+    const int kl = it * NG + grp;
+    const bool act = k0 + kl < kend;
+    const float4 *Zr = Z + ((size_t)(act ? kl : 0) * g.H + y) * g.Spos;
+    float4 zv[kC];
+#pragma unroll
+    for (int i = 0; i < kC; i++) zv[i] = Zr[i * S + t];
+    // causal sweep from rest
+    float4 s = f4(0.f), w1 = f4(0.f), w2 = f4(0.f);
+#pragma unroll
+    for (int i = 0; i < kC; i++) {
+      s = fma4(g1, sub4(zv[i], s), s);
+      float4 w = fma4(g2, sub4(s, w1), w1);
+      w = fma4(-c2, sub4(w1, w2), w);
+      w2 = w1;
+      w1 = w;
+      zv[i] = w;
+    }
+    float4 inc[3] = {s, w1, w2};
+    scan_up<SW>(inc, scanM, ls);
+    float4 exc[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+      exc[r] = shfl_up4(inc[r], 1, SW);
+      if (ls == 0) exc[r] = f4(0.f);
+    }
+    if constexpr (NW > 1) {
+      if (ls == 63) {
+#pragma unroll
+        for (int r = 0; r < 3; r++) xw[grp][wig][r] = inc[r];
+      }
+      __syncthreads();
+      float4 Kc[3] = {f4(0.f), f4(0.f), f4(0.f)};
+      for (int w = 0; w < wig; w++) {
+        float4 tk[3];
+        matvec3(iir + kIirWave, Kc, tk);
+#pragma unroll
+        for (int r = 0; r < 3; r++) Kc[r] = add4(xw[grp][w][r], tk[r]);
+      }
+      __syncthreads();
+      matvec3_acc(iir + kIirLane + 9 * ls, Kc, exc);
+      if (t == S - 1) matvec3_acc(iir + kIirWave, Kc, inc);
+    }
+    // true causal outputs
+#pragma unroll
+    for (int i = 0; i < kC; i++) zv[i] = add4(zv[i], row1dot(Apow + 9 * (i + 1), exc));
+    // zero extension beyond the padded row end
+    float4 Eb[3] = {f4(0.f), f4(0.f), f4(0.f)};
+    if (t == S - 1) matvec3(iir + kIirMts, inc, Eb);
+    // anticausal sweep from rest
+    float4 a = f4(0.f), z1 = f4(0.f), z2 = f4(0.f);
+#pragma unroll
+    for (int i = kC - 1; i >= 0; i--) {
+      a = fma4(g1, sub4(zv[i], a), a);
+      float4 z = fma4(g2, sub4(a, z1), z1);
+      z = fma4(-c2, sub4(z1, z2), z);
+      z2 = z1;
+      z1 = z;
+      zv[i] = z;
+    }
+    float4 hd[3] = {a, z1, z2};
+    if (t == S - 1) matvec3_acc(Apow + 9 * kC, Eb, hd);
+    scan_down<SW>(hd, scanM, ls);
+    float4 ein[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+      ein[r] = shfl_down4(hd[r], 1, SW);
+      if (ls == SW - 1) ein[r] = f4(0.f);
+    }
+    if constexpr (NW > 1) {
+      if (ls == 0) {
+#pragma unroll
+        for (int r = 0; r < 3; r++) xw[grp][wig][r] = hd[r];
+      }
+      __syncthreads();
+      float4 Kc[3] = {f4(0.f), f4(0.f), f4(0.f)};
+      for (int w = NW - 1; w > wig; w--) {
+        float4 tk[3];
+        matvec3(iir + kIirWave, Kc, tk);
+#pragma unroll
+        for (int r = 0; r < 3; r++) Kc[r] = add4(xw[grp][w][r], tk[r]);
+      }
+      __syncthreads();
+      matvec3_acc(iir + kIirLane + 9 * (63 - ls), Kc, ein);
+    }
+    if (t == S - 1) {
+#pragma unroll
+      for (int r = 0; r < 3; r++) ein[r] = Eb[r];
+    }
+#pragma unroll
+    for (int i = 0; i < kC; i++) zv[i] = add4(zv[i], row1dot(Apow + 9 * (kC - i), ein));
+    // eqs. (f1), (f2): weight by the phase at the output pixel
+    if (act) {
+      const int k = k0 + kl;
+      const int32_t m = tab.pm[e.off + k];
+      const float cp = tab.pc[e.off + k];
+      const uint64_t q = e.qfix;
+      const double at = e.alpha_turn;
+#pragma unroll
+      for (int i = 0; i < kC; i++) {
+        const int x = x0 + i;
+        if (x < g.W) {
+          float c, sn;
+          turn_sincos(phase_turn<Tin>(m, frow[x], q, at), c, sn);
+          Pa[i] = fmaf(cp, fmaf(c, zv[i].x, sn * zv[i].y), Pa[i]);
+          Qa[i] = fmaf(cp, fmaf(c, zv[i].z, sn * zv[i].w), Qa[i]);
+        }
+      }
+    }
+  }
+  // sum the groups in a fixed order
+#pragma unroll
+  for (int i = 0; i < kC; i++) {
+    sred[0][grp * PAD + t * (kC + 1) + i] = Pa[i];
+    sred[1][grp * PAD + t * (kC + 1) + i] = Qa[i];
+  }
+  __syncthreads();
+  unsigned long long nbad = 0;
+  for (int x = tid; x < g.W; x += kHThreads) {
+    const int o = (x / kC) * (kC + 1) + (x % kC);
+    float P = 0.f, Q = 0.f;
+#pragma unroll
+    for (int gg = 0; gg < NG; gg++) {
+      P += sred[0][gg * PAD + o];
+      Q += sred[1][gg * PAD + o];
+    }
+    const size_t pix = (size_t)y * g.W + x;
+    if (!first) {
+      float2 pq = PQ[pix];
+      P += pq.x;
+      Q += pq.y;
+    }
+    if (last) {
+      float r = P / Q;
+      float v;
+      if (Q > 0.f && isfinite(r)) {
+        v = g.center + r;
+      } else {
+        v = fval(frow[x]);
+        nbad++;
+      }
+      out[(int64_t)y * g.opitch + x] = v;
+    } else {
+      PQ[pix] = make_float2(P, Q);
+    }
+  }
+  if (last) {
+    for (int off = 32; off > 0; off >>= 1) nbad += __shfl_xor(nbad, off, 64);
+    if ((tid & 63) == 0 && nbad) atomicAdd(st.q_nonpos, nbad);
+  }
+}
+
+// ------------------------------------------------------------- launchers
+hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, st, T_used, T_raw);
+  return hipGetLastError();
+}
+
+template <typename Tin>
+static hipError_t range_t(hipStream_t s, const Tin *f, const Geom &g, int R, Tin *rowmax, DevState st,
+                          int32_t T_cap) {
+  dim3 gr((g.W + kRowSeg - 1) / kRowSeg, g.H);
+  hipLaunchKernelGGL(k_rowmax<Tin>, gr, dim3(64), 0, s, f, g.pitch, g.H, g.W, R, rowmax, st);
+  dim3 gc((g.W + 63) / 64, (g.H + kColBand - 1) / kColBand);
+  hipLaunchKernelGGL(k_colmax_T<Tin>, gc, dim3(64), 0, s, f, g.pitch, (const Tin *)rowmax, g.H, g.W, R,
+                     st, T_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,
+                        DevState st, int32_t T_cap) {
+  if (R > kMaxR) return hipErrorInvalidValue;
+  switch (dt) {
+    case BF_U8: return range_t<uint8_t>(s, (const uint8_t *)f, g, R, (uint8_t *)rowmax, st, T_cap);
+    case BF_U16: return range_t<uint16_t>(s, (const uint16_t *)f, g, R, (uint16_t *)rowmax, st, T_cap);
+    default: return range_t<float>(s, (const float *)f, g, R, (float *)rowmax, st, T_cap);
+  }
+}
+
+template <typename Tin, int S>
+static void launch_h(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab, DevState st,
+                     const float *iir, int k0, int kcount, const float4 *Z, float2 *PQ, bool first,
+                     bool last) {
+  hipLaunchKernelGGL((k_iir_h_accum<Tin, S>), dim3(g.H), dim3(kHThreads), 0, s, f, out, g, tab, st, iir,
+                     k0, kcount, Z, PQ, (int)first, (int)last);
+}
+
+template <typename Tin>
+static hipError_t iir_chunk_t(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab,
+                              DevState st, const float *iir, int k0, int kcount, float4 *cb, float4 *Z,
+                              float2 *PQ, bool first, bool last) {
+  const int nbx = (g.Spos + kVThreads - 1) / kVThreads;
+  if (kcount > 0) {
+    hipLaunchKernelGGL(k_iir_v_summary<Tin>, dim3(nbx, g.nc, kcount), dim3(kVThreads), 0, s, f, g, tab,
+                       st, iir, k0, cb);
+    hipLaunchKernelGGL(k_iir_v_fixup, dim3(nbx, kcount), dim3(kVThreads), 0, s, g, tab, st, iir, k0, cb);
+    hipLaunchKernelGGL(k_iir_v_final<Tin>, dim3(nbx, g.nc, kcount), dim3(kVThreads), 0, s, f, g, tab, st,
+                       iir, k0, (const float4 *)cb, Z);
+  }
+  switch (g.S) {
+    case 1: launch_h<Tin, 1>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
+    case 2: launch_h<Tin, 2>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
+    case 4: launch_h<Tin, 4>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
+    case 8: launch_h<Tin, 8>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
+    case 16: launch_h<Tin, 16>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
+    case 32: launch_h<Tin, 32>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
+    case 64: launch_h<Tin, 64>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
+    case 128: launch_h<Tin, 128>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
+    case 256: launch_h<Tin, 256>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *out, const Geom &g,
+                            DevTables tab, DevState st, const float *iir, int k0, int kcount, float4 *cb,
+                            float4 *Z, float2 *PQ, bool first, bool last) {
+  switch (dt) {
+    case BF_U8:
+      return iir_chunk_t<uint8_t>(s, (const uint8_t *)f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, first,
+                                  last);
+    case BF_U16:
+      return iir_chunk_t<uint16_t>(s, (const uint16_t *)f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ,
+                                   first, last);
+    default:
+      return iir_chunk_t<float>(s, (const float *)f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, first,
+                                last);
+  }
+}
+
+}  // namespace bfi

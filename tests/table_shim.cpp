@@ -1,0 +1,36 @@
+// Test-only shim: exposes the host table code of libbf.so (bf_tables.cpp) to
+// the CPU tests, which compare it with the FP64 oracle.  Built with g++ by
+// tests/test_host_tables.py; not part of the library.
+#include <cstring>
+#include <string>
+
+#include "../paper_1203_5128_amd/csrc/bf_internal.h"
+
+extern "C" {
+int shim_order_N(double T, double sigma_r) { return bfi::order_N(T, sigma_r); }
+int shim_trunc_M(int N, double sigma_r8, double eps) { return bfi::trunc_M(N, sigma_r8, eps); }
+// Fills N, M, K, qfix, alpha_turn for T and copies the pairs (m, c').
+int shim_table_entry(double sigma_r, double eps, double range, int T_cap, int T, int *N, int *M, int *K,
+                     unsigned long long *qfix, double *alpha_turn, int *pm, float *pc, int cap) {
+  bfi::OrderTable t;
+  std::string err;
+  if (!bfi::build_order_table(sigma_r, eps, range, T_cap, t, err)) return -1;
+  const bfi::OrderEntry &e = t.ent[t.idx_of_T[T]];
+  *N = e.N; *M = e.M; *K = e.K; *qfix = e.qfix; *alpha_turn = e.alpha_turn;
+  for (int k = 0; k < e.K && k < cap; k++) { pm[k] = t.pm[e.off + k]; pc[k] = t.pc[e.off + k]; }
+  return t.K_max;
+}
+int shim_iir_consts(double sigma, float *out, int n) {
+  std::vector<float> v;
+  std::string err;
+  if (!bfi::build_iir_consts(sigma, v, err)) return -1;
+  std::memcpy(out, v.data(), sizeof(float) * (n < (int)v.size() ? n : (int)v.size()));
+  return (int)v.size();
+}
+int shim_layout(int *o) {
+  o[0] = bfi::kIirCoef; o[1] = bfi::kIirMts; o[2] = bfi::kIirApFull; o[3] = bfi::kIirAeFull;
+  o[4] = bfi::kIirPhiFull; o[5] = bfi::kIirCmFull; o[6] = bfi::kIirApow; o[7] = bfi::kIirSize;
+  o[8] = bfi::kB; o[9] = bfi::kC;
+  return 0;
+}
+}

@@ -1,0 +1,61 @@
+"""The C ABI of libbf.so: every symbol of include/bf.h is exported, and the
+argument checks reject bad parameters before any device work (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1203_5128_amd import bf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "bf.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:bf_status|void|const char \*)\s*\*?\s*(bf_\w+)\s*\(", src, re.M)))
+
+
+def test_library_loads_and_exports_header_symbols():
+    L = bf.lib()
+    names = header_functions()
+    assert set(names) >= {"bf_plan", "bf_filter", "bf_filter_batch", "bf_plan_destroy", "bf_status_string",
+                          "bf_dynamic_range", "bf_last_error_detail"}
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in bf.EXPORTS
+
+
+def test_status_strings():
+    for s in range(7):
+        assert bf.bf_status_string(s)
+    assert bf.bf_status_string(99) == "unknown status"
+
+
+BAD = [dict(H=0), dict(W=0), dict(sigma_s=0.0), dict(sigma_s=-1.0), dict(sigma_r=0.0), dict(eps=0.0),
+       dict(eps=1.0), dict(radius=-1), dict(t_value=-5.0), dict(value_range=-1.0), dict(dtype=7),
+       dict(blur=9), dict(t_mode=3), dict(in_pitch=3), dict(out_pitch=5)]
+
+
+@pytest.mark.parametrize("bad", BAD)
+def test_invalid_params_rejected_without_device(bad):
+    kw = dict(H=16, W=16, dtype="u8", sigma_s=2.0, sigma_r=20.0, eps=1e-3)
+    kw.update(bad)
+    p = bf.make_params(**kw)
+    h = ctypes.c_void_p(123)
+    st = bf.lib().bf_plan(ctypes.byref(p), 1, ctypes.byref(h))
+    assert st == bf.BF_ERR_INVALID_ARG
+    assert h.value is None
+    assert bf.bf_last_error_detail()
+
+
+def test_null_arguments():
+    L = bf.lib()
+    assert L.bf_plan(None, 1, None) == bf.BF_ERR_INVALID_ARG
+    h = ctypes.c_void_p()
+    p = bf.make_params(8, 8)
+    assert L.bf_plan(ctypes.byref(p), 0, ctypes.byref(h)) == bf.BF_ERR_INVALID_ARG
+    assert L.bf_filter(None, None, None, None, None) == bf.BF_ERR_INVALID_ARG
+    assert L.bf_filter_batch(None, 1, None, None, None, None) == bf.BF_ERR_INVALID_ARG
+    assert L.bf_dynamic_range(None, None, None, None) == bf.BF_ERR_INVALID_ARG
+    L.bf_plan_destroy(None)

@@ -1,0 +1,256 @@
+"""CPU tests of libbf.so's host code (order tables, recursive-filter constants)
+and a numpy model of the blocked recursive filter the kernels run, all checked
+against the FP64 oracle.  The host code is compiled with g++ into a test shim;
+no GPU is used."""
+import ctypes
+import math
+import os
+import subprocess
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+
+import oracle as o
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SHIM_DIR = os.path.join(ROOT, "tests", "_build")
+SHIM = os.path.join(SHIM_DIR, "libtableshim.so")
+
+
+@pytest.fixture(scope="module")
+def shim():
+    os.makedirs(SHIM_DIR, exist_ok=True)
+    srcs = [os.path.join(ROOT, "tests", "table_shim.cpp"),
+            os.path.join(ROOT, "paper_1203_5128_amd", "csrc", "bf_tables.cpp")]
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-I",
+                           os.path.join(ROOT, "include")] + srcs + ["-o", SHIM])
+    L = ctypes.CDLL(SHIM)
+    L.shim_order_N.argtypes = [ctypes.c_double, ctypes.c_double]
+    L.shim_trunc_M.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    P = ctypes.c_void_p
+    L.shim_table_entry.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_int, P, P, P, P, P, P, P, ctypes.c_int]
+    L.shim_iir_consts.argtypes = [ctypes.c_double, P, ctypes.c_int]
+    L.shim_layout.argtypes = [P]
+    return L
+
+
+def entry(L, sigma_r, eps, rng_, T_cap, T):
+    N, M, K = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    q = ctypes.c_ulonglong()
+    at = ctypes.c_double()
+    pm = (ctypes.c_int * 8192)()
+    pc = (ctypes.c_float * 8192)()
+    kmax = L.shim_table_entry(sigma_r, eps, rng_, T_cap, T, ctypes.byref(N), ctypes.byref(M), ctypes.byref(K),
+                              ctypes.byref(q), ctypes.byref(at), pm, pc, 8192)
+    assert kmax >= 0
+    return dict(N=N.value, M=M.value, K=K.value, qfix=q.value, at=at.value,
+                pm=np.array(pm[:K.value]), pc=np.array(pc[:K.value]), K_max=kmax)
+
+
+def test_order_matches_oracle(shim):
+    for sr in (2.0, 5.0, 10.0, 10.5, 20.0, 30.0, 60.0, 800.0, 1000.0):
+        for T in list(range(0, 300)) + list(range(300, 65536, 997)):
+            assert shim.shim_order_N(float(T), sr) == o.order(T, sr), (T, sr)
+
+
+def test_truncation_matches_oracle(shim):
+    for eps in (1e-2, 1e-3, 1e-4, 0.05):
+        for sr8 in (5.0, 10.0, 10.01, 25.0, 40.0, 40.5):
+            for N in list(range(1, 300)) + [411, 1053, 2718]:
+                if 10.0 < sr8 <= 40.0 and N > 600:
+                    continue
+                assert shim.shim_trunc_M(N, sr8, eps) == o.trunc_rule(N, sr8, eps), (N, sr8, eps)
+
+
+@pytest.mark.parametrize("sr,eps,rng_,T", [(10.0, 1e-3, 255.0, 212), (30.0, 1e-3, 255.0, 255),
+                                           (20.0, 1e-3, 255.0, 255), (800.0, 1e-4, 65535.0, 65535),
+                                           (50.0, 1e-3, 255.0, 100), (3.0, 1e-2, 255.0, 17)])
+def test_pairs_match_expansion(shim, sr, eps, rng_, T):
+    e = entry(shim, sr, eps, rng_, int(rng_), T)
+    N = o.order(T, sr)
+    M = o.trunc_rule(N, sr * 255.0 / rng_, eps)
+    assert (e["N"], e["M"]) == (N, M)
+    ns = [n for n in range(M, N - M + 1) if 2 * n < N]
+    exp_m = [2 * n - N for n in ns] + ([0] if N % 2 == 0 else [])
+    exp_c = [2 * o.coef(N, n) for n in ns] + ([o.coef(N, N // 2)] if N % 2 == 0 else [])
+    assert list(e["pm"]) == exp_m
+    assert np.allclose(e["pc"], exp_c, rtol=2e-7, atol=0)
+    # the folded weights sum to the kept mass of eq. (approx)
+    kept = sum(o.coef(N, n) for n in range(M, N - M + 1))
+    assert abs(float(np.sum(e["pc"].astype(np.float64))) - kept) < 1e-5
+    # fixed-point phase step: frac(1/(2 pi sqrt(N) sigma_r)) * 2^64 to a few units
+    getcontext().prec = 60
+    pi = Decimal("3.14159265358979323846264338327950288419716939937510582097494459")
+    at = Decimal(1) / (2 * pi * Decimal(N).sqrt() * Decimal(repr(sr)))
+    exact = (at - int(at)) * (Decimal(2) ** 64)
+    assert abs(Decimal(e["qfix"]) - exact) < 64
+    assert math.isclose(e["at"], float(at), rel_tol=1e-15)
+
+
+# ------------------------------------------------------------------ IIR model
+def consts(L, sigma):
+    buf = (ctypes.c_float * 8192)()
+    n = L.shim_iir_consts(sigma, buf, 8192)
+    assert n > 0
+    lay = (ctypes.c_int * 10)()
+    L.shim_layout(lay)
+    names = ["coef", "mts", "ap", "ae", "phi", "cm", "apow", "size", "kB", "kC"]
+    lay = dict(zip(names, list(lay)))
+    C = np.array(buf[:n], dtype=np.float64)
+    kB, kC = lay["kB"], lay["kC"]
+    d = dict(g1=C[0], g2=C[1], c2=C[2], kB=kB, kC=kC,
+             mts=C[lay["mts"]:lay["mts"] + 9].reshape(3, 3),
+             ap=C[lay["ap"]:lay["ap"] + 3 * kB].reshape(3, kB),
+             ae=C[lay["ae"]:lay["ae"] + 3 * kB].reshape(3, kB),
+             phi=C[lay["phi"]:lay["phi"] + 9].reshape(3, 3),
+             cm=C[lay["cm"]:lay["cm"] + 9].reshape(3, 3),
+             apow=C[lay["apow"]:lay["apow"] + 9 * (kC + 1)].reshape(kC + 1, 3, 3))
+    off = lay["apow"] + 9 * (kC + 1)
+    d["lane"] = C[off:off + 9 * 64].reshape(64, 3, 3)
+    off += 9 * 64
+    d["scan"] = C[off:off + 9 * 8].reshape(8, 3, 3)
+    off += 9 * 8
+    d["wave"] = C[off:off + 9].reshape(3, 3)
+    return d
+
+
+def _sweep(x, st, g1, g2, c2, rev=False):
+    s, w1, w2 = st
+    out = np.zeros_like(x)
+    idx = range(len(x) - 1, -1, -1) if rev else range(len(x))
+    for i in idx:
+        s = s + g1 * (x[i] - s)
+        w = w1 + g2 * (s - w1) - c2 * (w1 - w2)
+        w2, w1 = w1, w
+        out[i] = w
+    return out, np.array([s, w1, w2])
+
+
+def model_vertical(x, C):
+    """The three vertical kernels: chunk summaries, carry chain, final sweeps."""
+    kB = C["kB"]
+    H = len(x)
+    nc = -(-H // kB)
+    xp = np.zeros(nc * kB)
+    xp[:H] = x
+    g1, g2, c2 = C["g1"], C["g2"], C["c2"]
+    Pb = [C["ap"] @ xp[j * kB:(j + 1) * kB] for j in range(nc)]
+    Eb = [C["ae"] @ xp[j * kB:(j + 1) * kB] for j in range(nc)]
+    P = np.zeros(3)
+    Pin = []
+    for j in range(nc):
+        Pin.append(P)
+        P = Pb[j] + C["phi"] @ P
+    E = C["mts"] @ P
+    Ein = [None] * nc
+    for j in range(nc - 1, -1, -1):
+        Ein[j] = E
+        E = Eb[j] + C["cm"] @ Pin[j] + C["phi"] @ E
+    out = np.zeros(nc * kB)
+    for j in range(nc):
+        w, _ = _sweep(xp[j * kB:(j + 1) * kB], Pin[j], g1, g2, c2)
+        z, _ = _sweep(w, Ein[j], g1, g2, c2, rev=True)
+        out[j * kB:(j + 1) * kB] = z
+    return out[:H]
+
+
+def model_horizontal(x, C):
+    """The horizontal kernel: per-thread sweeps from rest, Hillis-Steele scans
+    of chunk states within 64-lane waves, wave carries through LDS."""
+    kC = C["kC"]
+    W = len(x)
+    S = 1
+    while S * kC < W:
+        S *= 2
+    SW = min(S, 64)
+    xp = np.zeros(S * kC)
+    xp[:W] = x
+    g1, g2, c2 = C["g1"], C["g2"], C["c2"]
+    zero3 = np.zeros(3)
+    wt, tau = [], []
+    for t in range(S):
+        w, st = _sweep(xp[t * kC:(t + 1) * kC], zero3, g1, g2, c2)
+        wt.append(w)
+        tau.append(st)
+    inc = [v.copy() for v in tau]
+    k = 0
+    while (1 << k) < SW:
+        d = 1 << k
+        new = [v.copy() for v in inc]
+        for t in range(S):
+            ls = t % SW
+            if ls >= d:
+                new[t] = inc[t] + C["scan"][k] @ inc[t - d]
+        inc = new
+        k += 1
+    exc = [np.zeros(3) if t % SW == 0 else inc[t - 1] for t in range(S)]
+    if S > 64:
+        NW = S // 64
+        tot = [inc[w * 64 + 63] for w in range(NW)]
+        for t in range(S):
+            wig, ls = t // 64, t % 64
+            Kc = np.zeros(3)
+            for w in range(wig):
+                Kc = tot[w] + C["wave"] @ Kc
+            exc[t] = exc[t] + C["lane"][ls] @ Kc
+            if t == S - 1:
+                inc[t] = inc[t] + C["wave"] @ Kc
+    for t in range(S):
+        for i in range(kC):
+            wt[t][i] += C["apow"][i + 1][1] @ exc[t]
+    Eb = C["mts"] @ inc[S - 1]
+    zt, hd = [], []
+    for t in range(S):
+        z, st = _sweep(wt[t], zero3, g1, g2, c2, rev=True)
+        zt.append(z)
+        hd.append(st)
+    hd[S - 1] = hd[S - 1] + C["apow"][kC] @ Eb
+    k = 0
+    while (1 << k) < SW:
+        d = 1 << k
+        new = [v.copy() for v in hd]
+        for t in range(S):
+            ls = t % SW
+            if ls + d < SW:
+                new[t] = hd[t] + C["scan"][k] @ hd[t + d]
+        hd = new
+        k += 1
+    ein = [np.zeros(3) if t % SW == SW - 1 else hd[t + 1] for t in range(S)]
+    if S > 64:
+        NW = S // 64
+        tot = [hd[w * 64] for w in range(NW)]
+        for t in range(S):
+            wig, ls = t // 64, t % 64
+            Kc = np.zeros(3)
+            for w in range(NW - 1, wig, -1):
+                Kc = tot[w] + C["wave"] @ Kc
+            ein[t] = ein[t] + C["lane"][63 - ls] @ Kc
+    ein[S - 1] = Eb
+    for t in range(S):
+        for i in range(kC):
+            zt[t][i] += C["apow"][kC - i][1] @ ein[t]
+    return np.concatenate(zt)[:W]
+
+
+@pytest.mark.parametrize("sigma", [0.7, 2.0, 3.0, 8.0, 10.0, 16.0])
+@pytest.mark.parametrize("n", [1, 5, 31, 32, 33, 100, 257, 512])
+def test_blocked_vertical_model_matches_oracle(shim, sigma, n):
+    C = consts(shim, sigma)
+    rng = np.random.default_rng(n)
+    x = rng.uniform(-1, 1, n)
+    ref = o.blur_1d(x, "iir", sigma)
+    got = model_vertical(x, C)
+    assert np.abs(got - ref).max() < 2e-5 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("sigma", [0.7, 3.0, 10.0, 16.0])
+@pytest.mark.parametrize("n", [1, 7, 32, 33, 200, 512, 1000, 2049, 4096])
+def test_blocked_horizontal_model_matches_oracle(shim, sigma, n):
+    C = consts(shim, sigma)
+    rng = np.random.default_rng(1000 + n)
+    x = rng.uniform(-1, 1, n)
+    ref = o.blur_1d(x, "iir", sigma)
+    got = model_horizontal(x, C)
+    assert np.abs(got - ref).max() < 2e-5 * max(1.0, np.abs(ref).max())
