@@ -127,6 +127,25 @@ bf_status bf_filter_batch(bf_plan_t plan, int32_t n, const void *const *d_in, fl
  * ceil) to *T_out after synchronising hip_stream. */
 bf_status bf_dynamic_range(bf_plan_t plan, const void *d_in, void *hip_stream, double *T_out);
 
+/* Stage timing.  While enabled, every filter call of the plan records HIP
+ * events on its stream between the stages it launches (range, vertical
+ * summaries, carry chain, vertical sweeps, horizontal pass + combine).
+ * bf_profile_read synchronises the plan's last stream, returns the summed
+ * device milliseconds and launch counts per stage since the last read, and
+ * clears them.  Stage indices are the BF_STAGE_* values. */
+enum {
+  BF_STAGE_RANGE = 0,
+  BF_STAGE_V_SUMMARY = 1,
+  BF_STAGE_V_CARRY = 2,
+  BF_STAGE_V_FINAL = 3,
+  BF_STAGE_H_COMBINE = 4,
+  BF_STAGE_TOEPLITZ = 5,
+  BF_STAGE_COUNT = 6
+};
+bf_status bf_profile(bf_plan_t plan, int32_t enable);
+bf_status bf_profile_read(bf_plan_t plan, double *ms /* [BF_STAGE_COUNT] */,
+                          int64_t *launches /* [BF_STAGE_COUNT] */);
+
 /* Release the plan.  The caller synchronises the plan's streams first. */
 void bf_plan_destroy(bf_plan_t plan);
 

@@ -11,6 +11,8 @@ from .bf import (  # noqa: F401
     bf_last_error_detail,
     bf_plan,
     bf_plan_destroy,
+    bf_profile,
+    bf_profile_read,
     bf_status_string,
     bilateral_filter,
     make_params,

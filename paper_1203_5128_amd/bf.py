@@ -36,8 +36,9 @@ BLURS = {"auto": BF_BLUR_AUTO, "iir_f32": BF_BLUR_IIR_F32, "toeplitz_f16": BF_BL
          "toeplitz_bf16x2": BF_BLUR_TOEPLITZ_BF16X2}
 BLUR_NAMES = {v: k for k, v in BLURS.items()}
 
-EXPORTS = ["bf_plan", "bf_filter", "bf_filter_batch", "bf_dynamic_range", "bf_plan_destroy",
-           "bf_status_string", "bf_last_error_detail"]
+EXPORTS = ["bf_plan", "bf_filter", "bf_filter_batch", "bf_dynamic_range", "bf_profile", "bf_profile_read",
+           "bf_plan_destroy", "bf_status_string", "bf_last_error_detail"]
+STAGES = ["range", "v_summary", "v_carry", "v_final", "h_combine", "toeplitz"]
 
 
 class bf_params(ctypes.Structure):
@@ -89,6 +90,10 @@ def lib():
         L.bf_filter_batch.restype = ctypes.c_int
         L.bf_dynamic_range.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double)]
         L.bf_dynamic_range.restype = ctypes.c_int
+        L.bf_profile.argtypes = [P, ctypes.c_int32]
+        L.bf_profile.restype = ctypes.c_int
+        L.bf_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.bf_profile_read.restype = ctypes.c_int
         L.bf_plan_destroy.argtypes = [P]
         L.bf_plan_destroy.restype = None
         L.bf_status_string.argtypes = [ctypes.c_int]
@@ -166,6 +171,18 @@ def bf_dynamic_range(plan: int, d_in: int, stream=None) -> float:
     return T.value
 
 
+def bf_profile(plan: int, enable: bool):
+    _check(lib().bf_profile(plan, int(bool(enable))))
+
+
+def bf_profile_read(plan: int):
+    """{stage: (milliseconds, launches)} since the last read."""
+    ms = (ctypes.c_double * len(STAGES))()
+    n = (ctypes.c_int64 * len(STAGES))()
+    _check(lib().bf_profile_read(plan, ms, n))
+    return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
+
+
 def bf_plan_destroy(plan: int):
     lib().bf_plan_destroy(plan)
 
@@ -194,6 +211,12 @@ class Plan:
         reps = bf_filter_batch(self.handle, [i.data_ptr() for i in imgs], [o.data_ptr() for o in outs],
                                stream, report)
         return outs, reps
+
+    def profile(self, enable=True):
+        bf_profile(self.handle, enable)
+
+    def profile_read(self):
+        return bf_profile_read(self.handle)
 
     def dynamic_range(self, img, stream=None):
         return bf_dynamic_range(self.handle, img.data_ptr(), stream)

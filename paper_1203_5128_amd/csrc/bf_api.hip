@@ -67,6 +67,15 @@ struct bf_plan_s {
   float2 *d_PQ = nullptr;
   size_t rowmax_bytes = 0, cb_bytes = 0, Z_bytes = 0, PQ_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // stage timing (bf_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Pending { int stage; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  hipEvent_t open_ev[BF_STAGE_COUNT] = {};
+  double prof_ms[BF_STAGE_COUNT] = {};
+  int64_t prof_n[BF_STAGE_COUNT] = {};
+  StageRec rec;
 };
 
 namespace {
@@ -197,6 +206,35 @@ bf_status ensure(void **ptr, size_t &have, size_t need) {
   return BF_OK;
 }
 
+hipEvent_t take_event(bf_plan_s *pl) {
+  if (!pl->ev_pool.empty()) {
+    hipEvent_t e = pl->ev_pool.back();
+    pl->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void stage_mark(void *ctx, int stage, hipStream_t s, bool end) {
+  bf_plan_s *pl = (bf_plan_s *)ctx;
+  if (!end) {
+    hipEvent_t e = take_event(pl);
+    if (e && hipEventRecord(e, s) == hipSuccess) pl->open_ev[stage] = e;
+    return;
+  }
+  hipEvent_t a = pl->open_ev[stage];
+  pl->open_ev[stage] = nullptr;
+  if (!a) return;
+  hipEvent_t b = take_event(pl);
+  if (!b || hipEventRecord(b, s) != hipSuccess) {
+    pl->ev_pool.push_back(a);
+    return;
+  }
+  pl->pending.push_back({stage, a, b});
+}
+
 // Enqueue the whole of Algorithm 2 for one image.
 bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out, hipStream_t s) {
   const Geom &g = ip.g;
@@ -206,7 +244,7 @@ bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out
   if (ip.p.t_mode == BF_T_LOCAL) {
     e = launch_reset(s, st, 0, 0.0);
     if (e != hipSuccess) return dev_fail(e, "reset");
-    e = launch_range(s, ip.p.dtype, d_in, g, ip.R, pl->d_rowmax, st, ip.T_cap);
+    e = launch_range(s, ip.p.dtype, d_in, g, ip.R, pl->d_rowmax, st, ip.T_cap, pl->rec);
     if (e != hipSuccess) return dev_fail(e, "dynamic range");
   } else {
     e = launch_reset(s, st, ip.T_global, ip.T_global_raw);
@@ -216,7 +254,7 @@ bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out
   for (int k0 = 0; k0 < Kmax; k0 += ip.KC) {
     const int kcount = std::min(ip.KC, Kmax - k0);
     e = launch_iir_chunk(s, ip.p.dtype, d_in, d_out, g, tab, st, ip.d_iir, k0, kcount, pl->d_cb, pl->d_Z,
-                         pl->d_PQ, k0 == 0, k0 + ip.KC >= Kmax);
+                         pl->d_PQ, k0 == 0, k0 + ip.KC >= Kmax, pl->rec);
     if (e != hipSuccess) return dev_fail(e, "blur");
   }
   return BF_OK;
@@ -309,8 +347,45 @@ bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out) {
   return BF_OK;
 }
 
+bf_status bf_profile(bf_plan_t pl, int32_t enable) {
+  if (!pl) return fail(BF_ERR_INVALID_ARG, "NULL plan");
+  pl->prof = enable != 0;
+  pl->rec.mark = pl->prof ? stage_mark : nullptr;
+  pl->rec.ctx = pl;
+  return BF_OK;
+}
+
+bf_status bf_profile_read(bf_plan_t pl, double *ms, int64_t *launches) {
+  if (!pl || !ms || !launches) return fail(BF_ERR_INVALID_ARG, "NULL argument");
+  for (auto &p : pl->pending) {
+    hipError_t e = hipEventSynchronize(p.b);
+    if (e != hipSuccess) return dev_fail(e, "hipEventSynchronize");
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, p.a, p.b);
+    pl->prof_ms[p.stage] += t;
+    pl->prof_n[p.stage] += 1;
+    pl->ev_pool.push_back(p.a);
+    pl->ev_pool.push_back(p.b);
+  }
+  pl->pending.clear();
+  for (int i = 0; i < BF_STAGE_COUNT; i++) {
+    ms[i] = pl->prof_ms[i];
+    launches[i] = pl->prof_n[i];
+    pl->prof_ms[i] = 0.0;
+    pl->prof_n[i] = 0;
+  }
+  return BF_OK;
+}
+
 void bf_plan_destroy(bf_plan_t pl) {
   if (!pl) return;
+  for (auto &p : pl->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : pl->ev_pool) (void)hipEventDestroy(e);
+  for (auto e : pl->open_ev)
+    if (e) (void)hipEventDestroy(e);
   for (auto &ip : pl->im) free_image(ip);
   (void)hipFree(pl->d_rowmax);
   (void)hipFree(pl->d_cb);
@@ -369,7 +444,7 @@ bf_status bf_dynamic_range(bf_plan_t pl, const void *d_in, void *hip_stream, dou
   ImagePlan &ip = pl->im[0];
   DevState st = state_of(ip);
   hipError_t e = launch_reset(s, st, 0, 0.0);
-  if (e == hipSuccess) e = launch_range(s, ip.p.dtype, d_in, ip.g, ip.R, pl->d_rowmax, st, ip.T_cap);
+  if (e == hipSuccess) e = launch_range(s, ip.p.dtype, d_in, ip.g, ip.R, pl->d_rowmax, st, ip.T_cap, pl->rec);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return dev_fail(e, "dynamic range");
   unsigned long long traw;

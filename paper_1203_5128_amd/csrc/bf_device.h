@@ -37,12 +37,22 @@ struct Geom {
   float center;       // intensity subtracted from f in the f*cos, f*sin images
 };
 
+// Optional recorder of stage boundaries (host side): called before and after
+// each stage's launches on the launch stream.
+struct StageRec {
+  void (*mark)(void *ctx, int stage, hipStream_t s, bool end) = nullptr;
+  void *ctx = nullptr;
+  void begin(int stage, hipStream_t s) const { if (mark) mark(ctx, stage, s, false); }
+  void end(int stage, hipStream_t s) const { if (mark) mark(ctx, stage, s, true); }
+};
+
 // ---- launch wrappers (bf_kernels.hip) ----
 hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw);
 hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,
-                        DevState st, int32_t T_cap);
+                        DevState st, int32_t T_cap, const StageRec &rec);
 hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *out, const Geom &g,
                             DevTables tab, DevState st, const float *iir, int k0, int kcount,
-                            float4 *cb, float4 *Z, float2 *PQ, bool first, bool last);
+                            float4 *cb, float4 *Z, float2 *PQ, bool first, bool last,
+                            const StageRec &rec);
 
 }  // namespace bfi

@@ -49,8 +49,11 @@ bool build_order_table(double sigma_r, double eps, double value_range, int32_t T
                        OrderTable &out, std::string &err);
 
 // ------------------------------------------- recursive Gaussian constants
-// State of one direction of the cascade after element n: (s[n], w[n], w[n-1])
-// with s the first-order section and w the second-order section output.
+// State of one direction of the cascade after element n: (s[n], w[n], d[n])
+// with s the first-order section, w the second-order section output and
+// d[n] = w[n] - w[n-1].  Carrying the difference instead of w[n-1] keeps the
+// FP32 rounding of the second-order section from being fed back through its
+// poles, which sit close to z = 1 for wide Gaussians.
 // Rows and columns are padded with zeros to a multiple of the chunk length and
 // the zero-extension boundary is applied at the padded end: the causal outputs
 // in the padding are exactly the continuation of the zero-extended signal, so

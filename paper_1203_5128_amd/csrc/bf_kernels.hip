@@ -62,6 +62,17 @@ __device__ __forceinline__ float4 shfl_down4(float4 v, int d, int w) {
                      __shfl_down(v.w, d, w));
 }
 
+// One step of the recursive Gaussian cascade on the state (s, w, d):
+// first-order section s += g1 (x - s), then the second-order section carried
+// as w[n] = w[n-1] + d[n], d[n] = g2 (s - w[n-1]) - c2 d[n-1].
+__device__ __forceinline__ void casc_step(float g1, float g2, float c2, float4 x, float4 &s, float4 &w,
+                                          float4 &d) {
+  s = fma4(g1, sub4(x, s), s);
+  float4 nd = fma4(-c2, d, make_float4(g2 * (s.x - w.x), g2 * (s.y - w.y), g2 * (s.z - w.z), g2 * (s.w - w.w)));
+  w = add4(w, nd);
+  d = nd;
+}
+
 template <typename Tin>
 __device__ __forceinline__ float fval(Tin v) {
   return (float)v;
@@ -397,33 +408,25 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_final(const Tin *__restrict
   const float g1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
   const size_t base = ((size_t)kl * g.nc + j) * 6;
   float4 s = cb[(base + 0) * g.Spos + p];
-  float4 w1 = cb[(base + 1) * g.Spos + p];
-  float4 w2 = cb[(base + 2) * g.Spos + p];
+  float4 w = cb[(base + 1) * g.Spos + p];
+  float4 d = cb[(base + 2) * g.Spos + p];
   float4 wv[kB];
 #pragma unroll
   for (int i = 0; i < kB; i++) {
     const int y = y0 + i;
     float4 xv = f4(0.f);
     if (y < g.H) xv = planes<Tin>(f[(int64_t)y * g.pitch + x], m, q, at, g.center);
-    s = fma4(g1, sub4(xv, s), s);
-    float4 w = fma4(g2, sub4(s, w1), w1);
-    w = fma4(-c2, sub4(w1, w2), w);
-    w2 = w1;
-    w1 = w;
+    casc_step(g1, g2, c2, xv, s, w, d);
     wv[i] = w;
   }
-  float4 a = cb[(base + 3) * g.Spos + p];
-  float4 z1 = cb[(base + 4) * g.Spos + p];
-  float4 z2 = cb[(base + 5) * g.Spos + p];
+  s = cb[(base + 3) * g.Spos + p];
+  w = cb[(base + 4) * g.Spos + p];
+  d = cb[(base + 5) * g.Spos + p];
 #pragma unroll
   for (int i = kB - 1; i >= 0; i--) {
-    a = fma4(g1, sub4(wv[i], a), a);
-    float4 z = fma4(g2, sub4(a, z1), z1);
-    z = fma4(-c2, sub4(z1, z2), z);
-    z2 = z1;
-    z1 = z;
+    casc_step(g1, g2, c2, wv[i], s, w, d);
     const int y = y0 + i;
-    if (y < g.H) Zk[(size_t)y * g.Spos + p] = z;
+    if (y < g.H) Zk[(size_t)y * g.Spos + p] = w;
   }
 }
 
@@ -499,17 +502,13 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
 #pragma unroll
     for (int i = 0; i < kC; i++) zv[i] = Zr[i * S + t];
     // causal sweep from rest
-    float4 s = f4(0.f), w1 = f4(0.f), w2 = f4(0.f);
+    float4 s = f4(0.f), w = f4(0.f), d = f4(0.f);
 #pragma unroll
     for (int i = 0; i < kC; i++) {
-      s = fma4(g1, sub4(zv[i], s), s);
-      float4 w = fma4(g2, sub4(s, w1), w1);
-      w = fma4(-c2, sub4(w1, w2), w);
-      w2 = w1;
-      w1 = w;
+      casc_step(g1, g2, c2, zv[i], s, w, d);
       zv[i] = w;
     }
-    float4 inc[3] = {s, w1, w2};
+    float4 inc[3] = {s, w, d};
     scan_up<SW>(inc, scanM, ls);
     float4 exc[3];
 #pragma unroll
@@ -541,17 +540,15 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
     float4 Eb[3] = {f4(0.f), f4(0.f), f4(0.f)};
     if (t == S - 1) matvec3(iir + kIirMts, inc, Eb);
     // anticausal sweep from rest
-    float4 a = f4(0.f), z1 = f4(0.f), z2 = f4(0.f);
+    s = f4(0.f);
+    w = f4(0.f);
+    d = f4(0.f);
 #pragma unroll
     for (int i = kC - 1; i >= 0; i--) {
-      a = fma4(g1, sub4(zv[i], a), a);
-      float4 z = fma4(g2, sub4(a, z1), z1);
-      z = fma4(-c2, sub4(z1, z2), z);
-      z2 = z1;
-      z1 = z;
-      zv[i] = z;
+      casc_step(g1, g2, c2, zv[i], s, w, d);
+      zv[i] = w;
     }
-    float4 hd[3] = {a, z1, z2};
+    float4 hd[3] = {s, w, d};
     if (t == S - 1) matvec3_acc(Apow + 9 * kC, Eb, hd);
     scan_down<SW>(hd, scanM, ls);
     float4 ein[3];
@@ -651,22 +648,24 @@ hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw
 
 template <typename Tin>
 static hipError_t range_t(hipStream_t s, const Tin *f, const Geom &g, int R, Tin *rowmax, DevState st,
-                          int32_t T_cap) {
+                          int32_t T_cap, const StageRec &rec) {
+  rec.begin(BF_STAGE_RANGE, s);
   dim3 gr((g.W + kRowSeg - 1) / kRowSeg, g.H);
   hipLaunchKernelGGL(k_rowmax<Tin>, gr, dim3(64), 0, s, f, g.pitch, g.H, g.W, R, rowmax, st);
   dim3 gc((g.W + 63) / 64, (g.H + kColBand - 1) / kColBand);
   hipLaunchKernelGGL(k_colmax_T<Tin>, gc, dim3(64), 0, s, f, g.pitch, (const Tin *)rowmax, g.H, g.W, R,
                      st, T_cap);
+  rec.end(BF_STAGE_RANGE, s);
   return hipGetLastError();
 }
 
 hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,
-                        DevState st, int32_t T_cap) {
+                        DevState st, int32_t T_cap, const StageRec &rec) {
   if (R > kMaxR) return hipErrorInvalidValue;
   switch (dt) {
-    case BF_U8: return range_t<uint8_t>(s, (const uint8_t *)f, g, R, (uint8_t *)rowmax, st, T_cap);
-    case BF_U16: return range_t<uint16_t>(s, (const uint16_t *)f, g, R, (uint16_t *)rowmax, st, T_cap);
-    default: return range_t<float>(s, (const float *)f, g, R, (float *)rowmax, st, T_cap);
+    case BF_U8: return range_t<uint8_t>(s, (const uint8_t *)f, g, R, (uint8_t *)rowmax, st, T_cap, rec);
+    case BF_U16: return range_t<uint16_t>(s, (const uint16_t *)f, g, R, (uint16_t *)rowmax, st, T_cap, rec);
+    default: return range_t<float>(s, (const float *)f, g, R, (float *)rowmax, st, T_cap, rec);
   }
 }
 
@@ -681,15 +680,22 @@ static void launch_h(hipStream_t s, const Tin *f, float *out, const Geom &g, Dev
 template <typename Tin>
 static hipError_t iir_chunk_t(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab,
                               DevState st, const float *iir, int k0, int kcount, float4 *cb, float4 *Z,
-                              float2 *PQ, bool first, bool last) {
+                              float2 *PQ, bool first, bool last, const StageRec &rec) {
   const int nbx = (g.Spos + kVThreads - 1) / kVThreads;
   if (kcount > 0) {
+    rec.begin(BF_STAGE_V_SUMMARY, s);
     hipLaunchKernelGGL(k_iir_v_summary<Tin>, dim3(nbx, g.nc, kcount), dim3(kVThreads), 0, s, f, g, tab,
                        st, iir, k0, cb);
+    rec.end(BF_STAGE_V_SUMMARY, s);
+    rec.begin(BF_STAGE_V_CARRY, s);
     hipLaunchKernelGGL(k_iir_v_fixup, dim3(nbx, kcount), dim3(kVThreads), 0, s, g, tab, st, iir, k0, cb);
+    rec.end(BF_STAGE_V_CARRY, s);
+    rec.begin(BF_STAGE_V_FINAL, s);
     hipLaunchKernelGGL(k_iir_v_final<Tin>, dim3(nbx, g.nc, kcount), dim3(kVThreads), 0, s, f, g, tab, st,
                        iir, k0, (const float4 *)cb, Z);
+    rec.end(BF_STAGE_V_FINAL, s);
   }
+  rec.begin(BF_STAGE_H_COMBINE, s);
   switch (g.S) {
     case 1: launch_h<Tin, 1>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
     case 2: launch_h<Tin, 2>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
@@ -702,22 +708,23 @@ static hipError_t iir_chunk_t(hipStream_t s, const Tin *f, float *out, const Geo
     case 256: launch_h<Tin, 256>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
     default: return hipErrorInvalidValue;
   }
+  rec.end(BF_STAGE_H_COMBINE, s);
   return hipGetLastError();
 }
 
 hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *out, const Geom &g,
                             DevTables tab, DevState st, const float *iir, int k0, int kcount, float4 *cb,
-                            float4 *Z, float2 *PQ, bool first, bool last) {
+                            float4 *Z, float2 *PQ, bool first, bool last, const StageRec &rec) {
   switch (dt) {
     case BF_U8:
       return iir_chunk_t<uint8_t>(s, (const uint8_t *)f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, first,
-                                  last);
+                                  last, rec);
     case BF_U16:
       return iir_chunk_t<uint16_t>(s, (const uint16_t *)f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ,
-                                   first, last);
+                                   first, last, rec);
     default:
       return iir_chunk_t<float>(s, (const float *)f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, first,
-                                last);
+                                last, rec);
   }
 }
 

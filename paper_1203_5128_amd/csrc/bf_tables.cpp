@@ -154,12 +154,12 @@ M3 mpow(const M3 &x, long e) {
 }
 struct Casc {
   double g1, g2, c2;
-  // one step of the cascade on state (s, w1, w2) with input x
+  // one step of the cascade on state (s, w, d) with input x, d = w[n] - w[n-1]
   void step(double st[3], double x) const {
     double s = st[0] + g1 * (x - st[0]);
-    double w = st[1] + g2 * (s - st[1]) - c2 * (st[1] - st[2]);
-    st[2] = st[1];
-    st[1] = w;
+    double d = g2 * (s - st[1]) - c2 * st[2];
+    st[1] = st[1] + d;
+    st[2] = d;
     st[0] = s;
   }
 };
@@ -201,10 +201,11 @@ bool build_iir_consts(double sigma_s, std::vector<float> &out, std::string &err)
   out[kIirCoef + 0] = (float)g1;
   out[kIirCoef + 1] = (float)g2;
   out[kIirCoef + 2] = (float)c2;
+  // zero-input step of Casc as a matrix on (s, w, d)
   M3 A{};
   A.a[0] = 1.0 - g1;
-  A.a[3] = g2 * (1.0 - g1); A.a[4] = 1.0 - g2 - c2; A.a[5] = c2;
-  A.a[7] = 1.0;
+  A.a[3] = g2 * (1.0 - g1); A.a[4] = 1.0 - g2; A.a[5] = -c2;
+  A.a[6] = g2 * (1.0 - g1); A.a[7] = -g2;      A.a[8] = -c2;
   // zero-extension boundary: continue the causal recursion with zero input
   // past the end, run the anticausal recursion back from far away
   long L = (long)std::ceil(40.0 * sigma_s) + 64;

@@ -117,15 +117,15 @@ def consts(L, sigma):
 
 
 def _sweep(x, st, g1, g2, c2, rev=False):
-    s, w1, w2 = st
+    s, w, d = st
     out = np.zeros_like(x)
     idx = range(len(x) - 1, -1, -1) if rev else range(len(x))
     for i in idx:
         s = s + g1 * (x[i] - s)
-        w = w1 + g2 * (s - w1) - c2 * (w1 - w2)
-        w2, w1 = w1, w
+        d = g2 * (s - w) - c2 * d
+        w = w + d
         out[i] = w
-    return out, np.array([s, w1, w2])
+    return out, np.array([s, w, d])
 
 
 def model_vertical(x, C):
