@@ -159,11 +159,17 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip) {
   g.W = p.width;
   g.pitch = p.in_pitch > 0 ? p.in_pitch : p.width;
   g.opitch = p.out_pitch > 0 ? p.out_pitch : p.width;
+  // pixels per thread of the horizontal pass: the smaller chunk needs fewer
+  // registers (more waves in flight) but twice the scan steps per pixel
+  int cC = kCSmall;
+  if (const char *c = std::getenv("BF_HCHUNK")) cC = std::atoi(c) == kCLarge ? kCLarge : kCSmall;
+  if (g.W > kCSmall * kHThreads) cC = kCLarge;
   int S = 1, logS = 0;
-  while (S * kC < g.W) { S <<= 1; logS++; }
+  while (S * cC < g.W) { S <<= 1; logS++; }
   g.S = S;
   g.logS = logS;
-  g.Spos = S * kC;
+  g.cC = cC;
+  g.Spos = S * cC;
   g.nc = (g.H + kB - 1) / kB;
   g.center = (float)(0.5 * ip.range);
   // device tables

@@ -32,7 +32,8 @@ struct Geom {
   int64_t pitch;      // input pitch (elements)
   int64_t opitch;     // output pitch (elements)
   int S, logS;        // threads per row in the horizontal pass (power of two)
-  int Spos;           // S * kC positions per padded row
+  int cC;             // pixels per thread in the horizontal pass (kCSmall or kCLarge)
+  int Spos;           // S * cC positions per padded row
   int nc;             // vertical chunks of kB rows
   float center;       // intensity subtracted from f in the f*cos, f*sin images
 };

@@ -13,14 +13,16 @@ namespace bfi {
 // ---------------------------------------------------------------- geometry
 // Vertical pass: rows per chunk of the blocked recursive filter.
 constexpr int kB = 32;
-// Horizontal pass: pixels of a row owned by one thread.
-constexpr int kC = 32;
+// Horizontal pass: pixels of a row owned by one thread (a per-plan choice
+// between the two values below; each has its own block of scan constants).
+constexpr int kCSmall = 16;
+constexpr int kCLarge = 32;
 // Threads per workgroup of the horizontal pass.
 constexpr int kHThreads = 256;
 // Threads per workgroup of the vertical passes.
 constexpr int kVThreads = 256;
-// Largest supported width: kC * kHThreads pixels in one row group.
-constexpr int kMaxWidth = kC * kHThreads;
+// Largest supported width: one row group of kHThreads threads.
+constexpr int kMaxWidth = kCLarge * kHThreads;
 
 // ------------------------------------------------------- order tables (a1)
 // One entry per distinct order N reachable from T in [0, T_cap].
@@ -65,11 +67,17 @@ constexpr int kIirApFull = kIirMts + 9;          // 3 x kB: chunk end state per 
 constexpr int kIirAeFull = kIirApFull + 3 * kB;  // 3 x kB: chunk head state per input
 constexpr int kIirPhiFull = kIirAeFull + 3 * kB; // 3x3: A^kB
 constexpr int kIirCmFull = kIirPhiFull + 9;      // 3x3: causal carry -> anticausal head
-constexpr int kIirApow = kIirCmFull + 9;         // 9 x (kC+1): A^v, v = 0..kC
-constexpr int kIirLane = kIirApow + 9 * (kC + 1);// 9 x 64: A^(kC*l), l = 0..63
-constexpr int kIirScan = kIirLane + 9 * 64;      // 9 x 8: A^(kC*2^k), k = 0..7
-constexpr int kIirWave = kIirScan + 9 * 8;       // 9: A^(64 kC)
-constexpr int kIirSize = kIirWave + 9;
+// Horizontal-pass block for a chunk of c pixels per thread:
+//   A^v, v = 0..c (9 each); A^(c l), l = 0..63; A^(c 2^k), k = 0..7; A^(64 c).
+constexpr int iir_hblock_size(int c) { return 9 * (c + 1) + 9 * 64 + 9 * 8 + 9; }
+constexpr int kIirHSmall = kIirCmFull + 9;
+constexpr int kIirHLarge = kIirHSmall + iir_hblock_size(kCSmall);
+constexpr int kIirSize = kIirHLarge + iir_hblock_size(kCLarge);
+// offsets inside a horizontal block
+constexpr int iir_h_apow(int) { return 0; }
+constexpr int iir_h_lane(int c) { return 9 * (c + 1); }
+constexpr int iir_h_scan(int c) { return 9 * (c + 1) + 9 * 64; }
+constexpr int iir_h_wave(int c) { return 9 * (c + 1) + 9 * 64 + 9 * 8; }
 
 bool yvv_cascade(double sigma, double &g1, double &g2, double &c1, double &c2, std::string &err);
 bool build_iir_consts(double sigma_s, std::vector<float> &out, std::string &err);

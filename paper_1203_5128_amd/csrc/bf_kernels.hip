@@ -78,6 +78,60 @@ __device__ __forceinline__ float fval(Tin v) {
   return (float)v;
 }
 
+// ---- segmented running maxima across a wave (Appendix MAX-FILTER) --------
+// Lane l holds element e = e0 + l.  Partitions of the running maxima start at
+// segs (scan up) or end at sege (scan down).  Within each 16-lane row the
+// scan uses DPP row shifts (VALU only); rows are then chained through
+// v_readlane of the last lane of the previous row.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(-INFINITY), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ float seg_max_up(float v, int e, int segs, int lane) {
+  const int lr = lane & 15;
+  float o;
+  o = dpp_mov<0x111>(v);  // row_shr:1
+  if (lr >= 1 && e - 1 >= segs) v = fmaxf(v, o);
+  o = dpp_mov<0x112>(v);  // row_shr:2
+  if (lr >= 2 && e - 2 >= segs) v = fmaxf(v, o);
+  o = dpp_mov<0x114>(v);  // row_shr:4
+  if (lr >= 4 && e - 4 >= segs) v = fmaxf(v, o);
+  o = dpp_mov<0x118>(v);  // row_shr:8
+  if (lr >= 8 && e - 8 >= segs) v = fmaxf(v, o);
+  const int e0 = e - lane;
+  float t = lane_value(v, 15);
+  if ((lane >> 4) == 1 && e0 + 15 >= segs) v = fmaxf(v, t);
+  t = lane_value(v, 31);
+  if ((lane >> 4) == 2 && e0 + 31 >= segs) v = fmaxf(v, t);
+  t = lane_value(v, 47);
+  if ((lane >> 4) == 3 && e0 + 47 >= segs) v = fmaxf(v, t);
+  return v;
+}
+__device__ __forceinline__ float seg_max_down(float v, int e, int sege, int lane) {
+  const int lr = lane & 15;
+  float o;
+  o = dpp_mov<0x101>(v);  // row_shl:1
+  if (lr <= 14 && e + 1 <= sege) v = fmaxf(v, o);
+  o = dpp_mov<0x102>(v);  // row_shl:2
+  if (lr <= 13 && e + 2 <= sege) v = fmaxf(v, o);
+  o = dpp_mov<0x104>(v);  // row_shl:4
+  if (lr <= 11 && e + 4 <= sege) v = fmaxf(v, o);
+  o = dpp_mov<0x108>(v);  // row_shl:8
+  if (lr <= 7 && e + 8 <= sege) v = fmaxf(v, o);
+  const int e0 = e - lane;
+  float t = lane_value(v, 48);
+  if ((lane >> 4) == 2 && e0 + 48 <= sege) v = fmaxf(v, t);
+  t = lane_value(v, 32);
+  if ((lane >> 4) == 1 && e0 + 32 <= sege) v = fmaxf(v, t);
+  t = lane_value(v, 16);
+  if ((lane >> 4) == 0 && e0 + 16 <= sege) v = fmaxf(v, t);
+  return v;
+}
+
 __device__ __forceinline__ const OrderEntry &lookup(const DevTables &tab, const int32_t *Tu) {
   int T = *Tu;
   T = T < 0 ? 0 : (T > tab.T_cap ? tab.T_cap : T);
@@ -145,6 +199,20 @@ __device__ __forceinline__ float4 planes(Tin v, int32_t m, uint64_t q, double at
   return make_float4(d * c, d * s, c, s);
 }
 
+// Publish a non-negative dynamic-range candidate.  Many workgroups race for
+// the same two words, so an atomic is issued only when a relaxed read shows
+// that the candidate is larger than the current value.
+__device__ __forceinline__ void publish_T(const DevState &st, double t, int32_t T_cap) {
+  const double tc = ceil(t);
+  const int ti = tc > 2147483647.0 ? 2147483647 : (int)tc;
+  const unsigned long long tb = (unsigned long long)__double_as_longlong(t);
+  if (ti > __hip_atomic_load(st.T_used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(st.T_used, ti);
+  if (tb > __hip_atomic_load(st.T_raw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(st.T_raw, tb);
+  if (ti > T_cap) atomicOr(st.flags, 2);
+}
+
 // ------------------------------------------------------------------- reset
 __global__ void k_reset(DevState st, int32_t T_used, double T_raw) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -162,108 +230,171 @@ __global__ void k_reset(DevState st, int32_t T_used, double T_raw) {
 // and right running maxima r (reset at each partition end) are segmented
 // scans done with wave shuffles, carried tile to tile; then
 // out(x) = max(r[e], l[e+2R]) with e = x - xs.
+// e mod Wd for 0 <= e < 2^22 without an integer division
+__device__ __forceinline__ int mod_small(int e, int Wd, float inv) {
+  int q = (int)((float)e * inv);
+  int r = e - q * Wd;
+  r = r < 0 ? r + Wd : r;
+  r = r >= Wd ? r - Wd : r;
+  return r;
+}
+
 constexpr int kRowSeg = 256;
 constexpr int kMaxR = 1024;
 
 template <typename Tin>
 __global__ __launch_bounds__(64) void k_rowmax(const Tin *__restrict__ f, int64_t pitch, int H, int W,
                                                int R, Tin *__restrict__ rowmax, DevState st) {
+  __shared__ float sv[kRowSeg + 2 * kMaxR + 64];
   __shared__ float sl[kRowSeg + 2 * kMaxR + 64];
-  __shared__ float sr[kRowSeg + 2 * kMaxR + 64];
   const int y = blockIdx.y;
   const int xs = blockIdx.x * kRowSeg;
   if (xs >= W) return;
   const int n_out = min(kRowSeg, W - xs);
   const int L = n_out + 2 * R;
   const int Wd = 2 * R + 1;
+  const float inv = 1.0f / (float)Wd;
   const int lane = threadIdx.x;
   const Tin *frow = f + (int64_t)y * pitch;
   bool bad = false;
+  // stage the segment and its halo, 8 loads per lane in flight at a time
+  for (int e0 = 0; e0 < L; e0 += 8 * 64) {
+    float vb[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int e = e0 + u * 64 + lane;
+      const int x = xs - R + e;
+      vb[u] = (e < L && x >= 0 && x < W) ? fval(frow[x]) : -INFINITY;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int e = e0 + u * 64 + lane;
+      if (e < L) {
+        const int x = xs - R + e;
+        const float v = vb[u];
+        if (x >= 0 && x < W && !isfinite(v)) bad = true;  // NaN or Inf in the image
+        sv[e] = isfinite(v) ? v : -INFINITY;
+      }
+    }
+  }
+  __syncthreads();
   float carry = -INFINITY;
   for (int e0 = 0; e0 < L; e0 += 64) {
     const int e = e0 + lane;
-    const int x = xs - R + e;
-    float v = -INFINITY;
-    if (e < L && x >= 0 && x < W) {
-      v = fval(frow[x]);
-      if (!isfinite(v)) { bad = true; v = -INFINITY; }
-    }
-    const int segs = e - e % Wd;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      float o = __shfl_up(v, d, 64);
-      if (lane >= d && e - d >= segs) v = fmaxf(v, o);
-    }
+    float v = e < L ? sv[e] : -INFINITY;
+    const int segs = e - mod_small(e, Wd, inv);
+    v = seg_max_up(v, e, segs, lane);
     if (e0 > 0 && e0 - 1 >= segs) v = fmaxf(v, carry);
-    carry = __shfl(v, 63, 64);
+    carry = lane_value(v, 63);
     if (e < L) sl[e] = v;
   }
   carry = -INFINITY;
   for (int e0 = ((L - 1) / 64) * 64; e0 >= 0; e0 -= 64) {
     const int e = e0 + lane;
-    const int x = xs - R + e;
-    float v = -INFINITY;
-    if (e < L && x >= 0 && x < W) {
-      v = fval(frow[x]);
-      if (!isfinite(v)) v = -INFINITY;
-    }
-    const int sege = e - e % Wd + Wd - 1;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      float o = __shfl_down(v, d, 64);
-      if (lane + d < 64 && e + d <= sege) v = fmaxf(v, o);
-    }
+    float v = e < L ? sv[e] : -INFINITY;
+    const int sege = e - mod_small(e, Wd, inv) + Wd - 1;
+    v = seg_max_down(v, e, sege, lane);
     if (e0 + 64 <= sege) v = fmaxf(v, carry);
-    carry = __shfl(v, 0, 64);
-    if (e < L) sr[e] = v;
+    carry = lane_value(v, 0);
+    // r[e] is final here; out(x) = max(r[x - xs], l[x - xs + 2R])
+    if (e < n_out) sv[e] = v;  // sv[e] no longer needed as input for e' <= e
   }
   __syncthreads();
   Tin *orow = rowmax + (int64_t)y * W + xs;
-  for (int i = lane; i < n_out; i += 64) orow[i] = (Tin)fmaxf(sr[i], sl[i + 2 * R]);
+  for (int i = lane; i < n_out; i += 64) orow[i] = (Tin)fmaxf(sv[i], sl[i + 2 * R]);
   if (__any(bad) && lane == 0) atomicOr(st.flags, 1);
 }
 
 // ---------------------------------------- Algorithm 1, column pass and T
-// One lane per column, a band of kColBand rows per workgroup (with R rows of
-// halo each side).  Right running maxima of the band are built bottom-up into
-// LDS, left running maxima top-down, out = max(r, l) as in the row pass; then
-// T = max over the band of (out - f) (Prop. 2.1, sign read from its proof).
-constexpr int kColBand = 128;
+// A workgroup takes 16 columns and a band of 64 output rows.  The band's row
+// maxima with R rows of halo above and below, and f over the band, are staged
+// in LDS (row stride 17 floats: a wave reading down a column hits distinct
+// banks).  Each wave then takes 4 columns and runs the segmented right and
+// left running maxima with its lanes along the column, exactly as the row
+// pass does along rows; T = max (out - f) (Prop. 2.1, sign read from its
+// proof) is reduced over the band.
+constexpr int kColBand = 64;
+constexpr int kColMaxR = 48;
+constexpr int kColW = 16;
+constexpr int kColStride = kColW + 1;
 
 template <typename Tin>
-__global__ __launch_bounds__(64) void k_colmax_T(const Tin *__restrict__ f, int64_t pitch,
-                                                 const Tin *__restrict__ rowmax, int H, int W, int R,
-                                                 DevState st, int32_t T_cap) {
-  __shared__ float srb[kColBand][64];
-  const int lane = threadIdx.x;
-  const int x = blockIdx.x * 64 + lane;
+__global__ __launch_bounds__(256) void k_colmax_T(const Tin *__restrict__ f, int64_t pitch,
+                                                  const Tin *__restrict__ rowmax, int H, int W, int R,
+                                                  DevState st, int32_t T_cap) {
+  __shared__ float tile[(kColBand + 2 * kColMaxR) * kColStride];
+  __shared__ float fb[kColBand * kColStride];
+  __shared__ float rr[4][4][kColBand];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int x0 = blockIdx.x * kColW;
   const int y0 = blockIdx.y * kColBand;
   const int nb = min(kColBand, H - y0);
-  const int L = nb + 2 * R;
-  const int Wd = 2 * R + 1;
-  double tmax = 0.0;
-  if (x < W) {
-    float r = -INFINITY;
-    int ph = (L - 1) % Wd;  // position of e inside its partition
-    for (int e = L - 1; e >= 0; e--) {
-      const int y = y0 - R + e;
-      float v = (y >= 0 && y < H) ? fval(rowmax[(int64_t)y * W + x]) : -INFINITY;
-      r = (ph == Wd - 1) ? v : fmaxf(r, v);
-      if (e < nb) srb[e][lane] = r;
-      ph = ph == 0 ? Wd - 1 : ph - 1;
+  const int L = nb + 2 * R;  // tile rows: y = y0 - R + e
+  for (int base = 0; base < L * kColW; base += 4 * 256) {
+    float vb[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int idx = base + u * 256 + tid;
+      const int e = idx >> 4, c = idx & 15;
+      const int y = y0 - R + e, x = x0 + c;
+      vb[u] = (idx < L * kColW && y >= 0 && y < H && x < W) ? fval(rowmax[(int64_t)y * W + x]) : -INFINITY;
     }
-    float l = -INFINITY;
-    ph = 0;
-    for (int e = 0; e < L; e++) {
-      const int y = y0 - R + e;
-      float v = (y >= 0 && y < H) ? fval(rowmax[(int64_t)y * W + x]) : -INFINITY;
-      l = (ph == 0) ? v : fmaxf(l, v);
-      ph = ph == Wd - 1 ? 0 : ph + 1;
-      if (e >= 2 * R) {
-        const int i = e - 2 * R;
-        const float mx = fmaxf(srb[i][lane], l);
-        const float fv = fval(f[(int64_t)(y0 + i) * pitch + x]);
-        const double d = (double)mx - (double)fv;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int idx = base + u * 256 + tid;
+      if (idx < L * kColW) tile[(idx >> 4) * kColStride + (idx & 15)] = vb[u];
+    }
+  }
+  {
+    float vb[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int idx = u * 256 + tid;
+      const int i = idx >> 4, x = x0 + (idx & 15);
+      vb[u] = (i < nb && x < W) ? fval(f[(int64_t)(y0 + i) * pitch + x]) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int idx = u * 256 + tid;
+      fb[(idx >> 4) * kColStride + (idx & 15)] = vb[u];
+    }
+  }
+  __syncthreads();
+  const int Wd = 2 * R + 1;
+  const float inv = 1.0f / (float)Wd;
+  const int c0 = wv * 4;
+  // right running maxima for e < nb (bottom-up tiles), four columns at once
+  float carry[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int e0 = ((L - 1) / 64) * 64; e0 >= 0; e0 -= 64) {
+    const int e = e0 + lane;
+    const int sege = e - mod_small(e, Wd, inv) + Wd - 1;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      float v = e < L ? tile[e * kColStride + c0 + k] : -INFINITY;
+      v = seg_max_down(v, e, sege, lane);
+      if (e0 + 64 <= sege) v = fmaxf(v, carry[k]);
+      carry[k] = lane_value(v, 0);
+      if (e < nb) rr[wv][k][e] = v;
+    }
+  }
+  // left running maxima (top-down); output row i has window e in [i, i+2R]
+  double tmax = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) carry[k] = -INFINITY;
+  for (int e0 = 0; e0 < L; e0 += 64) {
+    const int e = e0 + lane;
+    const int segs = e - mod_small(e, Wd, inv);
+    const int i = e - 2 * R;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      float v = e < L ? tile[e * kColStride + c0 + k] : -INFINITY;
+      v = seg_max_up(v, e, segs, lane);
+      if (e0 > 0 && e0 - 1 >= segs) v = fmaxf(v, carry[k]);
+      carry[k] = lane_value(v, 63);
+      if (i >= 0 && i < nb && x0 + c0 + k < W) {
+        const double d = (double)fmaxf(rr[wv][k][i], v) - (double)fb[i * kColStride + c0 + k];
         tmax = d > tmax ? d : tmax;
       }
     }
@@ -273,13 +404,78 @@ __global__ __launch_bounds__(64) void k_colmax_T(const Tin *__restrict__ f, int6
     double o = __shfl_xor(tmax, off, 64);
     tmax = o > tmax ? o : tmax;
   }
-  if (lane == 0) {
-    double tc = ceil(tmax);
-    int ti = tc > 2147483647.0 ? 2147483647 : (int)tc;
-    atomicMax(st.T_used, ti);
-    atomicMax(st.T_raw, (unsigned long long)__double_as_longlong(tmax));
-    if (ti > T_cap) atomicOr(st.flags, 2);
+  __shared__ double wmax[4];
+  if (lane == 0) wmax[wv] = tmax;
+  __syncthreads();
+  if (tid == 0) publish_T(st, fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3])), T_cap);
+}
+
+// Same column pass for windows too tall for the LDS tile: one lane per column
+// walks the band (plus halo) bottom-up for the right running maxima and
+// top-down for the left ones, loading 16 rows ahead.
+constexpr int kColBandSeq = 128;
+
+template <typename Tin>
+__global__ __launch_bounds__(64) void k_colmax_T_seq(const Tin *__restrict__ f, int64_t pitch,
+                                                     const Tin *__restrict__ rowmax, int H, int W, int R,
+                                                     DevState st, int32_t T_cap) {
+  __shared__ float srb[kColBandSeq][64];
+  const int lane = threadIdx.x;
+  const int x = blockIdx.x * 64 + lane;
+  const int y0 = blockIdx.y * kColBandSeq;
+  const int nb = min(kColBandSeq, H - y0);
+  const int L = nb + 2 * R;
+  const int Wd = 2 * R + 1;
+  double tmax = 0.0;
+  if (x < W) {
+    float r = -INFINITY;
+    int ph = (L - 1) % Wd;
+    for (int eb = L - 1; eb >= 0; eb -= 16) {
+      float vb[16];
+#pragma unroll
+      for (int u = 0; u < 16; u++) {
+        const int y = y0 - R + eb - u;
+        vb[u] = (eb - u >= 0 && y >= 0 && y < H) ? fval(rowmax[(int64_t)y * W + x]) : -INFINITY;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; u++) {
+        const int e = eb - u;
+        if (e < 0) break;
+        r = (ph == Wd - 1) ? vb[u] : fmaxf(r, vb[u]);
+        if (e < nb) srb[e][lane] = r;
+        ph = ph == 0 ? Wd - 1 : ph - 1;
+      }
+    }
+    float l = -INFINITY;
+    ph = 0;
+    for (int eb = 0; eb < L; eb += 16) {
+      float vb[16];
+#pragma unroll
+      for (int u = 0; u < 16; u++) {
+        const int y = y0 - R + eb + u;
+        vb[u] = (eb + u < L && y >= 0 && y < H) ? fval(rowmax[(int64_t)y * W + x]) : -INFINITY;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; u++) {
+        const int e = eb + u;
+        if (e >= L) break;
+        l = (ph == 0) ? vb[u] : fmaxf(l, vb[u]);
+        ph = ph == Wd - 1 ? 0 : ph + 1;
+        if (e >= 2 * R) {
+          const int i = e - 2 * R;
+          const float mx = fmaxf(srb[i][lane], l);
+          const double d = (double)mx - (double)fval(f[(int64_t)(y0 + i) * pitch + x]);
+          tmax = d > tmax ? d : tmax;
+        }
+      }
+    }
   }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_xor(tmax, off, 64);
+    tmax = o > tmax ? o : tmax;
+  }
+  if (lane == 0) publish_T(st, tmax, T_cap);
 }
 
 // --------------------------------------------- blocked recursive Gaussian
@@ -292,8 +488,8 @@ __global__ __launch_bounds__(64) void k_colmax_T(const Tin *__restrict__ f, int6
 // each chunk from its true states and writes the smoothed images.
 //
 // Positions p index the padded row in an interleaved order: p -> column
-// x = (p mod S) * kC + p / S, so that the horizontal pass, where thread t owns
-// columns [t kC, t kC + kC), reads consecutive addresses.
+// x = (p mod S) * c + p / S, so that the horizontal pass, where thread t owns
+// columns [t c, t c + c), reads consecutive addresses.
 
 template <typename Tin>
 __global__ __launch_bounds__(kVThreads) void k_iir_v_summary(const Tin *__restrict__ f, Geom g,
@@ -306,7 +502,7 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_summary(const Tin *__restri
   const OrderEntry &e = lookup(tab, st.T_used);
   const int k = k0 + kl;
   if (k >= e.K || p >= g.Spos) return;
-  const int x = (p & (g.S - 1)) * kC + (p >> g.logS);
+  const int x = (p & (g.S - 1)) * g.cC + (p >> g.logS);
   if (x >= g.W) return;
   const int32_t m = tab.pm[e.off + k];
   const uint64_t q = e.qfix;
@@ -316,10 +512,13 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_summary(const Tin *__restri
   float4 a0 = f4(0.f), a1 = f4(0.f), a2 = f4(0.f), b0 = f4(0.f), b1 = f4(0.f), b2 = f4(0.f);
   const int y0 = j * kB;
   const int n = min(kB, g.H - y0);
-#pragma unroll 4
-  for (int i = 0; i < n; i++) {
-    const Tin v = f[(int64_t)(y0 + i) * g.pitch + x];
-    const float4 xv = planes<Tin>(v, m, q, at, g.center);
+  Tin fv[kB];
+#pragma unroll
+  for (int i = 0; i < kB; i++) fv[i] = f[(int64_t)(y0 + min(i, n - 1)) * g.pitch + x];
+#pragma unroll
+  for (int i = 0; i < kB; i++) {
+    // rows past the image contribute nothing (zero input)
+    const float4 xv = i < n ? planes<Tin>(fv[i], m, q, at, g.center) : f4(0.f);
     a0 = fma4(Ap[0 * kB + i], xv, a0);
     a1 = fma4(Ap[1 * kB + i], xv, a1);
     a2 = fma4(Ap[2 * kB + i], xv, a2);
@@ -344,41 +543,60 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_fixup(Geom g, DevTables tab
   const OrderEntry &e = lookup(tab, st.T_used);
   const int k = k0 + kl;
   if (k >= e.K || p >= g.Spos) return;
-  const int x = (p & (g.S - 1)) * kC + (p >> g.logS);
+  const int x = (p & (g.S - 1)) * g.cC + (p >> g.logS);
   if (x >= g.W) return;
   const float *Phi = iir + kIirPhiFull;
   const float *Cm = iir + kIirCmFull;
   const float *Mts = iir + kIirMts;
+  constexpr int U = 8;  // chunks whose summaries are loaded ahead
   float4 P[3] = {f4(0.f), f4(0.f), f4(0.f)};
-  for (int j = 0; j < g.nc; j++) {
-    const size_t base = ((size_t)kl * g.nc + j) * 6;
-    float4 pb[3];
+  for (int j0 = 0; j0 < g.nc; j0 += U) {
+    float4 pb[U][3];
 #pragma unroll
-    for (int r = 0; r < 3; r++) pb[r] = cb[(base + r) * g.Spos + p];
+    for (int u = 0; u < U; u++)
+      if (j0 + u < g.nc) {
+        const size_t base = ((size_t)kl * g.nc + j0 + u) * 6;
 #pragma unroll
-    for (int r = 0; r < 3; r++) cb[(base + r) * g.Spos + p] = P[r];  // causal state entering j
-    float4 np[3];
-    matvec3(Phi, P, np);
+        for (int r = 0; r < 3; r++) pb[u][r] = cb[(base + r) * g.Spos + p];
+      }
 #pragma unroll
-    for (int r = 0; r < 3; r++) P[r] = add4(pb[r], np[r]);
+    for (int u = 0; u < U; u++)
+      if (j0 + u < g.nc) {
+        const size_t base = ((size_t)kl * g.nc + j0 + u) * 6;
+#pragma unroll
+        for (int r = 0; r < 3; r++) cb[(base + r) * g.Spos + p] = P[r];  // causal state entering the chunk
+        float4 np[3];
+        matvec3(Phi, P, np);
+#pragma unroll
+        for (int r = 0; r < 3; r++) P[r] = add4(pb[u][r], np[r]);
+      }
   }
   float4 E[3];
   matvec3(Mts, P, E);  // zero extension below the padded column
-  for (int j = g.nc - 1; j >= 0; j--) {
-    const size_t base = ((size_t)kl * g.nc + j) * 6;
-    float4 eb[3], pin[3];
+  for (int j0 = g.nc - 1; j0 >= 0; j0 -= U) {
+    float4 eb[U][3], pin[U][3];
 #pragma unroll
-    for (int r = 0; r < 3; r++) {
-      eb[r] = cb[(base + 3 + r) * g.Spos + p];
-      pin[r] = cb[(base + r) * g.Spos + p];
-    }
+    for (int u = 0; u < U; u++)
+      if (j0 - u >= 0) {
+        const size_t base = ((size_t)kl * g.nc + j0 - u) * 6;
 #pragma unroll
-    for (int r = 0; r < 3; r++) cb[(base + 3 + r) * g.Spos + p] = E[r];  // anticausal state entering j
-    float4 t1[3];
-    matvec3(Phi, E, t1);
-    matvec3_acc(Cm, pin, t1);
+        for (int r = 0; r < 3; r++) {
+          eb[u][r] = cb[(base + 3 + r) * g.Spos + p];
+          pin[u][r] = cb[(base + r) * g.Spos + p];
+        }
+      }
 #pragma unroll
-    for (int r = 0; r < 3; r++) E[r] = add4(eb[r], t1[r]);
+    for (int u = 0; u < U; u++)
+      if (j0 - u >= 0) {
+        const size_t base = ((size_t)kl * g.nc + j0 - u) * 6;
+#pragma unroll
+        for (int r = 0; r < 3; r++) cb[(base + 3 + r) * g.Spos + p] = E[r];  // anticausal state entering it
+        float4 t1[3];
+        matvec3(Phi, E, t1);
+        matvec3_acc(Cm, pin[u], t1);
+#pragma unroll
+        for (int r = 0; r < 3; r++) E[r] = add4(eb[u][r], t1[r]);
+      }
   }
 }
 
@@ -394,7 +612,7 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_final(const Tin *__restrict
   const OrderEntry &e = lookup(tab, st.T_used);
   const int k = k0 + kl;
   if (k >= e.K || p >= g.Spos) return;
-  const int x = (p & (g.S - 1)) * kC + (p >> g.logS);
+  const int x = (p & (g.S - 1)) * g.cC + (p >> g.logS);
   const int y0 = j * kB;
   float4 *Zk = Z + (size_t)kl * g.H * g.Spos;
   if (x >= g.W) {  // padding columns of the horizontal pass hold zeros
@@ -410,12 +628,15 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_final(const Tin *__restrict
   float4 s = cb[(base + 0) * g.Spos + p];
   float4 w = cb[(base + 1) * g.Spos + p];
   float4 d = cb[(base + 2) * g.Spos + p];
+  const int n = min(kB, g.H - y0);
+  Tin fv[kB];
+#pragma unroll
+  for (int i = 0; i < kB; i++) fv[i] = f[(int64_t)(y0 + min(i, n - 1)) * g.pitch + x];
   float4 wv[kB];
 #pragma unroll
   for (int i = 0; i < kB; i++) {
-    const int y = y0 + i;
     float4 xv = f4(0.f);
-    if (y < g.H) xv = planes<Tin>(f[(int64_t)y * g.pitch + x], m, q, at, g.center);
+    if (i < n) xv = planes<Tin>(fv[i], m, q, at, g.center);
     casc_step(g1, g2, c2, xv, s, w, d);
     wv[i] = w;
   }
@@ -462,7 +683,7 @@ __device__ __forceinline__ void scan_down(float4 v[3], const float *__restrict__
   }
 }
 
-template <typename Tin, int S>
+template <typename Tin, int S, int kC>
 __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict__ f,
                                                            float *__restrict__ out, Geom g,
                                                            DevTables tab, DevState st,
@@ -474,7 +695,9 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
   constexpr int SW = S < 64 ? S : 64;
   constexpr int NW = S > 64 ? S / 64 : 1;
   constexpr int PAD = S * (kC + 1);  // LDS row of one group, one slot skipped per kC
-  __shared__ float sred[2][NG * PAD];
+  // (P, Q) per group and pixel; slot (grp, t, i) belongs to one thread until the
+  // groups are summed at the end
+  __shared__ float2 spq[NG * PAD];
   __shared__ float4 xw[NG][NW][3];
   const int y = blockIdx.x;
   const int tid = threadIdx.x;
@@ -486,13 +709,19 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
   const int kend = min(k0 + kcount, e.K);
   const int niter = kend > k0 ? (kend - k0 + NG - 1) / NG : 0;
   const float g1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
-  const float *Apow = iir + kIirApow;
-  const float *scanM = iir + kIirScan;
+  const float *hb = iir + (kC == kCSmall ? kIirHSmall : kIirHLarge);
+  const float *Apow = hb + iir_h_apow(kC);
+  const float *scanM = hb + iir_h_scan(kC);
+  const float *laneM = hb + iir_h_lane(kC);
+  const float *waveM = hb + iir_h_wave(kC);
   const Tin *frow = f + (int64_t)y * g.pitch;
   const int x0 = t * kC;
-  float Pa[kC], Qa[kC];
+  float2 *mypq = spq + grp * PAD + t * (kC + 1);
 #pragma unroll
-  for (int i = 0; i < kC; i++) { Pa[i] = 0.f; Qa[i] = 0.f; }
+  for (int i = 0; i < kC; i++) mypq[i] = make_float2(0.f, 0.f);
+  Tin fv[kC];
+#pragma unroll
+  for (int i = 0; i < kC; i++) fv[i] = frow[min(x0 + i, g.W - 1)];
 
   for (int it = 0; it < niter; it++) {
     const int kl = it * NG + grp;
@@ -525,13 +754,13 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
       float4 Kc[3] = {f4(0.f), f4(0.f), f4(0.f)};
       for (int w = 0; w < wig; w++) {
         float4 tk[3];
-        matvec3(iir + kIirWave, Kc, tk);
+        matvec3(waveM, Kc, tk);
 #pragma unroll
         for (int r = 0; r < 3; r++) Kc[r] = add4(xw[grp][w][r], tk[r]);
       }
       __syncthreads();
-      matvec3_acc(iir + kIirLane + 9 * ls, Kc, exc);
-      if (t == S - 1) matvec3_acc(iir + kIirWave, Kc, inc);
+      matvec3_acc(laneM + 9 * ls, Kc, exc);
+      if (t == S - 1) matvec3_acc(waveM, Kc, inc);
     }
     // true causal outputs
 #pragma unroll
@@ -566,12 +795,12 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
       float4 Kc[3] = {f4(0.f), f4(0.f), f4(0.f)};
       for (int w = NW - 1; w > wig; w--) {
         float4 tk[3];
-        matvec3(iir + kIirWave, Kc, tk);
+        matvec3(waveM, Kc, tk);
 #pragma unroll
         for (int r = 0; r < 3; r++) Kc[r] = add4(xw[grp][w][r], tk[r]);
       }
       __syncthreads();
-      matvec3_acc(iir + kIirLane + 9 * (63 - ls), Kc, ein);
+      matvec3_acc(laneM + 9 * (63 - ls), Kc, ein);
     }
     if (t == S - 1) {
 #pragma unroll
@@ -591,19 +820,16 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
         const int x = x0 + i;
         if (x < g.W) {
           float c, sn;
-          turn_sincos(phase_turn<Tin>(m, frow[x], q, at), c, sn);
-          Pa[i] = fmaf(cp, fmaf(c, zv[i].x, sn * zv[i].y), Pa[i]);
-          Qa[i] = fmaf(cp, fmaf(c, zv[i].z, sn * zv[i].w), Qa[i]);
+          turn_sincos(phase_turn<Tin>(m, fv[i], q, at), c, sn);
+          float2 pq = mypq[i];
+          pq.x = fmaf(cp, fmaf(c, zv[i].x, sn * zv[i].y), pq.x);
+          pq.y = fmaf(cp, fmaf(c, zv[i].z, sn * zv[i].w), pq.y);
+          mypq[i] = pq;
         }
       }
     }
   }
   // sum the groups in a fixed order
-#pragma unroll
-  for (int i = 0; i < kC; i++) {
-    sred[0][grp * PAD + t * (kC + 1) + i] = Pa[i];
-    sred[1][grp * PAD + t * (kC + 1) + i] = Qa[i];
-  }
   __syncthreads();
   unsigned long long nbad = 0;
   for (int x = tid; x < g.W; x += kHThreads) {
@@ -611,8 +837,9 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
     float P = 0.f, Q = 0.f;
 #pragma unroll
     for (int gg = 0; gg < NG; gg++) {
-      P += sred[0][gg * PAD + o];
-      Q += sred[1][gg * PAD + o];
+      const float2 pq = spq[gg * PAD + o];
+      P += pq.x;
+      Q += pq.y;
     }
     const size_t pix = (size_t)y * g.W + x;
     if (!first) {
@@ -652,9 +879,15 @@ static hipError_t range_t(hipStream_t s, const Tin *f, const Geom &g, int R, Tin
   rec.begin(BF_STAGE_RANGE, s);
   dim3 gr((g.W + kRowSeg - 1) / kRowSeg, g.H);
   hipLaunchKernelGGL(k_rowmax<Tin>, gr, dim3(64), 0, s, f, g.pitch, g.H, g.W, R, rowmax, st);
-  dim3 gc((g.W + 63) / 64, (g.H + kColBand - 1) / kColBand);
-  hipLaunchKernelGGL(k_colmax_T<Tin>, gc, dim3(64), 0, s, f, g.pitch, (const Tin *)rowmax, g.H, g.W, R,
-                     st, T_cap);
+  if (R <= kColMaxR) {
+    dim3 gc((g.W + kColW - 1) / kColW, (g.H + kColBand - 1) / kColBand);
+    hipLaunchKernelGGL(k_colmax_T<Tin>, gc, dim3(256), 0, s, f, g.pitch, (const Tin *)rowmax, g.H, g.W, R,
+                       st, T_cap);
+  } else {
+    dim3 gc((g.W + 63) / 64, (g.H + kColBandSeq - 1) / kColBandSeq);
+    hipLaunchKernelGGL(k_colmax_T_seq<Tin>, gc, dim3(64), 0, s, f, g.pitch, (const Tin *)rowmax, g.H, g.W,
+                       R, st, T_cap);
+  }
   rec.end(BF_STAGE_RANGE, s);
   return hipGetLastError();
 }
@@ -669,12 +902,30 @@ hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g
   }
 }
 
-template <typename Tin, int S>
+template <typename Tin, int S, int C>
 static void launch_h(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab, DevState st,
                      const float *iir, int k0, int kcount, const float4 *Z, float2 *PQ, bool first,
                      bool last) {
-  hipLaunchKernelGGL((k_iir_h_accum<Tin, S>), dim3(g.H), dim3(kHThreads), 0, s, f, out, g, tab, st, iir,
+  hipLaunchKernelGGL((k_iir_h_accum<Tin, S, C>), dim3(g.H), dim3(kHThreads), 0, s, f, out, g, tab, st, iir,
                      k0, kcount, Z, PQ, (int)first, (int)last);
+}
+
+template <typename Tin, int C>
+static bool launch_h_S(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab, DevState st,
+                       const float *iir, int k0, int kcount, const float4 *Z, float2 *PQ, bool first,
+                       bool last) {
+  switch (g.S) {
+    case 1: launch_h<Tin, 1, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
+    case 2: launch_h<Tin, 2, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
+    case 4: launch_h<Tin, 4, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
+    case 8: launch_h<Tin, 8, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
+    case 16: launch_h<Tin, 16, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
+    case 32: launch_h<Tin, 32, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
+    case 64: launch_h<Tin, 64, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
+    case 128: launch_h<Tin, 128, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
+    case 256: launch_h<Tin, 256, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
+    default: return false;
+  }
 }
 
 template <typename Tin>
@@ -696,18 +947,10 @@ static hipError_t iir_chunk_t(hipStream_t s, const Tin *f, float *out, const Geo
     rec.end(BF_STAGE_V_FINAL, s);
   }
   rec.begin(BF_STAGE_H_COMBINE, s);
-  switch (g.S) {
-    case 1: launch_h<Tin, 1>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
-    case 2: launch_h<Tin, 2>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
-    case 4: launch_h<Tin, 4>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
-    case 8: launch_h<Tin, 8>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
-    case 16: launch_h<Tin, 16>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
-    case 32: launch_h<Tin, 32>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
-    case 64: launch_h<Tin, 64>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
-    case 128: launch_h<Tin, 128>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
-    case 256: launch_h<Tin, 256>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); break;
-    default: return hipErrorInvalidValue;
-  }
+  const bool ok = g.cC == kCSmall
+                      ? launch_h_S<Tin, kCSmall>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last)
+                      : launch_h_S<Tin, kCLarge>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last);
+  if (!ok) return hipErrorInvalidValue;
   rec.end(BF_STAGE_H_COMBINE, s);
   return hipGetLastError();
 }

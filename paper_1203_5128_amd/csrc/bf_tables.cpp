@@ -221,11 +221,14 @@ bool build_iir_consts(double sigma_s, std::vector<float> &out, std::string &err)
   }
   put(out, kIirMts, mts);
   chunk_mats(cs, kB, out, kIirApFull, kIirAeFull, kIirPhiFull, kIirCmFull, A);
-  for (int v = 0; v <= kC; v++) put(out, kIirApow + 9 * v, mpow(A, v));
-  M3 Ac = mpow(A, kC);
-  for (int l = 0; l < 64; l++) put(out, kIirLane + 9 * l, mpow(Ac, l));
-  for (int k = 0; k < 8; k++) put(out, kIirScan + 9 * k, mpow(Ac, 1L << k));
-  put(out, kIirWave, mpow(Ac, 64));
+  for (int c : {kCSmall, kCLarge}) {
+    const int hb = c == kCSmall ? kIirHSmall : kIirHLarge;
+    for (int v = 0; v <= c; v++) put(out, hb + iir_h_apow(c) + 9 * v, mpow(A, v));
+    M3 Ac = mpow(A, c);
+    for (int l = 0; l < 64; l++) put(out, hb + iir_h_lane(c) + 9 * l, mpow(Ac, l));
+    for (int k = 0; k < 8; k++) put(out, hb + iir_h_scan(c) + 9 * k, mpow(Ac, 1L << k));
+    put(out, hb + iir_h_wave(c), mpow(Ac, 64));
+  }
   return true;
 }
 

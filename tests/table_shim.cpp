@@ -27,10 +27,12 @@ int shim_iir_consts(double sigma, float *out, int n) {
   std::memcpy(out, v.data(), sizeof(float) * (n < (int)v.size() ? n : (int)v.size()));
   return (int)v.size();
 }
-int shim_layout(int *o) {
+int shim_layout(int c, int *o) {
+  const int hb = c == bfi::kCSmall ? bfi::kIirHSmall : bfi::kIirHLarge;
   o[0] = bfi::kIirCoef; o[1] = bfi::kIirMts; o[2] = bfi::kIirApFull; o[3] = bfi::kIirAeFull;
-  o[4] = bfi::kIirPhiFull; o[5] = bfi::kIirCmFull; o[6] = bfi::kIirApow; o[7] = bfi::kIirSize;
-  o[8] = bfi::kB; o[9] = bfi::kC;
+  o[4] = bfi::kIirPhiFull; o[5] = bfi::kIirCmFull; o[6] = hb + bfi::iir_h_apow(c); o[7] = bfi::kIirSize;
+  o[8] = bfi::kB; o[9] = c; o[10] = hb + bfi::iir_h_lane(c); o[11] = hb + bfi::iir_h_scan(c);
+  o[12] = hb + bfi::iir_h_wave(c);
   return 0;
 }
 }

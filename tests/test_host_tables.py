@@ -32,7 +32,7 @@ def shim():
     L.shim_table_entry.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int, P, P, P, P, P, P, P, ctypes.c_int]
     L.shim_iir_consts.argtypes = [ctypes.c_double, P, ctypes.c_int]
-    L.shim_layout.argtypes = [P]
+    L.shim_layout.argtypes = [ctypes.c_int, P]
     return L
 
 
@@ -90,30 +90,27 @@ def test_pairs_match_expansion(shim, sr, eps, rng_, T):
 
 
 # ------------------------------------------------------------------ IIR model
-def consts(L, sigma):
-    buf = (ctypes.c_float * 8192)()
-    n = L.shim_iir_consts(sigma, buf, 8192)
-    assert n > 0
-    lay = (ctypes.c_int * 10)()
-    L.shim_layout(lay)
-    names = ["coef", "mts", "ap", "ae", "phi", "cm", "apow", "size", "kB", "kC"]
+def consts(L, sigma, c=32):
+    buf = (ctypes.c_float * 16384)()
+    n = L.shim_iir_consts(sigma, buf, 16384)
+    assert 0 < n <= 16384
+    lay = (ctypes.c_int * 13)()
+    L.shim_layout(c, lay)
+    names = ["coef", "mts", "ap", "ae", "phi", "cm", "apow", "size", "kB", "kC", "lane", "scan", "wave"]
     lay = dict(zip(names, list(lay)))
+    assert n == lay["size"]
     C = np.array(buf[:n], dtype=np.float64)
     kB, kC = lay["kB"], lay["kC"]
-    d = dict(g1=C[0], g2=C[1], c2=C[2], kB=kB, kC=kC,
-             mts=C[lay["mts"]:lay["mts"] + 9].reshape(3, 3),
-             ap=C[lay["ap"]:lay["ap"] + 3 * kB].reshape(3, kB),
-             ae=C[lay["ae"]:lay["ae"] + 3 * kB].reshape(3, kB),
-             phi=C[lay["phi"]:lay["phi"] + 9].reshape(3, 3),
-             cm=C[lay["cm"]:lay["cm"] + 9].reshape(3, 3),
-             apow=C[lay["apow"]:lay["apow"] + 9 * (kC + 1)].reshape(kC + 1, 3, 3))
-    off = lay["apow"] + 9 * (kC + 1)
-    d["lane"] = C[off:off + 9 * 64].reshape(64, 3, 3)
-    off += 9 * 64
-    d["scan"] = C[off:off + 9 * 8].reshape(8, 3, 3)
-    off += 9 * 8
-    d["wave"] = C[off:off + 9].reshape(3, 3)
-    return d
+    return dict(g1=C[0], g2=C[1], c2=C[2], kB=kB, kC=kC,
+                mts=C[lay["mts"]:lay["mts"] + 9].reshape(3, 3),
+                ap=C[lay["ap"]:lay["ap"] + 3 * kB].reshape(3, kB),
+                ae=C[lay["ae"]:lay["ae"] + 3 * kB].reshape(3, kB),
+                phi=C[lay["phi"]:lay["phi"] + 9].reshape(3, 3),
+                cm=C[lay["cm"]:lay["cm"] + 9].reshape(3, 3),
+                apow=C[lay["apow"]:lay["apow"] + 9 * (kC + 1)].reshape(kC + 1, 3, 3),
+                lane=C[lay["lane"]:lay["lane"] + 9 * 64].reshape(64, 3, 3),
+                scan=C[lay["scan"]:lay["scan"] + 9 * 8].reshape(8, 3, 3),
+                wave=C[lay["wave"]:lay["wave"] + 9].reshape(3, 3))
 
 
 def _sweep(x, st, g1, g2, c2, rev=False):
@@ -245,10 +242,11 @@ def test_blocked_vertical_model_matches_oracle(shim, sigma, n):
     assert np.abs(got - ref).max() < 2e-5 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("c", [16, 32])
 @pytest.mark.parametrize("sigma", [0.7, 3.0, 10.0, 16.0])
 @pytest.mark.parametrize("n", [1, 7, 32, 33, 200, 512, 1000, 2049, 4096])
-def test_blocked_horizontal_model_matches_oracle(shim, sigma, n):
-    C = consts(shim, sigma)
+def test_blocked_horizontal_model_matches_oracle(shim, c, sigma, n):
+    C = consts(shim, sigma, c)
     rng = np.random.default_rng(1000 + n)
     x = rng.uniform(-1, 1, n)
     ref = o.blur_1d(x, "iir", sigma)
