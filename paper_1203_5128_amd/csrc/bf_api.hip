@@ -65,7 +65,8 @@ struct bf_plan_s {
   float4 *d_cb = nullptr;
   float4 *d_Z = nullptr;
   float2 *d_PQ = nullptr;
-  size_t rowmax_bytes = 0, cb_bytes = 0, Z_bytes = 0, PQ_bytes = 0;
+  float2 *d_lut = nullptr;  // cos/sin tables of the pairs in flight (8-bit inputs)
+  size_t rowmax_bytes = 0, cb_bytes = 0, Z_bytes = 0, PQ_bytes = 0, lut_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // stage timing (bf_profile)
   bool prof = false;
@@ -76,6 +77,11 @@ struct bf_plan_s {
   double prof_ms[BF_STAGE_COUNT] = {};
   int64_t prof_n[BF_STAGE_COUNT] = {};
   StageRec rec;
+  // graphs of the launch sequence, keyed by the image pointers they bake in
+  struct GraphEntry { int img; const void *in; float *out; hipGraphExec_t exec; };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_stream = nullptr;  // private stream used only for capture
+  bool use_graph = true;
 };
 
 namespace {
@@ -241,6 +247,45 @@ void stage_mark(void *ctx, int stage, hipStream_t s, bool end) {
   pl->pending.push_back({stage, a, b});
 }
 
+bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out, hipStream_t s);
+
+// Launch image img through a captured graph of its kernel sequence.  The
+// graph is captured once per (image, input, output) on a private stream and
+// replayed on the caller's stream; the sequence has kernels only.
+bf_status run_image_graph(bf_plan_s *pl, int img, const void *d_in, float *d_out, hipStream_t s) {
+  for (auto &g : pl->graphs)
+    if (g.img == img && g.in == d_in && g.out == d_out) {
+      hipError_t e = hipGraphLaunch(g.exec, s);
+      return e == hipSuccess ? BF_OK : dev_fail(e, "hipGraphLaunch");
+    }
+  hipError_t e;
+  if (!pl->cap_stream) {
+    e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return dev_fail(e, "hipStreamCreate");
+  }
+  e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return dev_fail(e, "hipStreamBeginCapture");
+  bf_status st = run_image(pl, pl->im[img], d_in, d_out, pl->cap_stream);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(pl->cap_stream, &graph);
+  if (st) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return dev_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return dev_fail(e, "hipGraphInstantiate");
+  if (pl->graphs.size() >= 16) {
+    (void)hipGraphExecDestroy(pl->graphs.front().exec);
+    pl->graphs.erase(pl->graphs.begin());
+  }
+  pl->graphs.push_back({img, d_in, d_out, exec});
+  e = hipGraphLaunch(exec, s);
+  return e == hipSuccess ? BF_OK : dev_fail(e, "hipGraphLaunch");
+}
+
 // Enqueue the whole of Algorithm 2 for one image.
 bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out, hipStream_t s) {
   const Geom &g = ip.g;
@@ -260,7 +305,7 @@ bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out
   for (int k0 = 0; k0 < Kmax; k0 += ip.KC) {
     const int kcount = std::min(ip.KC, Kmax - k0);
     e = launch_iir_chunk(s, ip.p.dtype, d_in, d_out, g, tab, st, ip.d_iir, k0, kcount, pl->d_cb, pl->d_Z,
-                         pl->d_PQ, k0 == 0, k0 + ip.KC >= Kmax, pl->rec);
+                         pl->d_PQ, k0 == 0, k0 + ip.KC >= Kmax, pl->d_lut, pl->rec);
     if (e != hipSuccess) return dev_fail(e, "blur");
   }
   return BF_OK;
@@ -325,7 +370,7 @@ bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out) {
   bf_plan_s *pl = new bf_plan_s();
   (void)hipGetDevice(&pl->device);
   pl->im.resize(n_images);
-  size_t rowmax = 0, cb = 0, Z = 0, PQ = 0;
+  size_t rowmax = 0, cb = 0, Z = 0, PQ = 0, lut = 0;
   for (int i = 0; i < n_images; i++) {
     bf_status s = prepare_image(params[i], pl->im[i]);
     if (s) {
@@ -338,13 +383,16 @@ bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out) {
     cb = std::max(cb, (size_t)ip.KC * g.nc * 6 * g.Spos * sizeof(float4));
     Z = std::max(Z, (size_t)ip.KC * g.H * g.Spos * sizeof(float4));
     PQ = std::max(PQ, (size_t)g.H * g.W * sizeof(float2));
+    lut = std::max(lut, (size_t)ip.KC * 256 * sizeof(float2));
   }
   bf_status s;
   if ((s = ensure(&pl->d_rowmax, pl->rowmax_bytes, rowmax)) || (s = ensure((void **)&pl->d_cb, pl->cb_bytes, cb)) ||
-      (s = ensure((void **)&pl->d_Z, pl->Z_bytes, Z)) || (s = ensure((void **)&pl->d_PQ, pl->PQ_bytes, PQ))) {
+      (s = ensure((void **)&pl->d_Z, pl->Z_bytes, Z)) || (s = ensure((void **)&pl->d_PQ, pl->PQ_bytes, PQ)) ||
+      (s = ensure((void **)&pl->d_lut, pl->lut_bytes, lut))) {
     bf_plan_destroy(pl);
     return s;
   }
+  if (const char *g = std::getenv("BF_GRAPH")) pl->use_graph = std::atoi(g) != 0;
   if (hipEventCreate(&pl->ev0) != hipSuccess || hipEventCreate(&pl->ev1) != hipSuccess) {
     bf_plan_destroy(pl);
     return fail(BF_ERR_DEVICE, "hipEventCreate");
@@ -390,6 +438,8 @@ void bf_plan_destroy(bf_plan_t pl) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : pl->ev_pool) (void)hipEventDestroy(e);
+  for (auto &g : pl->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
   for (auto e : pl->open_ev)
     if (e) (void)hipEventDestroy(e);
   for (auto &ip : pl->im) free_image(ip);
@@ -397,6 +447,7 @@ void bf_plan_destroy(bf_plan_t pl) {
   (void)hipFree(pl->d_cb);
   (void)hipFree(pl->d_Z);
   (void)hipFree(pl->d_PQ);
+  (void)hipFree(pl->d_lut);
   if (pl->ev0) (void)hipEventDestroy(pl->ev0);
   if (pl->ev1) (void)hipEventDestroy(pl->ev1);
   delete pl;
@@ -407,7 +458,8 @@ bf_status bf_filter(bf_plan_t pl, const void *d_in, float *d_out, void *hip_stre
   hipStream_t s = (hipStream_t)hip_stream;
   ImagePlan &ip = pl->im[0];
   if (rep) (void)hipEventRecord(pl->ev0, s);
-  bf_status st = run_image(pl, ip, d_in, d_out, s);
+  bf_status st = (pl->use_graph && !pl->prof) ? run_image_graph(pl, 0, d_in, d_out, s)
+                                               : run_image(pl, ip, d_in, d_out, s);
   if (st) return st;
   if (!rep) return BF_OK;
   (void)hipEventRecord(pl->ev1, s);
@@ -427,7 +479,8 @@ bf_status bf_filter_batch(bf_plan_t pl, int32_t n, const void *const *d_in, floa
   hipStream_t s = (hipStream_t)hip_stream;
   if (reps) (void)hipEventRecord(pl->ev0, s);
   for (int i = 0; i < n; i++) {
-    bf_status st = run_image(pl, pl->im[i], d_in[i], d_out[i], s);
+    bf_status st = (pl->use_graph && !pl->prof) ? run_image_graph(pl, i, d_in[i], d_out[i], s)
+                                                 : run_image(pl, pl->im[i], d_in[i], d_out[i], s);
     if (st) return st;
   }
   if (!reps) return BF_OK;

@@ -54,6 +54,6 @@ hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g
 hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *out, const Geom &g,
                             DevTables tab, DevState st, const float *iir, int k0, int kcount,
                             float4 *cb, float4 *Z, float2 *PQ, bool first, bool last,
-                            const StageRec &rec);
+                            float2 *glut, const StageRec &rec);
 
 }  // namespace bfi

@@ -190,6 +190,20 @@ __device__ __forceinline__ void turn_sincos(uint32_t tau, float &c, float &s) {
   s = ss;
 }
 
+// 8-bit images: cos and sin of one frequency for all 256 intensities, built
+// once per workgroup in LDS (one sincos per thread) instead of once per pixel.
+template <typename Tin>
+struct PhaseLut {
+  static constexpr bool kOn = sizeof(Tin) == 1;
+};
+__device__ __forceinline__ void build_lut(float2 *lut, int32_t m, uint64_t q, double at, int tid, int nthreads) {
+  for (int v = tid; v < 256; v += nthreads) {
+    float c, sn;
+    turn_sincos(phase_turn<uint8_t>(m, (uint8_t)v, q, at), c, sn);
+    lut[v] = make_float2(c, sn);
+  }
+}
+
 // The four images of one frequency at one pixel: (f-c) cos, (f-c) sin, cos, sin.
 template <typename Tin>
 __device__ __forceinline__ float4 planes(Tin v, int32_t m, uint64_t q, double at, float center) {
@@ -197,6 +211,18 @@ __device__ __forceinline__ float4 planes(Tin v, int32_t m, uint64_t q, double at
   turn_sincos(phase_turn<Tin>(m, v, q, at), c, s);
   float d = fval(v) - center;
   return make_float4(d * c, d * s, c, s);
+}
+// Same, reading cos/sin from the workgroup's table for 8-bit images.
+template <typename Tin>
+__device__ __forceinline__ float4 planes_any(Tin v, const float2 *lut, int32_t m, uint64_t q, double at,
+                                             float center) {
+  if constexpr (PhaseLut<Tin>::kOn) {
+    const float2 cs = lut[(int)v];
+    const float d = fval(v) - center;
+    return make_float4(d * cs.x, d * cs.y, cs.x, cs.y);
+  } else {
+    return planes<Tin>(v, m, q, at, center);
+  }
 }
 
 // Publish a non-negative dynamic-range candidate.  Many workgroups race for
@@ -501,12 +527,18 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_summary(const Tin *__restri
   const int kl = blockIdx.z;
   const OrderEntry &e = lookup(tab, st.T_used);
   const int k = k0 + kl;
-  if (k >= e.K || p >= g.Spos) return;
-  const int x = (p & (g.S - 1)) * g.cC + (p >> g.logS);
-  if (x >= g.W) return;
+  if (k >= e.K) return;
   const int32_t m = tab.pm[e.off + k];
   const uint64_t q = e.qfix;
   const double at = e.alpha_turn;
+  __shared__ float2 lut[PhaseLut<Tin>::kOn ? 256 : 1];
+  if constexpr (PhaseLut<Tin>::kOn) {
+    build_lut(lut, m, q, at, threadIdx.x, kVThreads);
+    __syncthreads();
+  }
+  if (p >= g.Spos) return;
+  const int x = (p & (g.S - 1)) * g.cC + (p >> g.logS);
+  if (x >= g.W) return;
   const float *Ap = iir + kIirApFull;
   const float *Ae = iir + kIirAeFull;
   float4 a0 = f4(0.f), a1 = f4(0.f), a2 = f4(0.f), b0 = f4(0.f), b1 = f4(0.f), b2 = f4(0.f);
@@ -518,7 +550,7 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_summary(const Tin *__restri
 #pragma unroll
   for (int i = 0; i < kB; i++) {
     // rows past the image contribute nothing (zero input)
-    const float4 xv = i < n ? planes<Tin>(fv[i], m, q, at, g.center) : f4(0.f);
+    const float4 xv = i < n ? planes_any<Tin>(fv[i], lut, m, q, at, g.center) : f4(0.f);
     a0 = fma4(Ap[0 * kB + i], xv, a0);
     a1 = fma4(Ap[1 * kB + i], xv, a1);
     a2 = fma4(Ap[2 * kB + i], xv, a2);
@@ -605,13 +637,25 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_final(const Tin *__restrict
                                                            DevTables tab, DevState st,
                                                            const float *__restrict__ iir, int k0,
                                                            const float4 *__restrict__ cb,
-                                                           float4 *__restrict__ Z) {
+                                                           float4 *__restrict__ Z,
+                                                           float2 *__restrict__ glut) {
   const int p = blockIdx.x * kVThreads + threadIdx.x;
   const int j = blockIdx.y;
   const int kl = blockIdx.z;
   const OrderEntry &e = lookup(tab, st.T_used);
   const int k = k0 + kl;
-  if (k >= e.K || p >= g.Spos) return;
+  if (k >= e.K) return;
+  const int32_t m = tab.pm[e.off + k];
+  const uint64_t q = e.qfix;
+  const double at = e.alpha_turn;
+  __shared__ float2 lut[PhaseLut<Tin>::kOn ? 256 : 1];
+  if constexpr (PhaseLut<Tin>::kOn) {
+    build_lut(lut, m, q, at, threadIdx.x, kVThreads);
+    // one workgroup per pair also leaves the table for the horizontal pass
+    if (blockIdx.x == 0 && j == 0) glut[(size_t)kl * 256 + threadIdx.x] = lut[threadIdx.x];
+    __syncthreads();
+  }
+  if (p >= g.Spos) return;
   const int x = (p & (g.S - 1)) * g.cC + (p >> g.logS);
   const int y0 = j * kB;
   float4 *Zk = Z + (size_t)kl * g.H * g.Spos;
@@ -620,9 +664,6 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_final(const Tin *__restrict
       if (y0 + i < g.H) Zk[(size_t)(y0 + i) * g.Spos + p] = f4(0.f);
     return;
   }
-  const int32_t m = tab.pm[e.off + k];
-  const uint64_t q = e.qfix;
-  const double at = e.alpha_turn;
   const float g1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
   const size_t base = ((size_t)kl * g.nc + j) * 6;
   float4 s = cb[(base + 0) * g.Spos + p];
@@ -636,7 +677,7 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_final(const Tin *__restrict
 #pragma unroll
   for (int i = 0; i < kB; i++) {
     float4 xv = f4(0.f);
-    if (i < n) xv = planes<Tin>(fv[i], m, q, at, g.center);
+    if (i < n) xv = planes_any<Tin>(fv[i], lut, m, q, at, g.center);
     casc_step(g1, g2, c2, xv, s, w, d);
     wv[i] = w;
   }
@@ -690,7 +731,7 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
                                                            const float *__restrict__ iir, int k0,
                                                            int kcount, const float4 *__restrict__ Z,
                                                            float2 *__restrict__ PQ, int first,
-                                                           int last) {
+                                                           int last, const float2 *__restrict__ glut) {
   constexpr int NG = kHThreads / S;
   constexpr int SW = S < 64 ? S : 64;
   constexpr int NW = S > 64 ? S / 64 : 1;
@@ -815,12 +856,19 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
       const float cp = tab.pc[e.off + k];
       const uint64_t q = e.qfix;
       const double at = e.alpha_turn;
+      const float2 *lk = glut + (size_t)kl * 256;
 #pragma unroll
       for (int i = 0; i < kC; i++) {
         const int x = x0 + i;
         if (x < g.W) {
           float c, sn;
-          turn_sincos(phase_turn<Tin>(m, fv[i], q, at), c, sn);
+          if constexpr (PhaseLut<Tin>::kOn) {
+            const float2 cs = lk[(int)fv[i]];
+            c = cs.x;
+            sn = cs.y;
+          } else {
+            turn_sincos(phase_turn<Tin>(m, fv[i], q, at), c, sn);
+          }
           float2 pq = mypq[i];
           pq.x = fmaf(cp, fmaf(c, zv[i].x, sn * zv[i].y), pq.x);
           pq.y = fmaf(cp, fmaf(c, zv[i].z, sn * zv[i].w), pq.y);
@@ -905,25 +953,25 @@ hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g
 template <typename Tin, int S, int C>
 static void launch_h(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab, DevState st,
                      const float *iir, int k0, int kcount, const float4 *Z, float2 *PQ, bool first,
-                     bool last) {
+                     bool last, const float2 *glut) {
   hipLaunchKernelGGL((k_iir_h_accum<Tin, S, C>), dim3(g.H), dim3(kHThreads), 0, s, f, out, g, tab, st, iir,
-                     k0, kcount, Z, PQ, (int)first, (int)last);
+                     k0, kcount, Z, PQ, (int)first, (int)last, glut);
 }
 
 template <typename Tin, int C>
 static bool launch_h_S(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab, DevState st,
                        const float *iir, int k0, int kcount, const float4 *Z, float2 *PQ, bool first,
-                       bool last) {
+                       bool last, const float2 *glut) {
   switch (g.S) {
-    case 1: launch_h<Tin, 1, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
-    case 2: launch_h<Tin, 2, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
-    case 4: launch_h<Tin, 4, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
-    case 8: launch_h<Tin, 8, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
-    case 16: launch_h<Tin, 16, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
-    case 32: launch_h<Tin, 32, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
-    case 64: launch_h<Tin, 64, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
-    case 128: launch_h<Tin, 128, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
-    case 256: launch_h<Tin, 256, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last); return true;
+    case 1: launch_h<Tin, 1, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
+    case 2: launch_h<Tin, 2, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
+    case 4: launch_h<Tin, 4, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
+    case 8: launch_h<Tin, 8, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
+    case 16: launch_h<Tin, 16, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
+    case 32: launch_h<Tin, 32, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
+    case 64: launch_h<Tin, 64, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
+    case 128: launch_h<Tin, 128, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
+    case 256: launch_h<Tin, 256, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
     default: return false;
   }
 }
@@ -931,7 +979,7 @@ static bool launch_h_S(hipStream_t s, const Tin *f, float *out, const Geom &g, D
 template <typename Tin>
 static hipError_t iir_chunk_t(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab,
                               DevState st, const float *iir, int k0, int kcount, float4 *cb, float4 *Z,
-                              float2 *PQ, bool first, bool last, const StageRec &rec) {
+                              float2 *PQ, bool first, bool last, float2 *glut, const StageRec &rec) {
   const int nbx = (g.Spos + kVThreads - 1) / kVThreads;
   if (kcount > 0) {
     rec.begin(BF_STAGE_V_SUMMARY, s);
@@ -943,13 +991,13 @@ static hipError_t iir_chunk_t(hipStream_t s, const Tin *f, float *out, const Geo
     rec.end(BF_STAGE_V_CARRY, s);
     rec.begin(BF_STAGE_V_FINAL, s);
     hipLaunchKernelGGL(k_iir_v_final<Tin>, dim3(nbx, g.nc, kcount), dim3(kVThreads), 0, s, f, g, tab, st,
-                       iir, k0, (const float4 *)cb, Z);
+                       iir, k0, (const float4 *)cb, Z, glut);
     rec.end(BF_STAGE_V_FINAL, s);
   }
   rec.begin(BF_STAGE_H_COMBINE, s);
   const bool ok = g.cC == kCSmall
-                      ? launch_h_S<Tin, kCSmall>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last)
-                      : launch_h_S<Tin, kCLarge>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last);
+                      ? launch_h_S<Tin, kCSmall>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut)
+                      : launch_h_S<Tin, kCLarge>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut);
   if (!ok) return hipErrorInvalidValue;
   rec.end(BF_STAGE_H_COMBINE, s);
   return hipGetLastError();
@@ -957,17 +1005,17 @@ static hipError_t iir_chunk_t(hipStream_t s, const Tin *f, float *out, const Geo
 
 hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *out, const Geom &g,
                             DevTables tab, DevState st, const float *iir, int k0, int kcount, float4 *cb,
-                            float4 *Z, float2 *PQ, bool first, bool last, const StageRec &rec) {
+                            float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, const StageRec &rec) {
   switch (dt) {
     case BF_U8:
       return iir_chunk_t<uint8_t>(s, (const uint8_t *)f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, first,
-                                  last, rec);
+                                  last, glut, rec);
     case BF_U16:
       return iir_chunk_t<uint16_t>(s, (const uint16_t *)f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ,
-                                   first, last, rec);
+                                   first, last, glut, rec);
     default:
       return iir_chunk_t<float>(s, (const float *)f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, first,
-                                last, rec);
+                                last, glut, rec);
   }
 }
 

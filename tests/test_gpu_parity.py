@@ -209,3 +209,34 @@ def test_batch_uneven_sizes_per_image_params():
         err = np.abs(out.cpu().numpy().astype(np.float64) - ref["out"]).max()
         print(f"[parity] batch {im.shape} ss={ss:.2f} sr={sr:.2f} max={err:.3e}", flush=True)
         assert err <= TOL8
+
+
+def test_graph_replays_match_eager():
+    """The captured launch sequence, replayed with eager GPU work in between,
+    gives bit-identical output every time and equals the direct launches."""
+    import os
+    torch = _torch()
+    from paper_1203_5128_amd import Plan, make_params
+    img = gen_random(82, 140, 170, "u8")
+    t = torch.from_numpy(img).to("cuda")
+    plan = Plan.create(make_params(140, 170, "u8", sigma_s=4.0, sigma_r=15.0))
+    outs = []
+    out = torch.empty((140, 170), device="cuda")
+    for r in range(4):
+        plan.filter(t, out, report=False)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().clone())
+        junk = torch.randn(1 << 20, device="cuda")
+        (junk * 2).sum().item()
+    plan.close()
+    os.environ["BF_GRAPH"] = "0"
+    try:
+        plan2 = Plan.create(make_params(140, 170, "u8", sigma_s=4.0, sigma_r=15.0))
+        eager, _ = plan2.filter(t)
+        torch.cuda.synchronize()
+        plan2.close()
+    finally:
+        del os.environ["BF_GRAPH"]
+    for o in outs:
+        assert torch.equal(o, outs[0])
+    assert torch.equal(eager.cpu(), outs[0])
