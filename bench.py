@@ -42,6 +42,20 @@ def algorithmic_bytes(stage: str, H: int, W: int, pairs: int, b_in: int, kcount:
     return 0.0
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_grad512_u8.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    return rec["traffic_bytes"] if sha.startswith(rec["source_sha256_prefix"]) else None
+
+
 def cpu_baseline(img, c, budget_s=25.0):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
@@ -142,7 +156,8 @@ def main():
                               blur="iir_f32", T=rep["T"], N=rep["N"], M=rep["M"], pairs=pairs),
                   roofline=dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                                 unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                                avg_launch_ms=round(avg_ms, 5), bytes_per_launch=bytes_launch, traffic=None),
+                                avg_launch_ms=round(avg_ms, 5), bytes_per_launch=bytes_launch,
+                                traffic=measured_traffic(dom)),
                   stages=stages)
 
     # accuracy of the timed output against the FP64 oracle
