@@ -50,8 +50,37 @@ struct ImagePlan {
   int32_t *d_pm = nullptr;
   float *d_pc = nullptr;
   float *d_iir = nullptr;
+  float *d_taps = nullptr;  // Toeplitz path: FIR taps
+  ToepCfg tc{};
+  size_t z_per_pair = 0;    // workspace bytes of the smoothed images of one pair
   void *d_state = nullptr;  // T_used, flags, T_raw, q_nonpos
 };
+
+bool is_toeplitz(int v) { return v >= BF_BLUR_TOEPLITZ_F16 && v <= BF_BLUR_TOEPLITZ_BF16X2; }
+bool is_split(int v) { return v == BF_BLUR_TOEPLITZ_F16X2 || v == BF_BLUR_TOEPLITZ_BF16X2; }
+
+// Tile shape of the Toeplitz path for radius R: the tallest vertical tile
+// (fewest recomputed halo rows) whose LDS leaves room for two workgroups per
+// CU, else for one.  False when the band of 2R+1 taps does not fit.
+bool toeplitz_shape(int variant, int R, int H, ToepCfg &tc) {
+  tc.R = R;
+  tc.nks = (16 + 2 * R + 31) / 32;
+  if (tc.nks > 8) return false;
+  size_t pref = (size_t)kToepLdsMax / 2 - 2048;  // two workgroups per CU with their static tables
+  if (const char *b = std::getenv("BF_TOEP_LDS_KB")) pref = (size_t)std::atoi(b) << 10;
+  const int top = std::min(256, (H + 15) / 16 * 16);
+  tc.rows = 0;
+  for (size_t budget : {std::min(pref, (size_t)kToepDynMax), (size_t)kToepDynMax}) {
+    for (int rows = top; rows >= 16 && !tc.rows; rows -= 16)
+      if (toeplitz_v_lds(variant, rows, tc.nks) <= budget) tc.rows = rows;
+    if (tc.rows) break;
+  }
+  if (tc.rows) {  // same tile count, least padding: spread the rows evenly over the tiles
+    const int nty = (H + tc.rows - 1) / tc.rows;
+    tc.rows = ((H + 15) / 16 + nty - 1) / nty * 16;
+  }
+  return tc.rows > 0 && toeplitz_h_lds(variant, tc.nks) <= (size_t)kToepDynMax;
+}
 
 size_t elem_size(bf_dtype d) { return d == BF_U8 ? 1 : (d == BF_U16 ? 2 : 4); }
 
@@ -144,7 +173,6 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip) {
   if (p.dtype == BF_U16 && ip.range > 65535.0) return fail(BF_ERR_INVALID_ARG, "value_range above 65535 for u16");
   ip.R = p.radius > 0 ? p.radius : (int)std::ceil(3.0 * p.sigma_s);
   if (ip.R > 1024) return fail(BF_ERR_UNSUPPORTED, "radius above 1024");
-  if (p.width > kMaxWidth) return fail(BF_ERR_UNSUPPORTED, "width above 8192");
   double Tg = p.t_value > 0.0 ? p.t_value : ip.range;
   double cap = std::ceil(ip.range);
   if (p.t_mode == BF_T_GLOBAL) cap = std::max(cap, std::ceil(Tg));
@@ -153,12 +181,21 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip) {
   ip.T_global = (int32_t)std::ceil(Tg);
   ip.T_global_raw = Tg;
   int variant = p.blur == BF_BLUR_AUTO ? BF_BLUR_IIR_F32 : p.blur;
-  if (variant != BF_BLUR_IIR_F32) return fail(BF_ERR_UNSUPPORTED, "blur variant not built");
   ip.variant = variant;
+  if (!is_toeplitz(variant) && p.width > kMaxWidth)
+    return fail(BF_ERR_UNSUPPORTED, "width above 8192 for the recursive blur");
+  if (is_toeplitz(variant) && !toeplitz_shape(variant, ip.R, p.height, ip.tc))
+    return fail(BF_ERR_UNSUPPORTED, "radius above 120 for the Toeplitz blur");
   std::string err;
   if (!build_order_table(p.sigma_r, p.eps, ip.range, ip.T_cap, ip.tab, err)) return fail(BF_ERR_UNSUPPORTED, err);
-  std::vector<float> iir;
-  if (!build_iir_consts(p.sigma_s, iir, err)) return fail(BF_ERR_INVALID_ARG, err);
+  std::vector<float> iir, taps;
+  if (is_toeplitz(variant)) {
+    std::vector<double> t;
+    build_fir_taps(p.sigma_s, ip.R, t);
+    taps.assign(t.begin(), t.end());
+  } else if (!build_iir_consts(p.sigma_s, iir, err)) {
+    return fail(BF_ERR_INVALID_ARG, err);
+  }
   // geometry
   Geom &g = ip.g;
   g.H = p.height;
@@ -178,6 +215,9 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip) {
   g.Spos = S * cC;
   g.nc = (g.H + kB - 1) / kB;
   g.center = (float)(0.5 * ip.range);
+  if (!(g.center > 0.f)) return fail(BF_ERR_INVALID_ARG, "value_range too small");
+  g.padl = ip.R & 7;
+  g.zpitch = ((int64_t)g.W + g.padl + 7) / 8 * 8;
   // device tables
   bf_status st;
   if ((st = upload((void **)&ip.d_idx, ip.tab.idx_of_T.data(), ip.tab.idx_of_T.size() * 4))) return st;
@@ -185,15 +225,28 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip) {
   if ((st = upload((void **)&ip.d_pm, ip.tab.pm.data(), ip.tab.pm.size() * 4))) return st;
   if ((st = upload((void **)&ip.d_pc, ip.tab.pc.data(), ip.tab.pc.size() * 4))) return st;
   if ((st = upload((void **)&ip.d_iir, iir.data(), iir.size() * 4))) return st;
+  if ((st = upload((void **)&ip.d_taps, taps.data(), taps.size() * 4))) return st;
+  ip.tc.taps = ip.d_taps;
   hipError_t e = hipMalloc(&ip.d_state, 64);
   if (e != hipSuccess) return dev_fail(e, "hipMalloc(state)");
   // pairs per launch: bounded by a workspace budget for the smoothed images
   size_t per_pair = (size_t)g.H * g.Spos * sizeof(float4);
+  if (is_toeplitz(variant)) per_pair = (size_t)4 * g.H * g.zpitch * (is_split(variant) ? 4 : 2);
+  ip.z_per_pair = per_pair;
   size_t budget = (size_t)16 << 30;
   if (const char *b = std::getenv("BF_Z_BUDGET_MB")) budget = (size_t)std::atoll(b) << 20;
   size_t kc = budget / per_pair;
   if (kc < 1) kc = 1;
-  ip.KC = (int)std::min<size_t>(kc, (size_t)ip.tab.K_max);
+  ip.KC = (int)std::min<size_t>(std::min<size_t>(kc, (size_t)ip.tab.K_max), 65535);
+  if (is_toeplitz(variant)) {
+    // split the pairs of a launch over enough horizontal workgroups to fill the GPU
+    const int tiles = toeplitz_h_tiles(variant, g.H, g.W);
+    int groups = std::max(1, std::min(ip.KC, (2048 + tiles - 1) / tiles));
+    ip.tc.kpg = (ip.KC + groups - 1) / groups;
+    ip.tc.groups = (ip.KC + ip.tc.kpg - 1) / ip.tc.kpg;
+    hipError_t he = toeplitz_setup();
+    if (he != hipSuccess) return dev_fail(he, "Toeplitz LDS attributes");
+  }
   return BF_OK;
 }
 
@@ -203,6 +256,7 @@ void free_image(ImagePlan &ip) {
   (void)hipFree(ip.d_pm);
   (void)hipFree(ip.d_pc);
   (void)hipFree(ip.d_iir);
+  (void)hipFree(ip.d_taps);
   (void)hipFree(ip.d_state);
 }
 
@@ -302,6 +356,15 @@ bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out
     if (e != hipSuccess) return dev_fail(e, "reset");
   }
   const int Kmax = ip.tab.K_max;
+  if (is_toeplitz(ip.variant)) {
+    for (int k0 = 0; k0 < Kmax; k0 += ip.KC) {
+      const int kcount = std::min(ip.KC, Kmax - k0);
+      e = launch_toeplitz_chunk(s, ip.p.dtype, ip.variant, d_in, d_out, g, tab, st, ip.tc, k0, kcount, pl->d_Z,
+                                pl->d_PQ, k0 == 0, k0 + ip.KC >= Kmax, pl->rec);
+      if (e != hipSuccess) return dev_fail(e, "Toeplitz blur");
+    }
+    return BF_OK;
+  }
   for (int k0 = 0; k0 < Kmax; k0 += ip.KC) {
     const int kcount = std::min(ip.KC, Kmax - k0);
     e = launch_iir_chunk(s, ip.p.dtype, d_in, d_out, g, tab, st, ip.d_iir, k0, kcount, pl->d_cb, pl->d_Z,
@@ -380,10 +443,12 @@ bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out) {
     const ImagePlan &ip = pl->im[i];
     const Geom &g = ip.g;
     rowmax = std::max(rowmax, (size_t)g.H * g.W * elem_size(ip.p.dtype));
-    cb = std::max(cb, (size_t)ip.KC * g.nc * 6 * g.Spos * sizeof(float4));
-    Z = std::max(Z, (size_t)ip.KC * g.H * g.Spos * sizeof(float4));
-    PQ = std::max(PQ, (size_t)g.H * g.W * sizeof(float2));
-    lut = std::max(lut, (size_t)ip.KC * 256 * sizeof(float2));
+    if (!is_toeplitz(ip.variant)) {
+      cb = std::max(cb, (size_t)ip.KC * g.nc * 6 * g.Spos * sizeof(float4));
+      lut = std::max(lut, (size_t)ip.KC * 256 * sizeof(float2));
+    }
+    Z = std::max(Z, (size_t)ip.KC * ip.z_per_pair);
+    PQ = std::max(PQ, (size_t)(is_toeplitz(ip.variant) ? ip.tc.groups : 1) * g.H * g.W * sizeof(float2));
   }
   bf_status s;
   if ((s = ensure(&pl->d_rowmax, pl->rowmax_bytes, rowmax)) || (s = ensure((void **)&pl->d_cb, pl->cb_bytes, cb)) ||

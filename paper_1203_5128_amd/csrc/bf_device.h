@@ -36,7 +36,26 @@ struct Geom {
   int Spos;           // S * cC positions per padded row
   int nc;             // vertical chunks of kB rows
   float center;       // intensity subtracted from f in the f*cos, f*sin images
+  // Toeplitz path: smoothed images stored with a left pad of padl elements
+  // (padl = R mod 8) and a row pitch of zpitch elements (multiple of 8)
+  int64_t zpitch;
+  int padl;
 };
+
+// FIR taps and tile shape of the Toeplitz path.
+struct ToepCfg {
+  const float *taps;  // device, 2R+1 floats, exp(-(d-R)^2 / 2 sigma_s^2)
+  int R;
+  int nks;            // K-steps of 32 taps: 32 nks >= 16 + 2R
+  int rows;           // output rows per vertical tile (multiple of 16)
+  int groups;         // pair groups of the horizontal pass (partial sums each)
+  int kpg;            // pairs per group
+};
+
+// LDS of a gfx950 CU (all of it may go to one workgroup), and the largest
+// dynamic tile of the Toeplitz kernels (room left for their static tables).
+constexpr int kToepLdsMax = 160 * 1024;
+constexpr int kToepDynMax = kToepLdsMax - 4 * 1024;
 
 // Optional recorder of stage boundaries (host side): called before and after
 // each stage's launches on the launch stream.
@@ -55,5 +74,16 @@ hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *ou
                             DevTables tab, DevState st, const float *iir, int k0, int kcount,
                             float4 *cb, float4 *Z, float2 *PQ, bool first, bool last,
                             float2 *glut, const StageRec &rec);
+
+// ---- Toeplitz MFMA path (bf_toeplitz.hip) ----
+// LDS bytes of the two kernels' dynamic tiles, and the horizontal tile width.
+size_t toeplitz_v_lds(int variant, int rows, int nks);
+size_t toeplitz_h_lds(int variant, int nks);
+int toeplitz_h_tiles(int variant, int H, int W);
+// Allow the Toeplitz kernels the LDS they may ask for (once per process).
+hipError_t toeplitz_setup();
+hipError_t launch_toeplitz_chunk(hipStream_t s, bf_dtype dt, int variant, const void *f, float *out, const Geom &g,
+                                 DevTables tab, DevState st, const ToepCfg &tc, int k0, int kcount, void *Z,
+                                 float2 *PQ, bool first, bool last, const StageRec &rec);
 
 }  // namespace bfi

@@ -8,6 +8,7 @@
 #include <type_traits>
 
 #include "bf_device.h"
+#include "bf_phase.h"
 
 namespace bfi {
 
@@ -73,11 +74,6 @@ __device__ __forceinline__ void casc_step(float g1, float g2, float c2, float4 x
   d = nd;
 }
 
-template <typename Tin>
-__device__ __forceinline__ float fval(Tin v) {
-  return (float)v;
-}
-
 // ---- segmented running maxima across a wave (Appendix MAX-FILTER) --------
 // Lane l holds element e = e0 + l.  Partitions of the running maxima start at
 // segs (scan up) or end at sege (scan down).  Within each 16-lane row the
@@ -130,99 +126,6 @@ __device__ __forceinline__ float seg_max_down(float v, int e, int sege, int lane
   t = lane_value(v, 16);
   if ((lane >> 4) == 0 && e0 + 16 <= sege) v = fmaxf(v, t);
   return v;
-}
-
-__device__ __forceinline__ const OrderEntry &lookup(const DevTables &tab, const int32_t *Tu) {
-  int T = *Tu;
-  T = T < 0 ? 0 : (T > tab.T_cap ? tab.T_cap : T);
-  return tab.ent[tab.idx_of_T[T]];
-}
-
-// ------------------------------------------------------- phase generation
-// Turn (fraction of 2 pi) of the angle m * alpha * v, as an unsigned 32-bit
-// fixed-point number.  For integer v the product m*v is exact and the turn is
-// reduced exactly modulo 1 in 64-bit arithmetic (qfix = frac(alpha/2pi) 2^64);
-// a float v is split into its integer part (same exact path) and a fraction
-// r in [0,1) whose small angle m*r*alpha is added in double precision.
-template <typename Tin>
-__device__ __forceinline__ uint32_t phase_turn(int32_t m, Tin v, uint64_t q, double at) {
-  if constexpr (std::is_same<Tin, float>::value) {
-    float fl = floorf(v);
-    float r = v - fl;
-    int64_t mv = (int64_t)m * (int64_t)fl;
-    uint32_t ti = (uint32_t)(((uint64_t)mv * q) >> 32);
-    double x = (double)m * (double)r * at;
-    x -= rint(x);
-    return ti + (uint32_t)(int64_t)(x * 4294967296.0);
-  } else {
-    int64_t mv = (int64_t)m * (int64_t)v;
-    return (uint32_t)(((uint64_t)mv * q) >> 32);
-  }
-}
-
-// cos and sin of 2 pi tau / 2^32: exact quarter-turn reduction on the integer
-// turn, then Taylor polynomials on |x| <= pi/4 (truncation below 2e-9).
-__device__ __forceinline__ void turn_sincos(uint32_t tau, float &c, float &s) {
-  uint32_t q = (tau + 0x20000000u) >> 30;
-  int32_t r = (int32_t)(tau - (q << 30));
-  float x = (float)r * 1.46291807926715968e-9f;  // 2 pi / 2^32
-  float x2 = x * x;
-  float sp = fmaf(x * x2,
-                  fmaf(x2, fmaf(x2, fmaf(x2, 2.7557319223985893e-6f, -1.9841269841269841e-4f),
-                                8.3333333333333333e-3f),
-                       -1.6666666666666667e-1f),
-                  x);
-  float cp = fmaf(
-      x2,
-      fmaf(x2,
-           fmaf(x2, fmaf(x2, fmaf(x2, -2.7557319223985888e-7f, 2.4801587301587302e-5f),
-                         -1.3888888888888889e-3f),
-                4.1666666666666667e-2f),
-           -0.5f),
-      1.0f);
-  float cc = (q & 1u) ? -sp : cp;
-  float ss = (q & 1u) ? cp : sp;
-  if (q & 2u) {
-    cc = -cc;
-    ss = -ss;
-  }
-  c = cc;
-  s = ss;
-}
-
-// 8-bit images: cos and sin of one frequency for all 256 intensities, built
-// once per workgroup in LDS (one sincos per thread) instead of once per pixel.
-template <typename Tin>
-struct PhaseLut {
-  static constexpr bool kOn = sizeof(Tin) == 1;
-};
-__device__ __forceinline__ void build_lut(float2 *lut, int32_t m, uint64_t q, double at, int tid, int nthreads) {
-  for (int v = tid; v < 256; v += nthreads) {
-    float c, sn;
-    turn_sincos(phase_turn<uint8_t>(m, (uint8_t)v, q, at), c, sn);
-    lut[v] = make_float2(c, sn);
-  }
-}
-
-// The four images of one frequency at one pixel: (f-c) cos, (f-c) sin, cos, sin.
-template <typename Tin>
-__device__ __forceinline__ float4 planes(Tin v, int32_t m, uint64_t q, double at, float center) {
-  float c, s;
-  turn_sincos(phase_turn<Tin>(m, v, q, at), c, s);
-  float d = fval(v) - center;
-  return make_float4(d * c, d * s, c, s);
-}
-// Same, reading cos/sin from the workgroup's table for 8-bit images.
-template <typename Tin>
-__device__ __forceinline__ float4 planes_any(Tin v, const float2 *lut, int32_t m, uint64_t q, double at,
-                                             float center) {
-  if constexpr (PhaseLut<Tin>::kOn) {
-    const float2 cs = lut[(int)v];
-    const float d = fval(v) - center;
-    return make_float4(d * cs.x, d * cs.y, cs.x, cs.y);
-  } else {
-    return planes<Tin>(v, m, q, at, center);
-  }
 }
 
 // Publish a non-negative dynamic-range candidate.  Many workgroups race for

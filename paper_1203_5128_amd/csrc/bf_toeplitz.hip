@@ -1,0 +1,577 @@
+// gfx950 MFMA path of libbf.so: the spatial smoothing of SHIFTABLE-BF
+// (Sec. 1.2 step 3, eq. (GF)) as the separable FIR with taps
+// w[d] = exp(-(d-R)^2 / 2 sigma_s^2), d = 0..2R, zero extension, written as
+// banded Toeplitz matrices times image tiles on FP16/BF16 matrix cores with
+// FP32 accumulation.
+//
+// v_mfma_f32_16x16x32_{f16,bf16}: lane l holds A[l%16][8(l/16)+j] and
+// B[8(l/16)+j][l%16] (j = 0..7), and receives D[4(l/16)+i][l%16] (i = 0..3).
+//
+// Vertical pass: 16 output rows x 16 pixel columns of one image plane are
+//   D = T (16 x K) . In (K x 16),   T[i][t] = w[t - i] (zero off the band),
+// K = 32 nks >= 16 + 2R input rows.  Horizontal pass: 16 rows x 16 output
+// columns are D = In (16 x K) . T^T (K x 16).  The A fragment of T and the B
+// fragment of T^T are the same registers.
+//
+// Operands: the difference images (f - c) cos, (f - c) sin are divided by the
+// half range c so that every plane lies in [-1, 1]; with peak-one taps the
+// smoothed planes stay below (2R+1)^2 in magnitude, far inside FP16's range.
+// Both scale factors cancel in P/Q except the first, which the combine undoes.
+// Single variants store the vertical result (Z) in FP16/BF16; the split
+// variants store Z in FP32 and feed hi + lo halves to three MFMAs per product
+// (hi.hi + hi.lo + lo.hi).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+#include "bf_device.h"
+#include "bf_phase.h"
+
+namespace bfi {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <bool BF>
+struct MT;
+template <>
+struct MT<false> {
+  typedef _Float16 T;
+  typedef h8 V;
+  static __device__ __forceinline__ f4v mfma(V a, V b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MT<true> {
+  typedef __bf16 T;
+  typedef b8 V;
+  static __device__ __forceinline__ f4v mfma(V a, V b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// Tile shapes (the host sizes the vertical tile height to the LDS budget).
+template <bool SPLIT>
+struct TShape {
+  static constexpr int kVCols = SPLIT ? 16 : 32;   // pixel columns per vertical tile
+  static constexpr int kHCols = SPLIT ? 64 : 128;  // output columns per horizontal tile
+};
+constexpr int kHRows = 16;
+
+// Workgroups are dispatched to the eight XCDs in turn; map launch index id
+// to tile (id mod 8) * per + id / 8 so that each XCD works through a
+// contiguous run of neighbouring tiles, whose shared halos and cache lines
+// then meet in that XCD's L2.  per = ceil(tiles / 8).
+__device__ __forceinline__ int xcd_tile(int id, int per) { return (id & 7) * per + (id >> 3); }
+
+// The 2R+1 taps (2R+1 <= 241) are first copied to LDS by the workgroup (one
+// load per thread); each lane then builds its fragments from there.
+constexpr int kMaxTaps = 256;
+__device__ __forceinline__ void load_taps(float *wsh, const float *__restrict__ taps, int R, int tid) {
+  if (tid <= 2 * R) wsh[tid] = taps[tid];
+}
+
+// Tap fragment of lane l for K-step ks: T[l%16][32 ks + 8 (l/16) + j], read
+// from the LDS copy with a clamped index (no branches).
+template <bool BF>
+__device__ __forceinline__ void tap_frag(const float *w, int R, int ks, int lane, typename MT<BF>::V &hi,
+                                         typename MT<BF>::V &lo) {
+  typedef typename MT<BF>::T E;
+  const int i = lane & 15;
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    const int d = 32 * ks + 8 * (lane >> 4) + j - i;
+    const float t = w[min(max(d, 0), 2 * R)];
+    const float v = (d >= 0 && d <= 2 * R) ? t : 0.f;
+    const E h = (E)v;
+    hi[j] = h;
+    lo[j] = (E)(v - (float)h);
+  }
+}
+
+// ------------------------------------------------------------ vertical pass
+// Workgroup: `rows` output rows x kVCols pixel columns of one frequency pair.
+// The four images of the pair on the input rows [y0 - R, y0 + rows + R) are
+// generated from f into LDS as [plane][column][row] (row index contiguous, so
+// a lane's eight K elements are one 16-byte read; the padded row length
+// Kp = 8 mod 16 keeps both the staging writes and the fragment reads free of
+// bank conflicts), then the waves share the (16-row block, 16-column block)
+// products of all four planes.
+template <typename Tin, bool BF, bool SPLIT>
+__global__ __launch_bounds__(256) void k_toep_v(const Tin *__restrict__ f, Geom g, DevTables tab, DevState st,
+                                                const float *__restrict__ taps, int R, int nks, int rows, int ntx,
+                                                int ntiles, int per, int k0, void *__restrict__ Zv, size_t zplane) {
+  typedef typename MT<BF>::T E;
+  typedef typename MT<BF>::V V;
+  typedef typename std::conditional<SPLIT, float, E>::type ZT;
+  constexpr int kCols = TShape<SPLIT>::kVCols;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float2 lut[PhaseLut<Tin>::kOn ? 256 : 1];
+  __shared__ float wsh[kMaxTaps];
+  const int t = xcd_tile(blockIdx.x, per);
+  if (t >= ntiles) return;
+  const int kl = blockIdx.y;
+  const OrderEntry &e = lookup(tab, st.T_used);
+  const int k = k0 + kl;
+  if (k >= e.K) return;
+  const int32_t m = tab.pm[e.off + k];
+  const uint64_t q = e.qfix;
+  const double at = e.alpha_turn;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int x0 = (t % ntx) * kCols;
+  const int y0 = (t / ntx) * rows;
+  const int Kl = rows - 16 + 32 * nks;  // rows read by the last 16-row block
+  const int Kp = Kl + 8;
+  E *Bh = (E *)smem;
+  E *Bl = Bh + 4 * kCols * Kp;
+  const float inv = 1.f / g.center;
+  load_taps(wsh, taps, R, tid);  // consumed after the staging barrier
+  if constexpr (PhaseLut<Tin>::kOn) {
+    build_lut(lut, m, q, at, tid, 256);
+    __syncthreads();
+  }
+  // staging: one work item = 8 consecutive rows of one column.  The eight
+  // loads use clamped addresses and no branches, so they are all in flight
+  // together; rows and columns outside the image are zeroed afterwards.
+  const Freq fq = make_freq(m, q, at);
+  const int nstrip = Kl / 8;
+  for (int it = tid; it < nstrip * kCols; it += 256) {
+    const int c = it % kCols, sidx = it / kCols;
+    const int x = x0 + c;
+    const int xc = min(x, g.W - 1);
+    const int ybase = y0 - R + 8 * sidx;
+    Tin raw[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int yc = min(max(ybase + j, 0), g.H - 1);
+      raw[j] = f[(int64_t)yc * g.pitch + xc];
+    }
+    float pv[4][8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const bool ok = ybase + j >= 0 && ybase + j < g.H && x < g.W;
+      const float4 p = planes_any<Tin>(raw[j], lut, fq, g.center);
+      pv[0][j] = ok ? p.x * inv : 0.f;
+      pv[1][j] = ok ? p.y * inv : 0.f;
+      pv[2][j] = ok ? p.z : 0.f;
+      pv[3][j] = ok ? p.w : 0.f;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; p++) {
+      V h, l;
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        h[j] = (E)pv[p][j];
+        l[j] = (E)(pv[p][j] - (float)h[j]);
+      }
+      *(V *)(Bh + (p * kCols + c) * Kp + 8 * sidx) = h;
+      if (SPLIT) *(V *)(Bl + (p * kCols + c) * Kp + 8 * sidx) = l;
+    }
+  }
+  __syncthreads();
+  V th[8], tl[8];
+#pragma unroll
+  for (int ks = 0; ks < 8; ks++)
+    if (ks < nks) tap_frag<BF>(wsh, R, ks, lane, th[ks], tl[ks]);
+  ZT *Z = (ZT *)Zv + (size_t)kl * 4 * zplane;
+  const int nmb = rows / 16;
+  const int ncomb = nmb * (kCols / 16);
+  // D'[x][y] = In^T (16 columns x K) . T^T (K x 16 rows): the LDS column
+  // fragment is the A operand and the tap fragment the B operand, so lane l
+  // receives the 4 consecutive columns x0 + 16 nb + 4 (l/16) + i of row
+  // y0 + 16 mb + l%16 and writes them with one packed store.
+  typedef ZT Z4 __attribute__((ext_vector_type(4)));
+  typedef ZT Z2 __attribute__((ext_vector_type(2)));
+  for (int cb = wv; cb < ncomb; cb += 4) {
+    const int mb = cb % nmb, nb = cb / nmb;
+    const int px = nb * 16 + (lane & 15);
+    const int y = y0 + 16 * mb + (lane & 15);
+    const int xs = x0 + nb * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int p = 0; p < 4; p++) {
+      f4v acc = {0.f, 0.f, 0.f, 0.f};
+      const E *colh = Bh + (p * kCols + px) * Kp + 16 * mb + 8 * (lane >> 4);
+      const E *coll = Bl + (p * kCols + px) * Kp + 16 * mb + 8 * (lane >> 4);
+#pragma unroll
+      for (int ks = 0; ks < 8; ks++) {
+        if (ks < nks) {
+          const V bh = *(const V *)(colh + 32 * ks);
+          acc = MT<BF>::mfma(bh, th[ks], acc);
+          if (SPLIT) {
+            const V bl = *(const V *)(coll + 32 * ks);
+            acc = MT<BF>::mfma(bl, th[ks], acc);
+            acc = MT<BF>::mfma(bh, tl[ks], acc);
+          }
+        }
+      }
+      if (y < g.H && xs < g.W) {
+        ZT *zp = Z + (size_t)p * zplane + (size_t)y * g.zpitch + g.padl + xs;
+        if (xs + 4 <= g.W && (g.padl & 3) == 0) {
+          *(Z4 *)zp = (Z4){(ZT)acc[0], (ZT)acc[1], (ZT)acc[2], (ZT)acc[3]};
+        } else if (xs + 4 <= g.W && (g.padl & 1) == 0) {
+          *(Z2 *)zp = (Z2){(ZT)acc[0], (ZT)acc[1]};
+          *(Z2 *)(zp + 2) = (Z2){(ZT)acc[2], (ZT)acc[3]};
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+            if (xs + i < g.W) zp[i] = (ZT)acc[i];
+        }
+      }
+    }
+  }
+}
+
+// -------------------------------------------------- horizontal pass + combine
+// Workgroup: 16 rows x kHCols output columns and one group of consecutive
+// pairs (blockIdx.y).  For each pair the four vertical results on the columns
+// [x0 - R, x0 + kHCols + R) are staged in LDS as [plane][row][column] with
+// 16-byte loads (Z rows carry a left pad congruent to R mod 8, so the staged
+// window starts on an 8-element boundary); each wave multiplies its 16-column
+// blocks for every plane and folds the four results of each pixel with its
+// phases into the numerator and denominator of eqs. (f1), (f2).  With one
+// group and the last launch the workgroup divides and writes the output;
+// otherwise it leaves its partial sums in PQ[group] (added to what the
+// previous launch left there unless `first`).
+template <typename Tin, bool BF, bool SPLIT>
+__global__ __launch_bounds__(256) void k_toep_h(const Tin *__restrict__ f, float *__restrict__ out, Geom g,
+                                                DevTables tab, DevState st, const float *__restrict__ taps, int R,
+                                                int nks, int ntx, int ntiles, int per, int k0, int kcount, int kpg,
+                                                const void *__restrict__ Zv, size_t zplane,
+                                                float2 *__restrict__ PQ, int first, int finish) {
+  typedef typename MT<BF>::T E;
+  typedef typename MT<BF>::V V;
+  typedef typename std::conditional<SPLIT, float, E>::type ZT;
+  constexpr int kCols = TShape<SPLIT>::kHCols;
+  constexpr int kNbw = kCols / 64;  // 16-column blocks per wave
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float2 lut[PhaseLut<Tin>::kOn ? 256 : 1];
+  __shared__ float wsh[kMaxTaps];
+  const int t = xcd_tile(blockIdx.x, per);
+  if (t >= ntiles) return;
+  const OrderEntry &e = lookup(tab, st.T_used);
+  const int kb = k0 + blockIdx.y * kpg;
+  const int kend = min(min(kb + kpg, k0 + kcount), e.K);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int x0 = (t % ntx) * kCols;
+  const int y0 = (t / ntx) * kHRows;
+  const int Kl = kCols - 16 + 32 * nks;  // columns read by the last 16-column block
+  const int Kp = Kl + 8;
+  E *Ah = (E *)smem;
+  E *Al = Ah + 4 * kHRows * Kp;
+  load_taps(wsh, taps, R, tid);
+  __syncthreads();
+  V th[8], tl[8];
+#pragma unroll
+  for (int ks = 0; ks < 8; ks++)
+    if (ks < nks) tap_frag<BF>(wsh, R, ks, lane, th[ks], tl[ks]);
+  const int rbase = 4 * (lane >> 4);
+  Tin fv[kNbw][4];
+  float P[kNbw][4], Q[kNbw][4];
+#pragma unroll
+  for (int b = 0; b < kNbw; b++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int y = min(y0 + rbase + i, g.H - 1);
+      const int x = min(x0 + (kNbw * wv + b) * 16 + (lane & 15), g.W - 1);
+      fv[b][i] = f[(int64_t)y * g.pitch + x];
+      P[b][i] = 0.f;
+      Q[b][i] = 0.f;
+    }
+  const int zc0 = x0 - R + g.padl;  // multiple of 8
+  const int nvec = Kl / 8;
+  const ZT *Zb = (const ZT *)Zv;
+  const uint64_t q = e.qfix;
+  const double at = e.alpha_turn;
+  // Staging of one pair's Z tile: vector `it` of the tile is row rr = it / nvec
+  // (plane rr / 16), vectors v = it % nvec along the row.  Loads use an
+  // address inside the buffer for vectors off the image (then zeroed), so they
+  // carry no branches and several are in flight per thread.
+  typedef typename std::conditional<SPLIT, float4, V>::type LT;
+  constexpr int kLw = SPLIT ? 2 : 1;  // LT loads per vector
+  const int total = 4 * kHRows * nvec;
+  auto load_vec = [&](int it, int kl, LT *dst) {
+    it = min(it, total - 1);
+    const int v = it % nvec, rr = it / nvec;
+    const int y = y0 + rr % kHRows;
+    const int zc = zc0 + 8 * v;
+    const bool inr = y < g.H && zc + 8 > g.padl && zc < g.padl + g.W;
+    const ZT *src = Zb + (inr ? ((size_t)kl * 4 + rr / kHRows) * zplane + (size_t)y * g.zpitch + zc : 0);
+    dst[0] = *(const LT *)src;
+    if constexpr (SPLIT) dst[kLw - 1] = *(const LT *)(src + 4);
+  };
+  auto store_vec = [&](int it, const LT *raw) {
+    const int v = it % nvec, rr = it / nvec;
+    const int y = y0 + rr % kHRows;
+    const int zc = zc0 + 8 * v;
+    const bool inr = y < g.H && zc + 8 > g.padl && zc < g.padl + g.W;
+    const bool full = inr && zc >= g.padl && zc + 8 <= g.padl + g.W;
+    V h, l;
+    if constexpr (SPLIT) {
+      const float4 a = raw[0], bq = raw[kLw - 1];
+      const float vals[8] = {a.x, a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w};
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const bool ok = full || (inr && zc + j >= g.padl && zc + j < g.padl + g.W);
+        const float v8 = ok ? vals[j] : 0.f;
+        h[j] = (E)v8;
+        l[j] = (E)(v8 - (float)h[j]);
+      }
+    } else {
+      h = raw[0];
+      if (!full) {
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+          if (!(inr && zc + j >= g.padl && zc + j < g.padl + g.W)) h[j] = (E)0.f;
+      }
+    }
+    *(V *)(Ah + rr * Kp + 8 * v) = h;
+    if (SPLIT) *(V *)(Al + rr * Kp + 8 * v) = l;
+  };
+  for (int k = kb; k < kend; k++) {
+    const int kl = k - k0;
+    const int32_t m = tab.pm[e.off + k];
+    const float cp = tab.pc[e.off + k];
+    const Freq fq = make_freq(m, q, at);
+    __syncthreads();  // the previous pair's tile and table are consumed
+    if constexpr (PhaseLut<Tin>::kOn) build_lut(lut, m, q, at, tid, 256);
+    {
+      // batches of kU vectors per thread: every load of a batch is issued
+      // before the first is masked and stored
+      constexpr int kU = SPLIT ? 2 : 4;
+      for (int it0 = tid; it0 < total; it0 += 256 * kU) {
+        LT raw[kU][kLw];
+#pragma unroll
+        for (int u = 0; u < kU; u++) load_vec(it0 + 256 * u, kl, raw[u]);
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+          if (it0 + 256 * u < total) store_vec(it0 + 256 * u, raw[u]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < kNbw; b++) {
+      const int nb = kNbw * wv + b;
+      f4v acc[4];
+#pragma unroll
+      for (int p = 0; p < 4; p++) {
+        acc[p] = (f4v){0.f, 0.f, 0.f, 0.f};
+        const E *rowh = Ah + (p * kHRows + (lane & 15)) * Kp + 16 * nb + 8 * (lane >> 4);
+        const E *rowl = Al + (p * kHRows + (lane & 15)) * Kp + 16 * nb + 8 * (lane >> 4);
+#pragma unroll
+        for (int ks = 0; ks < 8; ks++) {
+          if (ks < nks) {
+            const V ah = *(const V *)(rowh + 32 * ks);
+            acc[p] = MT<BF>::mfma(ah, th[ks], acc[p]);
+            if (SPLIT) {
+              const V al = *(const V *)(rowl + 32 * ks);
+              acc[p] = MT<BF>::mfma(al, th[ks], acc[p]);
+              acc[p] = MT<BF>::mfma(ah, tl[ks], acc[p]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        float c, s;
+        if constexpr (PhaseLut<Tin>::kOn) {
+          const float2 cs = lut[(int)fv[b][i]];
+          c = cs.x;
+          s = cs.y;
+        } else {
+          turn_sincos(phase_turn<Tin>(fv[b][i], fq), c, s);
+        }
+        P[b][i] = fmaf(cp, fmaf(c, acc[0][i], s * acc[1][i]), P[b][i]);
+        Q[b][i] = fmaf(cp, fmaf(c, acc[2][i], s * acc[3][i]), Q[b][i]);
+      }
+    }
+  }
+  if (kb >= kend && !first && !finish) return;  // no pairs here: partial sums unchanged
+  float2 *PQg = PQ + (size_t)blockIdx.y * g.H * g.W;
+  unsigned long long nbad = 0;
+#pragma unroll
+  for (int b = 0; b < kNbw; b++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int y = y0 + rbase + i, x = x0 + (kNbw * wv + b) * 16 + (lane & 15);
+      if (y >= g.H || x >= g.W) continue;
+      float Pv = P[b][i], Qv = Q[b][i];
+      const size_t pix = (size_t)y * g.W + x;
+      if (!first) {
+        const float2 pq = PQg[pix];
+        Pv += pq.x;
+        Qv += pq.y;
+      }
+      if (finish) {
+        const float r = Pv / Qv;
+        float v;
+        if (Qv > 0.f && isfinite(r)) {
+          v = fmaf(g.center, r, g.center);
+        } else {
+          v = fval(fv[b][i]);
+          nbad++;
+        }
+        out[(int64_t)y * g.opitch + x] = v;
+      } else {
+        PQg[pix] = make_float2(Pv, Qv);
+      }
+    }
+  if (finish) {
+    for (int off = 32; off > 0; off >>= 1) nbad += __shfl_xor(nbad, off, 64);
+    if (lane == 0 && nbad) atomicAdd(st.q_nonpos, nbad);
+  }
+}
+
+// Sum of the groups' partial numerators and denominators, then eqs. (f1),
+// (f2) divided out: one thread per pixel.
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_toep_finish(const Tin *__restrict__ f, float *__restrict__ out, Geom g,
+                                                     DevState st, const float2 *__restrict__ PQ, int groups) {
+  const int64_t npx = (int64_t)g.H * g.W;
+  const int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  unsigned long long nbad = 0;
+  if (pix < npx) {
+    float Pv = 0.f, Qv = 0.f;
+    for (int gi = 0; gi < groups; gi++) {
+      const float2 pq = PQ[gi * npx + pix];
+      Pv += pq.x;
+      Qv += pq.y;
+    }
+    const int y = (int)(pix / g.W), x = (int)(pix % g.W);
+    const float r = Pv / Qv;
+    float v;
+    if (Qv > 0.f && isfinite(r)) {
+      v = fmaf(g.center, r, g.center);
+    } else {
+      v = fval(f[(int64_t)y * g.pitch + x]);
+      nbad = 1;
+    }
+    out[(int64_t)y * g.opitch + x] = v;
+  }
+  for (int off = 32; off > 0; off >>= 1) nbad += __shfl_xor(nbad, off, 64);
+  if ((threadIdx.x & 63) == 0 && nbad) atomicAdd(st.q_nonpos, nbad);
+}
+
+// ------------------------------------------------------------- launchers
+static bool split_of(int variant) { return variant == BF_BLUR_TOEPLITZ_F16X2 || variant == BF_BLUR_TOEPLITZ_BF16X2; }
+
+size_t toeplitz_v_lds(int variant, int rows, int nks) {
+  const bool split = split_of(variant);
+  const int cols = split ? TShape<true>::kVCols : TShape<false>::kVCols;
+  const int Kp = rows - 16 + 32 * nks + 8;
+  return (size_t)(split ? 2 : 1) * 4 * cols * Kp * 2;
+}
+size_t toeplitz_h_lds(int variant, int nks) {
+  const bool split = split_of(variant);
+  const int cols = split ? TShape<true>::kHCols : TShape<false>::kHCols;
+  const int Kp = cols - 16 + 32 * nks + 8;
+  return (size_t)(split ? 2 : 1) * 4 * kHRows * Kp * 2;
+}
+int toeplitz_h_tiles(int variant, int H, int W) {
+  const int cols = split_of(variant) ? TShape<true>::kHCols : TShape<false>::kHCols;
+  return ((W + cols - 1) / cols) * ((H + kHRows - 1) / kHRows);
+}
+
+template <typename Tin, bool BF, bool SPLIT>
+static hipError_t toep_t(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab, DevState st,
+                         const ToepCfg &tc, int k0, int kcount, void *Z, float2 *PQ, bool first, bool last,
+                         const StageRec &rec) {
+  const int variant = SPLIT ? (BF ? BF_BLUR_TOEPLITZ_BF16X2 : BF_BLUR_TOEPLITZ_F16X2)
+                            : (BF ? BF_BLUR_TOEPLITZ_BF16 : BF_BLUR_TOEPLITZ_F16);
+  if (tc.nks < 1 || tc.nks > 8 || 32 * tc.nks < 16 + 2 * tc.R || tc.rows < 16 || tc.rows % 16 || tc.groups < 1 ||
+      tc.kpg < 1 || kcount < 1 || kcount > 65535 || tc.groups > 65535)
+    return hipErrorInvalidValue;
+  const size_t zplane = (size_t)g.H * g.zpitch;
+  const size_t vl = toeplitz_v_lds(variant, tc.rows, tc.nks), hl = toeplitz_h_lds(variant, tc.nks);
+  rec.begin(BF_STAGE_TOEPLITZ, s);
+  {
+    constexpr int cols = TShape<SPLIT>::kVCols;
+    const int ntx = (g.W + cols - 1) / cols, nt = ntx * ((g.H + tc.rows - 1) / tc.rows), per = (nt + 7) / 8;
+    hipLaunchKernelGGL((k_toep_v<Tin, BF, SPLIT>), dim3(8 * per, kcount), dim3(256), vl, s, f, g, tab, st, tc.taps,
+                       tc.R, tc.nks, tc.rows, ntx, nt, per, k0, Z, zplane);
+  }
+  rec.end(BF_STAGE_TOEPLITZ, s);
+  rec.begin(BF_STAGE_H_COMBINE, s);
+  {
+    constexpr int cols = TShape<SPLIT>::kHCols;
+    const int ntx = (g.W + cols - 1) / cols, nt = ntx * ((g.H + kHRows - 1) / kHRows), per = (nt + 7) / 8;
+    const bool finish = last && tc.groups == 1;
+    hipLaunchKernelGGL((k_toep_h<Tin, BF, SPLIT>), dim3(8 * per, tc.groups), dim3(256), hl, s, f, out, g, tab, st,
+                       tc.taps, tc.R, tc.nks, ntx, nt, per, k0, kcount, tc.kpg, (const void *)Z, zplane, PQ,
+                       (int)first, (int)finish);
+    if (last && !finish) {
+      const int64_t npx = (int64_t)g.H * g.W;
+      hipLaunchKernelGGL((k_toep_finish<Tin>), dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, f, out, g, st,
+                         (const float2 *)PQ, tc.groups);
+    }
+  }
+  rec.end(BF_STAGE_H_COMBINE, s);
+  return hipGetLastError();
+}
+
+// Dynamic LDS above 64 KB must be allowed per kernel before its launch: the
+// kernel's static LDS plus the dynamic allowance may not exceed the CU's LDS.
+static hipError_t allow_one(const void *fn) {
+  hipFuncAttributes a;
+  hipError_t e = hipFuncGetAttributes(&a, fn);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kToepLdsMax - (int)a.sharedSizeBytes);
+}
+template <typename Tin, bool BF, bool SPLIT>
+static hipError_t allow_lds() {
+  hipError_t e = allow_one((const void *)k_toep_v<Tin, BF, SPLIT>);
+  return e == hipSuccess ? allow_one((const void *)k_toep_h<Tin, BF, SPLIT>) : e;
+}
+template <typename Tin>
+static hipError_t allow_lds_dt() {
+  hipError_t e;
+  if ((e = allow_lds<Tin, false, false>()) != hipSuccess) return e;
+  if ((e = allow_lds<Tin, true, false>()) != hipSuccess) return e;
+  if ((e = allow_lds<Tin, false, true>()) != hipSuccess) return e;
+  return allow_lds<Tin, true, true>();
+}
+hipError_t toeplitz_setup() {
+  hipError_t e;
+  if ((e = allow_lds_dt<uint8_t>()) != hipSuccess) return e;
+  if ((e = allow_lds_dt<uint16_t>()) != hipSuccess) return e;
+  return allow_lds_dt<float>();
+}
+
+template <typename Tin>
+static hipError_t toep_dt(hipStream_t s, int variant, const Tin *f, float *out, const Geom &g, DevTables tab,
+                          DevState st, const ToepCfg &tc, int k0, int kcount, void *Z, float2 *PQ, bool first,
+                          bool last, const StageRec &rec) {
+  switch (variant) {
+    case BF_BLUR_TOEPLITZ_F16:
+      return toep_t<Tin, false, false>(s, f, out, g, tab, st, tc, k0, kcount, Z, PQ, first, last, rec);
+    case BF_BLUR_TOEPLITZ_BF16:
+      return toep_t<Tin, true, false>(s, f, out, g, tab, st, tc, k0, kcount, Z, PQ, first, last, rec);
+    case BF_BLUR_TOEPLITZ_F16X2:
+      return toep_t<Tin, false, true>(s, f, out, g, tab, st, tc, k0, kcount, Z, PQ, first, last, rec);
+    case BF_BLUR_TOEPLITZ_BF16X2:
+      return toep_t<Tin, true, true>(s, f, out, g, tab, st, tc, k0, kcount, Z, PQ, first, last, rec);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_toeplitz_chunk(hipStream_t s, bf_dtype dt, int variant, const void *f, float *out, const Geom &g,
+                                 DevTables tab, DevState st, const ToepCfg &tc, int k0, int kcount, void *Z,
+                                 float2 *PQ, bool first, bool last, const StageRec &rec) {
+  switch (dt) {
+    case BF_U8:
+      return toep_dt<uint8_t>(s, variant, (const uint8_t *)f, out, g, tab, st, tc, k0, kcount, Z, PQ, first, last,
+                              rec);
+    case BF_U16:
+      return toep_dt<uint16_t>(s, variant, (const uint16_t *)f, out, g, tab, st, tc, k0, kcount, Z, PQ, first,
+                               last, rec);
+    default:
+      return toep_dt<float>(s, variant, (const float *)f, out, g, tab, st, tc, k0, kcount, Z, PQ, first, last,
+                            rec);
+  }
+}
+
+}  // namespace bfi

@@ -59,3 +59,15 @@ def test_null_arguments():
     assert L.bf_filter_batch(None, 1, None, None, None, None) == bf.BF_ERR_INVALID_ARG
     assert L.bf_dynamic_range(None, None, None, None) == bf.BF_ERR_INVALID_ARG
     L.bf_plan_destroy(None)
+
+
+@pytest.mark.parametrize("blur,R,ok", [("toeplitz_f16", 121, False), ("toeplitz_bf16", 150, False),
+                                       ("toeplitz_f16x2", 121, False), ("toeplitz_bf16x2", 400, False)])
+def test_toeplitz_radius_limits_rejected_without_device(blur, R, ok):
+    """The Toeplitz tiles hold the whole band of 2R+1 taps in LDS: radii whose
+    tiles exceed the LDS budget are refused before any device work."""
+    p = bf.make_params(16, 16, "u8", sigma_s=R / 3.0, sigma_r=20.0, radius=R, blur=blur)
+    h = ctypes.c_void_p(123)
+    st = bf.lib().bf_plan(ctypes.byref(p), 1, ctypes.byref(h))
+    assert st == bf.BF_ERR_UNSUPPORTED and h.value is None
+    assert "radius" in bf.bf_last_error_detail()
