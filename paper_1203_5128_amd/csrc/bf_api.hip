@@ -111,6 +111,21 @@ struct bf_plan_s {
   std::vector<GraphEntry> graphs;
   hipStream_t cap_stream = nullptr;  // private stream used only for capture
   bool use_graph = true;
+  // batches: images on the Toeplitz path run as grouped launches (one launch
+  // per stage for all of them), each in its own workspace region
+  bool grouped = false;
+  void *d_bws = nullptr;
+  size_t bws_bytes = 0;
+  std::vector<size_t> rowmax_off, z_off, pq_off;
+  struct BatchEntry {
+    std::vector<const void *> in;
+    std::vector<float *> out;
+    hipGraphExec_t exec;
+    void *d_args;
+  };
+  std::vector<BatchEntry> batches;
+  void *d_eager_args = nullptr;  // argument arrays of batches launched directly
+  size_t eager_args_bytes = 0;
 };
 
 namespace {
@@ -233,7 +248,7 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip) {
   size_t per_pair = (size_t)g.H * g.Spos * sizeof(float4);
   if (is_toeplitz(variant)) per_pair = (size_t)4 * g.H * g.zpitch * (is_split(variant) ? 4 : 2);
   ip.z_per_pair = per_pair;
-  size_t budget = (size_t)16 << 30;
+  size_t budget = (size_t)64 << 30;
   if (const char *b = std::getenv("BF_Z_BUDGET_MB")) budget = (size_t)std::atoll(b) << 20;
   size_t kc = budget / per_pair;
   if (kc < 1) kc = 1;
@@ -374,6 +389,240 @@ bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out
   return BF_OK;
 }
 
+// Whether an image of the plan runs inside the grouped launches of a batch.
+bool in_group(const bf_plan_s *pl, const ImagePlan &ip) {
+  return pl->grouped && is_toeplitz(ip.variant) && ip.KC == ip.tab.K_max;
+}
+
+// Host image of the argument arrays of one batch, packed for one upload.
+struct ArgPack {
+  std::vector<unsigned char> buf;
+  template <typename T>
+  size_t add(const std::vector<T> &v) {
+    const size_t off = (buf.size() + 255) / 256 * 256;
+    buf.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+// Block starts of a grouped launch from the per-image block counts.
+std::vector<int> starts_of(const std::vector<int> &blocks) {
+  std::vector<int> st(blocks.size() + 1, 0);
+  for (size_t i = 0; i < blocks.size(); i++) st[i + 1] = st[i] + blocks[i];
+  return st;
+}
+
+// The grouped launches of a batch: offsets of their argument arrays in the
+// packed buffer, block totals and LDS sizes.
+struct GLaunch {
+  int kind;  // 0 reset, 1 range, 2 Toeplitz stages
+  bf_dtype dt;
+  int variant;
+  bool seq;
+  int cnt;
+  size_t o[6];
+  int t[3];
+  size_t lds[2];
+};
+struct BatchPlan {
+  ArgPack pack;
+  std::vector<GLaunch> launches;
+};
+
+// Host side of a batch over images [0, n): the Toeplitz images grouped by
+// dtype and variant (their range stage by dtype and column-pass kind).
+void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_out, BatchPlan &bp) {
+  std::vector<int> gidx;
+  for (int i = 0; i < n; i++)
+    if (in_group(pl, pl->im[i])) gidx.push_back(i);
+  if (gidx.empty()) return;
+  {
+    std::vector<ResetArgs> ra;
+    std::vector<int> blocks;
+    for (int i : gidx) {
+      const ImagePlan &ip = pl->im[i];
+      const bool loc = ip.p.t_mode == BF_T_LOCAL;
+      ra.push_back(ResetArgs{GroupGrid{1, 1, 1}, state_of(ip), loc ? 0 : ip.T_global, loc ? 0.0 : ip.T_global_raw});
+      blocks.push_back(1);
+    }
+    const std::vector<int> st = starts_of(blocks);
+    GLaunch L{};
+    L.kind = 0;
+    L.cnt = (int)ra.size();
+    L.o[0] = bp.pack.add(ra);
+    L.o[1] = bp.pack.add(st);
+    L.t[0] = st.back();
+    bp.launches.push_back(L);
+  }
+  for (bf_dtype dt : {BF_U8, BF_U16, BF_F32})
+    for (bool seq : {false, true}) {
+      std::vector<RowmaxArgs> ra;
+      std::vector<ColmaxArgs> ca;
+      std::vector<int> rb, cb;
+      for (int i : gidx) {
+        const ImagePlan &ip = pl->im[i];
+        if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || range_col_seq(ip.R) != seq) continue;
+        void *rm = (char *)pl->d_bws + pl->rowmax_off[i];
+        const GroupGrid gr = range_row_grid(ip.g), gc = range_col_grid(ip.g, ip.R);
+        ra.push_back(RowmaxArgs{gr, d_in[i], ip.g.pitch, ip.g.H, ip.g.W, ip.R, rm, state_of(ip)});
+        ca.push_back(ColmaxArgs{gc, d_in[i], ip.g.pitch, rm, ip.g.H, ip.g.W, ip.R, state_of(ip), ip.T_cap});
+        rb.push_back(gr.gx * gr.gy);
+        cb.push_back(gc.gx * gc.gy);
+      }
+      if (ra.empty()) continue;
+      const std::vector<int> rs = starts_of(rb), cs = starts_of(cb);
+      GLaunch L{};
+      L.kind = 1;
+      L.dt = dt;
+      L.seq = seq;
+      L.cnt = (int)ra.size();
+      L.o[0] = bp.pack.add(ra);
+      L.o[1] = bp.pack.add(rs);
+      L.o[2] = bp.pack.add(ca);
+      L.o[3] = bp.pack.add(cs);
+      L.t[0] = rs.back();
+      L.t[1] = cs.back();
+      bp.launches.push_back(L);
+    }
+  for (bf_dtype dt : {BF_U8, BF_U16, BF_F32})
+    for (int v = BF_BLUR_TOEPLITZ_F16; v <= BF_BLUR_TOEPLITZ_BF16X2; v++) {
+      std::vector<ToepVArgs> va;
+      std::vector<ToepHArgs> ha;
+      std::vector<FinishArgs> fa;
+      std::vector<int> vb, hb, fb;
+      size_t vl = 0, hl = 0;
+      for (int i : gidx) {
+        const ImagePlan &ip = pl->im[i];
+        if (ip.p.dtype != dt || ip.variant != v) continue;
+        ToepVArgs a;
+        ToepHArgs b;
+        FinishArgs c;
+        toeplitz_args(v, d_in[i], d_out[i], ip.g, tables_of(ip), state_of(ip), ip.tc, 0, ip.tab.K_max,
+                      (char *)pl->d_bws + pl->z_off[i], (float2 *)((char *)pl->d_bws + pl->pq_off[i]), true, true,
+                      a, b, c);
+        va.push_back(a);
+        ha.push_back(b);
+        fa.push_back(c);
+        vb.push_back(a.gg.gx * a.gg.gy);
+        hb.push_back(b.gg.gx * b.gg.gy);
+        fb.push_back(b.finish ? 0 : c.gg.gx);
+        vl = std::max(vl, toeplitz_v_lds(v, ip.tc.rows, ip.tc.nks));
+        hl = std::max(hl, toeplitz_h_lds(v, ip.tc.nks));
+      }
+      if (va.empty()) continue;
+      const std::vector<int> vs = starts_of(vb), hs = starts_of(hb), fs = starts_of(fb);
+      GLaunch L{};
+      L.kind = 2;
+      L.dt = dt;
+      L.variant = v;
+      L.cnt = (int)va.size();
+      L.o[0] = bp.pack.add(va);
+      L.o[1] = bp.pack.add(vs);
+      L.o[2] = bp.pack.add(ha);
+      L.o[3] = bp.pack.add(hs);
+      L.o[4] = bp.pack.add(fa);
+      L.o[5] = bp.pack.add(fs);
+      L.t[0] = vs.back();
+      L.t[1] = hs.back();
+      L.t[2] = fs.back();
+      L.lds[0] = vl;
+      L.lds[1] = hl;
+      bp.launches.push_back(L);
+    }
+}
+
+// Device side of a batch: the grouped launches (their arguments already in
+// d_args) and then the launch sequences of the images outside the groups.
+// Kernels only, so it may run under stream capture.
+bf_status enqueue_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_out, const BatchPlan &bp,
+                        const char *d_args, hipStream_t s) {
+  for (const GLaunch &L : bp.launches) {
+    hipError_t e;
+    if (L.kind == 0) {
+      e = launch_reset_group(s, (const ResetArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]), L.t[0], L.cnt);
+    } else if (L.kind == 1) {
+      pl->rec.begin(BF_STAGE_RANGE, s);
+      e = launch_range_group(s, L.dt, L.seq, (const RowmaxArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]),
+                             L.t[0], (const ColmaxArgs *)(d_args + L.o[2]), (const int *)(d_args + L.o[3]), L.t[1],
+                             L.cnt);
+      pl->rec.end(BF_STAGE_RANGE, s);
+    } else {
+      const ToepGroup tg{L.cnt,
+                         (const ToepVArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]), L.t[0], L.lds[0],
+                         (const ToepHArgs *)(d_args + L.o[2]), (const int *)(d_args + L.o[3]), L.t[1], L.lds[1],
+                         (const FinishArgs *)(d_args + L.o[4]), (const int *)(d_args + L.o[5]), L.t[2]};
+      e = launch_toeplitz_group(s, L.dt, L.variant, tg, pl->rec);
+    }
+    if (e != hipSuccess) return dev_fail(e, "grouped launch");
+  }
+  for (int i = 0; i < n; i++) {
+    if (in_group(pl, pl->im[i])) continue;
+    bf_status st = run_image(pl, pl->im[i], d_in[i], d_out[i], s);
+    if (st) return st;
+  }
+  return BF_OK;
+}
+
+// A batch launched directly: arguments go to the plan's buffer once the
+// stream has finished with its previous contents.
+bf_status run_batch_eager(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_out, hipStream_t s) {
+  BatchPlan bp;
+  build_batch(pl, n, d_in, d_out, bp);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
+  bf_status st = ensure(&pl->d_eager_args, pl->eager_args_bytes, std::max<size_t>(bp.pack.buf.size(), 256));
+  if (st) return st;
+  if (!bp.pack.buf.empty()) {
+    e = hipMemcpy(pl->d_eager_args, bp.pack.buf.data(), bp.pack.buf.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return dev_fail(e, "hipMemcpy(batch arguments)");
+  }
+  return enqueue_batch(pl, n, d_in, d_out, bp, (const char *)pl->d_eager_args, s);
+}
+
+// The whole batch through one captured graph, cached per set of pointers;
+// the graph owns a private copy of the argument arrays.
+bf_status run_batch_graph(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_out, hipStream_t s) {
+  for (auto &b : pl->batches) {
+    if ((int)b.in.size() != n) continue;
+    bool same = true;
+    for (int i = 0; i < n && same; i++) same = b.in[i] == d_in[i] && b.out[i] == d_out[i];
+    if (!same) continue;
+    hipError_t e = hipGraphLaunch(b.exec, s);
+    return e == hipSuccess ? BF_OK : dev_fail(e, "hipGraphLaunch");
+  }
+  BatchPlan bp;
+  build_batch(pl, n, d_in, d_out, bp);
+  void *d_args = nullptr;
+  hipError_t e = hipMalloc(&d_args, std::max<size_t>(bp.pack.buf.size(), 256));
+  if (e != hipSuccess) return dev_fail(e, "hipMalloc(batch arguments)");
+  if (!bp.pack.buf.empty()) e = hipMemcpy(d_args, bp.pack.buf.data(), bp.pack.buf.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !pl->cap_stream) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipFree(d_args);
+    return dev_fail(e, "batch capture setup");
+  }
+  bf_status st = enqueue_batch(pl, n, d_in, d_out, bp, (const char *)d_args, pl->cap_stream);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(pl->cap_stream, &graph);
+  hipGraphExec_t exec = nullptr;
+  if (!st && e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (st || e != hipSuccess) {
+    (void)hipFree(d_args);
+    return st ? st : dev_fail(e, "batch graph");
+  }
+  if (pl->batches.size() >= 4) {
+    (void)hipGraphExecDestroy(pl->batches.front().exec);
+    (void)hipFree(pl->batches.front().d_args);
+    pl->batches.erase(pl->batches.begin());
+  }
+  pl->batches.push_back({std::vector<const void *>(d_in, d_in + n), std::vector<float *>(d_out, d_out + n), exec, d_args});
+  e = hipGraphLaunch(exec, s);
+  return e == hipSuccess ? BF_OK : dev_fail(e, "hipGraphLaunch");
+}
+
 bf_status fill_report(ImagePlan &ip, bf_report *rep, float ms) {
   unsigned char buf[24];
   hipError_t e = hipMemcpy(buf, ip.d_state, 24, hipMemcpyDeviceToHost);
@@ -457,6 +706,36 @@ bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out) {
     bf_plan_destroy(pl);
     return s;
   }
+  if (n_images > 1) {
+    // per-image regions for the grouped launches (row maxima, smoothed
+    // images of every pair, partial sums), within the workspace budget
+    size_t off = 0, zsum = 0;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off += (bytes + 255) / 256 * 256;
+      return o;
+    };
+    for (int i = 0; i < n_images; i++) {
+      const ImagePlan &ip = pl->im[i];
+      const bool t = is_toeplitz(ip.variant);
+      const size_t zb = t ? (size_t)ip.tab.K_max * ip.z_per_pair : 0;
+      zsum += zb;
+      pl->rowmax_off.push_back(take((size_t)ip.g.H * ip.g.W * elem_size(ip.p.dtype)));
+      pl->z_off.push_back(take(zb));
+      pl->pq_off.push_back(take(t ? (size_t)ip.tc.groups * ip.g.H * ip.g.W * sizeof(float2) : 0));
+    }
+    size_t budget = (size_t)64 << 30;
+    if (const char *b = std::getenv("BF_Z_BUDGET_MB")) budget = (size_t)std::atoll(b) << 20;
+    bool any = false;
+    for (const auto &ip : pl->im) any = any || is_toeplitz(ip.variant);
+    if (any && zsum <= budget) {
+      if ((s = ensure(&pl->d_bws, pl->bws_bytes, off))) {
+        bf_plan_destroy(pl);
+        return s;
+      }
+      pl->grouped = true;
+    }
+  }
   if (const char *g = std::getenv("BF_GRAPH")) pl->use_graph = std::atoi(g) != 0;
   if (hipEventCreate(&pl->ev0) != hipSuccess || hipEventCreate(&pl->ev1) != hipSuccess) {
     bf_plan_destroy(pl);
@@ -504,6 +783,12 @@ void bf_plan_destroy(bf_plan_t pl) {
   }
   for (auto e : pl->ev_pool) (void)hipEventDestroy(e);
   for (auto &g : pl->graphs) (void)hipGraphExecDestroy(g.exec);
+  for (auto &b : pl->batches) {
+    (void)hipGraphExecDestroy(b.exec);
+    (void)hipFree(b.d_args);
+  }
+  (void)hipFree(pl->d_bws);
+  (void)hipFree(pl->d_eager_args);
   if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
   for (auto e : pl->open_ev)
     if (e) (void)hipEventDestroy(e);
@@ -543,11 +828,9 @@ bf_status bf_filter_batch(bf_plan_t pl, int32_t n, const void *const *d_in, floa
     if (!d_in[i] || !d_out[i]) return fail(BF_ERR_INVALID_ARG, "NULL image pointer");
   hipStream_t s = (hipStream_t)hip_stream;
   if (reps) (void)hipEventRecord(pl->ev0, s);
-  for (int i = 0; i < n; i++) {
-    bf_status st = (pl->use_graph && !pl->prof) ? run_image_graph(pl, i, d_in[i], d_out[i], s)
-                                                 : run_image(pl, pl->im[i], d_in[i], d_out[i], s);
-    if (st) return st;
-  }
+  bf_status bst = (pl->use_graph && !pl->prof) ? run_batch_graph(pl, n, d_in, d_out, s)
+                                               : run_batch_eager(pl, n, d_in, d_out, s);
+  if (bst) return bst;
   if (!reps) return BF_OK;
   (void)hipEventRecord(pl->ev1, s);
   hipError_t e = hipStreamSynchronize(s);

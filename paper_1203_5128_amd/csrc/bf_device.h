@@ -42,6 +42,8 @@ struct Geom {
   int padl;
 };
 
+
+
 // FIR taps and tile shape of the Toeplitz path.
 struct ToepCfg {
   const float *taps;  // device, 2R+1 floats, exp(-(d-R)^2 / 2 sigma_s^2)
@@ -57,6 +59,93 @@ struct ToepCfg {
 constexpr int kToepLdsMax = 160 * 1024;
 constexpr int kToepDynMax = kToepLdsMax - 4 * 1024;
 
+// Block coordinates handed to a kernel body: the launch's own blockIdx for a
+// single image, or the coordinates inside one image's share of a grouped
+// launch over several images.
+struct Blk {
+  int x, y, z;
+};
+
+// Grouped launches: one launch runs the same stage for several images.  Image
+// i owns the launch's blocks [start[i], start[i+1]); each image's arguments
+// carry its own grid (gx, gy, gz), into which its local block index is
+// decomposed x-fastest.
+struct GroupGrid {
+  int gx, gy, gz;
+};
+__device__ __forceinline__ int group_find(const int *__restrict__ start, int n, int bid) {
+  int lo = 0, hi = n - 1;  // largest i with start[i] <= bid (it owns bid)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ __forceinline__ Blk group_blk(const GroupGrid &gg, int local) {
+  return Blk{local % gg.gx, (local / gg.gx) % gg.gy, local / (gg.gx * gg.gy)};
+}
+
+// Per-image arguments of the kernels that also run as grouped launches.
+struct ResetArgs {
+  GroupGrid gg;
+  DevState st;
+  int32_t T_used;
+  double T_raw;
+};
+struct RowmaxArgs {
+  GroupGrid gg;
+  const void *f;
+  int64_t pitch;
+  int H, W, R;
+  void *rowmax;
+  DevState st;
+};
+struct ColmaxArgs {
+  GroupGrid gg;
+  const void *f;
+  int64_t pitch;
+  const void *rowmax;
+  int H, W, R;
+  DevState st;
+  int32_t T_cap;
+};
+
+struct ToepVArgs {  // vertical pass: blocks (launch tile index, pair)
+  GroupGrid gg;
+  const void *f;
+  Geom g;
+  DevTables tab;
+  DevState st;
+  ToepCfg tc;
+  int ntx, ntiles, per, k0;
+  void *Z;
+  size_t zplane;
+};
+struct ToepHArgs {  // horizontal pass + combine: blocks (launch tile index, pair group)
+  GroupGrid gg;
+  const void *f;
+  float *out;
+  Geom g;
+  DevTables tab;
+  DevState st;
+  ToepCfg tc;
+  int ntx, ntiles, per, k0, kcount;
+  const void *Z;
+  size_t zplane;
+  float2 *PQ;
+  int first, finish;
+};
+struct FinishArgs {  // sum of the groups' partial sums and the division
+  GroupGrid gg;
+  const void *f;
+  float *out;
+  Geom g;
+  DevState st;
+  const float2 *PQ;
+  int groups;
+};
+
 // Optional recorder of stage boundaries (host side): called before and after
 // each stage's launches on the launch stream.
 struct StageRec {
@@ -70,6 +159,15 @@ struct StageRec {
 hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw);
 hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,
                         DevState st, int32_t T_cap, const StageRec &rec);
+// Grids of the range stage for one image and whether its column pass is the
+// sequential kind (windows taller than the LDS tile).
+GroupGrid range_row_grid(const Geom &g);
+GroupGrid range_col_grid(const Geom &g, int R);
+bool range_col_seq(int R);
+// Grouped launches over n images (device argument arrays and block starts).
+hipError_t launch_reset_group(hipStream_t s, const ResetArgs *a, const int *start, int total, int n);
+hipError_t launch_range_group(hipStream_t s, bf_dtype dt, bool seq, const RowmaxArgs *ra, const int *rstart,
+                              int rtotal, const ColmaxArgs *ca, const int *cstart, int ctotal, int n);
 hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *out, const Geom &g,
                             DevTables tab, DevState st, const float *iir, int k0, int kcount,
                             float4 *cb, float4 *Z, float2 *PQ, bool first, bool last,
@@ -82,6 +180,30 @@ size_t toeplitz_h_lds(int variant, int nks);
 int toeplitz_h_tiles(int variant, int H, int W);
 // Allow the Toeplitz kernels the LDS they may ask for (once per process).
 hipError_t toeplitz_setup();
+// Arguments of the Toeplitz kernels for one image and pairs [k0, k0+kcount);
+// fa.gg.gx blocks of the finishing kernel are needed when the image splits its
+// pairs into several groups and this is its last launch (ha.finish == 0).
+void toeplitz_args(int variant, const void *f, float *out, const Geom &g, DevTables tab, DevState st,
+                   const ToepCfg &tc, int k0, int kcount, void *Z, float2 *PQ, bool first, bool last,
+                   ToepVArgs &va, ToepHArgs &ha, FinishArgs &fa);
+// A grouped launch of the Toeplitz stages: device argument arrays, block
+// starts (n+1 entries each), block totals and the largest dynamic LDS.
+struct ToepGroup {
+  int n;
+  const ToepVArgs *va;
+  const int *vstart;
+  int vtotal;
+  size_t vlds;
+  const ToepHArgs *ha;
+  const int *hstart;
+  int htotal;
+  size_t hlds;
+  const FinishArgs *fa;
+  const int *fstart;
+  int ftotal;
+};
+hipError_t launch_toeplitz_group(hipStream_t s, bf_dtype dt, int variant, const ToepGroup &tg,
+                                 const StageRec &rec);
 hipError_t launch_toeplitz_chunk(hipStream_t s, bf_dtype dt, int variant, const void *f, float *out, const Geom &g,
                                  DevTables tab, DevState st, const ToepCfg &tc, int k0, int kcount, void *Z,
                                  float2 *PQ, bool first, bool last, const StageRec &rec);

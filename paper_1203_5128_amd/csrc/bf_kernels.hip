@@ -143,13 +143,22 @@ __device__ __forceinline__ void publish_T(const DevState &st, double t, int32_t 
 }
 
 // ------------------------------------------------------------------- reset
-__global__ void k_reset(DevState st, int32_t T_used, double T_raw) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+__device__ __forceinline__ void reset_body(const ResetArgs &a, const Blk b) {
+  const DevState st = a.st;
+  const int32_t T_used = a.T_used;
+  const double T_raw = a.T_raw;
+
+  if (threadIdx.x == 0 && b.x == 0) {
     *st.T_used = T_used;
     *st.T_raw = (unsigned long long)__double_as_longlong(T_raw);
     *st.flags = 0;
     *st.q_nonpos = 0ull;
   }
+}
+__global__ void k_reset(ResetArgs a) { reset_body(a, Blk{(int)blockIdx.x, 0, 0}); }
+__global__ void k_reset_grp(const ResetArgs *__restrict__ a, const int *__restrict__ start, int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  reset_body(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
 }
 
 // ------------------------------------------------- Algorithm 1, row pass
@@ -172,12 +181,17 @@ constexpr int kRowSeg = 256;
 constexpr int kMaxR = 1024;
 
 template <typename Tin>
-__global__ __launch_bounds__(64) void k_rowmax(const Tin *__restrict__ f, int64_t pitch, int H, int W,
-                                               int R, Tin *__restrict__ rowmax, DevState st) {
+__device__ __forceinline__ void rowmax_body(const RowmaxArgs &a, const Blk b) {
+  const Tin *__restrict__ f = (const Tin *)a.f;
+  const int64_t pitch = a.pitch;
+  const int W = a.W, R = a.R;
+  Tin *__restrict__ rowmax = (Tin *)a.rowmax;
+  const DevState st = a.st;
+
   __shared__ float sv[kRowSeg + 2 * kMaxR + 64];
   __shared__ float sl[kRowSeg + 2 * kMaxR + 64];
-  const int y = blockIdx.y;
-  const int xs = blockIdx.x * kRowSeg;
+  const int y = b.y;
+  const int xs = b.x * kRowSeg;
   if (xs >= W) return;
   const int n_out = min(kRowSeg, W - xs);
   const int L = n_out + 2 * R;
@@ -233,6 +247,16 @@ __global__ __launch_bounds__(64) void k_rowmax(const Tin *__restrict__ f, int64_
   for (int i = lane; i < n_out; i += 64) orow[i] = (Tin)fmaxf(sv[i], sl[i + 2 * R]);
   if (__any(bad) && lane == 0) atomicOr(st.flags, 1);
 }
+template <typename Tin>
+__global__ __launch_bounds__(64) void k_rowmax(RowmaxArgs a) {
+  rowmax_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
+}
+template <typename Tin>
+__global__ __launch_bounds__(64) void k_rowmax_grp(const RowmaxArgs *__restrict__ a,
+                                                   const int *__restrict__ start, int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  rowmax_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+}
 
 // ---------------------------------------- Algorithm 1, column pass and T
 // A workgroup takes 16 columns and a band of 64 output rows.  The band's row
@@ -248,17 +272,22 @@ constexpr int kColW = 16;
 constexpr int kColStride = kColW + 1;
 
 template <typename Tin>
-__global__ __launch_bounds__(256) void k_colmax_T(const Tin *__restrict__ f, int64_t pitch,
-                                                  const Tin *__restrict__ rowmax, int H, int W, int R,
-                                                  DevState st, int32_t T_cap) {
+__device__ __forceinline__ void colmax_T_body(const ColmaxArgs &a, const Blk b) {
+  const Tin *__restrict__ f = (const Tin *)a.f;
+  const int64_t pitch = a.pitch;
+  const Tin *__restrict__ rowmax = (const Tin *)a.rowmax;
+  const int H = a.H, W = a.W, R = a.R;
+  const DevState st = a.st;
+  const int32_t T_cap = a.T_cap;
+
   __shared__ float tile[(kColBand + 2 * kColMaxR) * kColStride];
   __shared__ float fb[kColBand * kColStride];
   __shared__ float rr[4][4][kColBand];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  const int x0 = blockIdx.x * kColW;
-  const int y0 = blockIdx.y * kColBand;
+  const int x0 = b.x * kColW;
+  const int y0 = b.y * kColBand;
   const int nb = min(kColBand, H - y0);
   const int L = nb + 2 * R;  // tile rows: y = y0 - R + e
   for (int base = 0; base < L * kColW; base += 4 * 256) {
@@ -338,6 +367,16 @@ __global__ __launch_bounds__(256) void k_colmax_T(const Tin *__restrict__ f, int
   __syncthreads();
   if (tid == 0) publish_T(st, fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3])), T_cap);
 }
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_colmax_T(ColmaxArgs a) {
+  colmax_T_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
+}
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_colmax_T_grp(const ColmaxArgs *__restrict__ a,
+                                                      const int *__restrict__ start, int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  colmax_T_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+}
 
 // Same column pass for windows too tall for the LDS tile: one lane per column
 // walks the band (plus halo) bottom-up for the right running maxima and
@@ -345,13 +384,18 @@ __global__ __launch_bounds__(256) void k_colmax_T(const Tin *__restrict__ f, int
 constexpr int kColBandSeq = 128;
 
 template <typename Tin>
-__global__ __launch_bounds__(64) void k_colmax_T_seq(const Tin *__restrict__ f, int64_t pitch,
-                                                     const Tin *__restrict__ rowmax, int H, int W, int R,
-                                                     DevState st, int32_t T_cap) {
+__device__ __forceinline__ void colmax_T_seq_body(const ColmaxArgs &a, const Blk b) {
+  const Tin *__restrict__ f = (const Tin *)a.f;
+  const int64_t pitch = a.pitch;
+  const Tin *__restrict__ rowmax = (const Tin *)a.rowmax;
+  const int H = a.H, W = a.W, R = a.R;
+  const DevState st = a.st;
+  const int32_t T_cap = a.T_cap;
+
   __shared__ float srb[kColBandSeq][64];
   const int lane = threadIdx.x;
-  const int x = blockIdx.x * 64 + lane;
-  const int y0 = blockIdx.y * kColBandSeq;
+  const int x = b.x * 64 + lane;
+  const int y0 = b.y * kColBandSeq;
   const int nb = min(kColBandSeq, H - y0);
   const int L = nb + 2 * R;
   const int Wd = 2 * R + 1;
@@ -405,6 +449,16 @@ __global__ __launch_bounds__(64) void k_colmax_T_seq(const Tin *__restrict__ f, 
     tmax = o > tmax ? o : tmax;
   }
   if (lane == 0) publish_T(st, tmax, T_cap);
+}
+template <typename Tin>
+__global__ __launch_bounds__(64) void k_colmax_T_seq(ColmaxArgs a) {
+  colmax_T_seq_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
+}
+template <typename Tin>
+__global__ __launch_bounds__(64) void k_colmax_T_seq_grp(const ColmaxArgs *__restrict__ a,
+                                                         const int *__restrict__ start, int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  colmax_T_seq_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
 }
 
 // --------------------------------------------- blocked recursive Gaussian
@@ -820,26 +874,58 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
 
 // ------------------------------------------------------------- launchers
 hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw) {
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, st, T_used, T_raw);
+  ResetArgs a{GroupGrid{1, 1, 1}, st, T_used, T_raw};
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
 }
+
+// Grids of the range stage for one image (also the per-image grids of a
+// grouped launch).
+GroupGrid range_row_grid(const Geom &g) { return GroupGrid{(g.W + kRowSeg - 1) / kRowSeg, g.H, 1}; }
+GroupGrid range_col_grid(const Geom &g, int R) {
+  if (R <= kColMaxR) return GroupGrid{(g.W + kColW - 1) / kColW, (g.H + kColBand - 1) / kColBand, 1};
+  return GroupGrid{(g.W + 63) / 64, (g.H + kColBandSeq - 1) / kColBandSeq, 1};
+}
+bool range_col_seq(int R) { return R > kColMaxR; }
 
 template <typename Tin>
 static hipError_t range_t(hipStream_t s, const Tin *f, const Geom &g, int R, Tin *rowmax, DevState st,
                           int32_t T_cap, const StageRec &rec) {
   rec.begin(BF_STAGE_RANGE, s);
-  dim3 gr((g.W + kRowSeg - 1) / kRowSeg, g.H);
-  hipLaunchKernelGGL(k_rowmax<Tin>, gr, dim3(64), 0, s, f, g.pitch, g.H, g.W, R, rowmax, st);
-  if (R <= kColMaxR) {
-    dim3 gc((g.W + kColW - 1) / kColW, (g.H + kColBand - 1) / kColBand);
-    hipLaunchKernelGGL(k_colmax_T<Tin>, gc, dim3(256), 0, s, f, g.pitch, (const Tin *)rowmax, g.H, g.W, R,
-                       st, T_cap);
-  } else {
-    dim3 gc((g.W + 63) / 64, (g.H + kColBandSeq - 1) / kColBandSeq);
-    hipLaunchKernelGGL(k_colmax_T_seq<Tin>, gc, dim3(64), 0, s, f, g.pitch, (const Tin *)rowmax, g.H, g.W,
-                       R, st, T_cap);
-  }
+  const GroupGrid gr = range_row_grid(g), gc = range_col_grid(g, R);
+  RowmaxArgs ra{gr, f, g.pitch, g.H, g.W, R, rowmax, st};
+  hipLaunchKernelGGL(k_rowmax<Tin>, dim3(gr.gx, gr.gy), dim3(64), 0, s, ra);
+  ColmaxArgs ca{gc, f, g.pitch, (const Tin *)rowmax, g.H, g.W, R, st, T_cap};
+  if (!range_col_seq(R))
+    hipLaunchKernelGGL(k_colmax_T<Tin>, dim3(gc.gx, gc.gy), dim3(256), 0, s, ca);
+  else
+    hipLaunchKernelGGL(k_colmax_T_seq<Tin>, dim3(gc.gx, gc.gy), dim3(64), 0, s, ca);
   rec.end(BF_STAGE_RANGE, s);
+  return hipGetLastError();
+}
+
+// Grouped range stage: the row pass of every image, then the column pass of
+// every image (all of one kind: LDS-tiled or sequential).
+template <typename Tin>
+static hipError_t range_group_t(hipStream_t s, bool seq, const RowmaxArgs *ra, const int *rstart, int rtotal,
+                                const ColmaxArgs *ca, const int *cstart, int ctotal, int n) {
+  if (rtotal > 0) hipLaunchKernelGGL(k_rowmax_grp<Tin>, dim3(rtotal), dim3(64), 0, s, ra, rstart, n);
+  if (ctotal > 0) {
+    if (!seq) hipLaunchKernelGGL(k_colmax_T_grp<Tin>, dim3(ctotal), dim3(256), 0, s, ca, cstart, n);
+    else hipLaunchKernelGGL(k_colmax_T_seq_grp<Tin>, dim3(ctotal), dim3(64), 0, s, ca, cstart, n);
+  }
+  return hipGetLastError();
+}
+hipError_t launch_range_group(hipStream_t s, bf_dtype dt, bool seq, const RowmaxArgs *ra, const int *rstart,
+                              int rtotal, const ColmaxArgs *ca, const int *cstart, int ctotal, int n) {
+  switch (dt) {
+    case BF_U8: return range_group_t<uint8_t>(s, seq, ra, rstart, rtotal, ca, cstart, ctotal, n);
+    case BF_U16: return range_group_t<uint16_t>(s, seq, ra, rstart, rtotal, ca, cstart, ctotal, n);
+    default: return range_group_t<float>(s, seq, ra, rstart, rtotal, ca, cstart, ctotal, n);
+  }
+}
+hipError_t launch_reset_group(hipStream_t s, const ResetArgs *a, const int *start, int total, int n) {
+  if (total > 0) hipLaunchKernelGGL(k_reset_grp, dim3(total), dim3(64), 0, s, a, start, n);
   return hipGetLastError();
 }
 

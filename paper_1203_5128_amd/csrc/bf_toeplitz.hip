@@ -102,9 +102,17 @@ __device__ __forceinline__ void tap_frag(const float *w, int R, int ks, int lane
 // bank conflicts), then the waves share the (16-row block, 16-column block)
 // products of all four planes.
 template <typename Tin, bool BF, bool SPLIT>
-__global__ __launch_bounds__(256) void k_toep_v(const Tin *__restrict__ f, Geom g, DevTables tab, DevState st,
-                                                const float *__restrict__ taps, int R, int nks, int rows, int ntx,
-                                                int ntiles, int per, int k0, void *__restrict__ Zv, size_t zplane) {
+__device__ __forceinline__ void toep_v_body(const ToepVArgs &a, const Blk b) {
+  const Tin *__restrict__ f = (const Tin *)a.f;
+  const Geom g = a.g;
+  const DevTables tab = a.tab;
+  const DevState st = a.st;
+  const float *__restrict__ taps = a.tc.taps;
+  const int R = a.tc.R, nks = a.tc.nks, rows = a.tc.rows;
+  const int ntx = a.ntx, ntiles = a.ntiles, per = a.per, k0 = a.k0;
+  void *__restrict__ Zv = a.Z;
+  const size_t zplane = a.zplane;
+
   typedef typename MT<BF>::T E;
   typedef typename MT<BF>::V V;
   typedef typename std::conditional<SPLIT, float, E>::type ZT;
@@ -112,9 +120,9 @@ __global__ __launch_bounds__(256) void k_toep_v(const Tin *__restrict__ f, Geom 
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float2 lut[PhaseLut<Tin>::kOn ? 256 : 1];
   __shared__ float wsh[kMaxTaps];
-  const int t = xcd_tile(blockIdx.x, per);
+  const int t = xcd_tile(b.x, per);
   if (t >= ntiles) return;
-  const int kl = blockIdx.y;
+  const int kl = b.y;
   const OrderEntry &e = lookup(tab, st.T_used);
   const int k = k0 + kl;
   if (k >= e.K) return;
@@ -224,6 +232,16 @@ __global__ __launch_bounds__(256) void k_toep_v(const Tin *__restrict__ f, Geom 
     }
   }
 }
+template <typename Tin, bool BF, bool SPLIT>
+__global__ __launch_bounds__(256) void k_toep_v(ToepVArgs a) {
+  toep_v_body<Tin, BF, SPLIT>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
+}
+template <typename Tin, bool BF, bool SPLIT>
+__global__ __launch_bounds__(256) void k_toep_v_grp(const ToepVArgs *__restrict__ a, const int *__restrict__ start,
+                                                    int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  toep_v_body<Tin, BF, SPLIT>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+}
 
 // -------------------------------------------------- horizontal pass + combine
 // Workgroup: 16 rows x kHCols output columns and one group of consecutive
@@ -237,11 +255,20 @@ __global__ __launch_bounds__(256) void k_toep_v(const Tin *__restrict__ f, Geom 
 // otherwise it leaves its partial sums in PQ[group] (added to what the
 // previous launch left there unless `first`).
 template <typename Tin, bool BF, bool SPLIT>
-__global__ __launch_bounds__(256) void k_toep_h(const Tin *__restrict__ f, float *__restrict__ out, Geom g,
-                                                DevTables tab, DevState st, const float *__restrict__ taps, int R,
-                                                int nks, int ntx, int ntiles, int per, int k0, int kcount, int kpg,
-                                                const void *__restrict__ Zv, size_t zplane,
-                                                float2 *__restrict__ PQ, int first, int finish) {
+__device__ __forceinline__ void toep_h_body(const ToepHArgs &a, const Blk b) {
+  const Tin *__restrict__ f = (const Tin *)a.f;
+  float *__restrict__ out = a.out;
+  const Geom g = a.g;
+  const DevTables tab = a.tab;
+  const DevState st = a.st;
+  const float *__restrict__ taps = a.tc.taps;
+  const int R = a.tc.R, nks = a.tc.nks, kpg = a.tc.kpg;
+  const int ntx = a.ntx, ntiles = a.ntiles, per = a.per, k0 = a.k0, kcount = a.kcount;
+  const void *__restrict__ Zv = a.Z;
+  const size_t zplane = a.zplane;
+  float2 *__restrict__ PQ = a.PQ;
+  const int first = a.first, finish = a.finish;
+
   typedef typename MT<BF>::T E;
   typedef typename MT<BF>::V V;
   typedef typename std::conditional<SPLIT, float, E>::type ZT;
@@ -250,10 +277,10 @@ __global__ __launch_bounds__(256) void k_toep_h(const Tin *__restrict__ f, float
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float2 lut[PhaseLut<Tin>::kOn ? 256 : 1];
   __shared__ float wsh[kMaxTaps];
-  const int t = xcd_tile(blockIdx.x, per);
+  const int t = xcd_tile(b.x, per);
   if (t >= ntiles) return;
   const OrderEntry &e = lookup(tab, st.T_used);
-  const int kb = k0 + blockIdx.y * kpg;
+  const int kb = k0 + b.y * kpg;
   const int kend = min(min(kb + kpg, k0 + kcount), e.K);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int x0 = (t % ntx) * kCols;
@@ -390,7 +417,7 @@ __global__ __launch_bounds__(256) void k_toep_h(const Tin *__restrict__ f, float
     }
   }
   if (kb >= kend && !first && !finish) return;  // no pairs here: partial sums unchanged
-  float2 *PQg = PQ + (size_t)blockIdx.y * g.H * g.W;
+  float2 *PQg = PQ + (size_t)b.y * g.H * g.W;
   unsigned long long nbad = 0;
 #pragma unroll
   for (int b = 0; b < kNbw; b++)
@@ -424,14 +451,30 @@ __global__ __launch_bounds__(256) void k_toep_h(const Tin *__restrict__ f, float
     if (lane == 0 && nbad) atomicAdd(st.q_nonpos, nbad);
   }
 }
+template <typename Tin, bool BF, bool SPLIT>
+__global__ __launch_bounds__(256) void k_toep_h(ToepHArgs a) {
+  toep_h_body<Tin, BF, SPLIT>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
+}
+template <typename Tin, bool BF, bool SPLIT>
+__global__ __launch_bounds__(256) void k_toep_h_grp(const ToepHArgs *__restrict__ a, const int *__restrict__ start,
+                                                    int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  toep_h_body<Tin, BF, SPLIT>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+}
 
 // Sum of the groups' partial numerators and denominators, then eqs. (f1),
 // (f2) divided out: one thread per pixel.
 template <typename Tin>
-__global__ __launch_bounds__(256) void k_toep_finish(const Tin *__restrict__ f, float *__restrict__ out, Geom g,
-                                                     DevState st, const float2 *__restrict__ PQ, int groups) {
+__device__ __forceinline__ void toep_finish_body(const FinishArgs &a, const Blk b) {
+  const Tin *__restrict__ f = (const Tin *)a.f;
+  float *__restrict__ out = a.out;
+  const Geom g = a.g;
+  const DevState st = a.st;
+  const float2 *__restrict__ PQ = a.PQ;
+  const int groups = a.groups;
+
   const int64_t npx = (int64_t)g.H * g.W;
-  const int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t pix = (int64_t)b.x * 256 + threadIdx.x;
   unsigned long long nbad = 0;
   if (pix < npx) {
     float Pv = 0.f, Qv = 0.f;
@@ -454,6 +497,16 @@ __global__ __launch_bounds__(256) void k_toep_finish(const Tin *__restrict__ f, 
   for (int off = 32; off > 0; off >>= 1) nbad += __shfl_xor(nbad, off, 64);
   if ((threadIdx.x & 63) == 0 && nbad) atomicAdd(st.q_nonpos, nbad);
 }
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_toep_finish(FinishArgs a) {
+  toep_finish_body<Tin>(a, Blk{(int)blockIdx.x, 0, 0});
+}
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_toep_finish_grp(const FinishArgs *__restrict__ a,
+                                                         const int *__restrict__ start, int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  toep_finish_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+}
 
 // ------------------------------------------------------------- launchers
 static bool split_of(int variant) { return variant == BF_BLUR_TOEPLITZ_F16X2 || variant == BF_BLUR_TOEPLITZ_BF16X2; }
@@ -475,6 +528,29 @@ int toeplitz_h_tiles(int variant, int H, int W) {
   return ((W + cols - 1) / cols) * ((H + kHRows - 1) / kHRows);
 }
 
+// Per-image arguments of the three Toeplitz kernels for pairs [k0, k0+kcount).
+void toeplitz_args(int variant, const void *f, float *out, const Geom &g, DevTables tab, DevState st,
+                   const ToepCfg &tc, int k0, int kcount, void *Z, float2 *PQ, bool first, bool last,
+                   ToepVArgs &va, ToepHArgs &ha, FinishArgs &fa) {
+  const bool split = split_of(variant);
+  const int vcols = split ? TShape<true>::kVCols : TShape<false>::kVCols;
+  const int hcols = split ? TShape<true>::kHCols : TShape<false>::kHCols;
+  const size_t zplane = (size_t)g.H * g.zpitch;
+  {
+    const int ntx = (g.W + vcols - 1) / vcols, nt = ntx * ((g.H + tc.rows - 1) / tc.rows), per = (nt + 7) / 8;
+    va = ToepVArgs{GroupGrid{8 * per, kcount, 1}, f, g, tab, st, tc, ntx, nt, per, k0, Z, zplane};
+  }
+  {
+    const int ntx = (g.W + hcols - 1) / hcols, nt = ntx * ((g.H + kHRows - 1) / kHRows), per = (nt + 7) / 8;
+    const bool finish = last && tc.groups == 1;
+    ha = ToepHArgs{GroupGrid{8 * per, tc.groups, 1}, f, out, g, tab, st, tc, ntx, nt, per, k0, kcount,
+                   (const void *)Z, zplane, PQ, (int)first, (int)finish};
+  }
+  const int64_t npx = (int64_t)g.H * g.W;
+  const int nfin = (last && tc.groups > 1) ? (int)((npx + 255) / 256) : 0;
+  fa = FinishArgs{GroupGrid{nfin > 0 ? nfin : 1, 1, 1}, f, out, g, st, (const float2 *)PQ, tc.groups};
+}
+
 template <typename Tin, bool BF, bool SPLIT>
 static hipError_t toep_t(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab, DevState st,
                          const ToepCfg &tc, int k0, int kcount, void *Z, float2 *PQ, bool first, bool last,
@@ -484,32 +560,58 @@ static hipError_t toep_t(hipStream_t s, const Tin *f, float *out, const Geom &g,
   if (tc.nks < 1 || tc.nks > 8 || 32 * tc.nks < 16 + 2 * tc.R || tc.rows < 16 || tc.rows % 16 || tc.groups < 1 ||
       tc.kpg < 1 || kcount < 1 || kcount > 65535 || tc.groups > 65535)
     return hipErrorInvalidValue;
-  const size_t zplane = (size_t)g.H * g.zpitch;
-  const size_t vl = toeplitz_v_lds(variant, tc.rows, tc.nks), hl = toeplitz_h_lds(variant, tc.nks);
+  ToepVArgs va;
+  ToepHArgs ha;
+  FinishArgs fa;
+  toeplitz_args(variant, f, out, g, tab, st, tc, k0, kcount, Z, PQ, first, last, va, ha, fa);
   rec.begin(BF_STAGE_TOEPLITZ, s);
-  {
-    constexpr int cols = TShape<SPLIT>::kVCols;
-    const int ntx = (g.W + cols - 1) / cols, nt = ntx * ((g.H + tc.rows - 1) / tc.rows), per = (nt + 7) / 8;
-    hipLaunchKernelGGL((k_toep_v<Tin, BF, SPLIT>), dim3(8 * per, kcount), dim3(256), vl, s, f, g, tab, st, tc.taps,
-                       tc.R, tc.nks, tc.rows, ntx, nt, per, k0, Z, zplane);
-  }
+  hipLaunchKernelGGL((k_toep_v<Tin, BF, SPLIT>), dim3(va.gg.gx, va.gg.gy), dim3(256),
+                     toeplitz_v_lds(variant, tc.rows, tc.nks), s, va);
   rec.end(BF_STAGE_TOEPLITZ, s);
   rec.begin(BF_STAGE_H_COMBINE, s);
-  {
-    constexpr int cols = TShape<SPLIT>::kHCols;
-    const int ntx = (g.W + cols - 1) / cols, nt = ntx * ((g.H + kHRows - 1) / kHRows), per = (nt + 7) / 8;
-    const bool finish = last && tc.groups == 1;
-    hipLaunchKernelGGL((k_toep_h<Tin, BF, SPLIT>), dim3(8 * per, tc.groups), dim3(256), hl, s, f, out, g, tab, st,
-                       tc.taps, tc.R, tc.nks, ntx, nt, per, k0, kcount, tc.kpg, (const void *)Z, zplane, PQ,
-                       (int)first, (int)finish);
-    if (last && !finish) {
-      const int64_t npx = (int64_t)g.H * g.W;
-      hipLaunchKernelGGL((k_toep_finish<Tin>), dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, f, out, g, st,
-                         (const float2 *)PQ, tc.groups);
-    }
-  }
+  hipLaunchKernelGGL((k_toep_h<Tin, BF, SPLIT>), dim3(ha.gg.gx, ha.gg.gy), dim3(256), toeplitz_h_lds(variant, tc.nks),
+                     s, ha);
+  if (last && !ha.finish) hipLaunchKernelGGL((k_toep_finish<Tin>), dim3(fa.gg.gx), dim3(256), 0, s, fa);
   rec.end(BF_STAGE_H_COMBINE, s);
   return hipGetLastError();
+}
+
+// Grouped Toeplitz stages over n images of one dtype and variant: the
+// vertical pass of all, the horizontal pass of all, then the finishing sums
+// of the images that split their pairs into several groups.
+template <typename Tin, bool BF, bool SPLIT>
+static hipError_t toep_group_t(hipStream_t s, const ToepGroup &tg, const StageRec &rec) {
+  rec.begin(BF_STAGE_TOEPLITZ, s);
+  if (tg.vtotal > 0)
+    hipLaunchKernelGGL((k_toep_v_grp<Tin, BF, SPLIT>), dim3(tg.vtotal), dim3(256), tg.vlds, s, tg.va, tg.vstart,
+                       tg.n);
+  rec.end(BF_STAGE_TOEPLITZ, s);
+  rec.begin(BF_STAGE_H_COMBINE, s);
+  if (tg.htotal > 0)
+    hipLaunchKernelGGL((k_toep_h_grp<Tin, BF, SPLIT>), dim3(tg.htotal), dim3(256), tg.hlds, s, tg.ha, tg.hstart,
+                       tg.n);
+  if (tg.ftotal > 0)
+    hipLaunchKernelGGL((k_toep_finish_grp<Tin>), dim3(tg.ftotal), dim3(256), 0, s, tg.fa, tg.fstart, tg.n);
+  rec.end(BF_STAGE_H_COMBINE, s);
+  return hipGetLastError();
+}
+template <typename Tin>
+static hipError_t toep_group_dt(hipStream_t s, int variant, const ToepGroup &tg, const StageRec &rec) {
+  switch (variant) {
+    case BF_BLUR_TOEPLITZ_F16: return toep_group_t<Tin, false, false>(s, tg, rec);
+    case BF_BLUR_TOEPLITZ_BF16: return toep_group_t<Tin, true, false>(s, tg, rec);
+    case BF_BLUR_TOEPLITZ_F16X2: return toep_group_t<Tin, false, true>(s, tg, rec);
+    case BF_BLUR_TOEPLITZ_BF16X2: return toep_group_t<Tin, true, true>(s, tg, rec);
+    default: return hipErrorInvalidValue;
+  }
+}
+hipError_t launch_toeplitz_group(hipStream_t s, bf_dtype dt, int variant, const ToepGroup &tg,
+                                 const StageRec &rec) {
+  switch (dt) {
+    case BF_U8: return toep_group_dt<uint8_t>(s, variant, tg, rec);
+    case BF_U16: return toep_group_dt<uint16_t>(s, variant, tg, rec);
+    default: return toep_group_dt<float>(s, variant, tg, rec);
+  }
 }
 
 // Dynamic LDS above 64 KB must be allowed per kernel before its launch: the
@@ -523,7 +625,10 @@ static hipError_t allow_one(const void *fn) {
 template <typename Tin, bool BF, bool SPLIT>
 static hipError_t allow_lds() {
   hipError_t e = allow_one((const void *)k_toep_v<Tin, BF, SPLIT>);
-  return e == hipSuccess ? allow_one((const void *)k_toep_h<Tin, BF, SPLIT>) : e;
+  if (e == hipSuccess) e = allow_one((const void *)k_toep_h<Tin, BF, SPLIT>);
+  if (e == hipSuccess) e = allow_one((const void *)k_toep_v_grp<Tin, BF, SPLIT>);
+  if (e == hipSuccess) e = allow_one((const void *)k_toep_h_grp<Tin, BF, SPLIT>);
+  return e;
 }
 template <typename Tin>
 static hipError_t allow_lds_dt() {

@@ -1,0 +1,169 @@
+"""GPU batches: images of uneven sizes with per-image sigma_s, sigma_r (and
+dtypes and variants) filtered by one bf_filter_batch call.
+
+Images on the Toeplitz path run as grouped launches (one launch per stage for
+all of them); each grouped output must equal, bit for bit, the same image
+filtered alone by its own plan, and match the FP64 oracle within the
+variant's tolerance.  Images on the recursive path in the same batch run
+their own launch sequences inside the same graph.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as o
+from bfsynth import CONFIGS, batch_images, gen_random
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"iir_f32": 2e-3, "toeplitz_f16x2": 2e-3, "toeplitz_bf16x2": 2.0 ** 11 * 2.0 ** -16,
+       "toeplitz_f16": 2.0 ** 11 * 2.0 ** -11, "toeplitz_bf16": 2.0 ** 11 * 2.0 ** -8}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _single(img, p):
+    torch = _torch()
+    from paper_1203_5128_amd import Plan
+    plan = Plan.create(p)
+    out, rep = plan.filter(torch.from_numpy(np.ascontiguousarray(img)).to("cuda"))
+    torch.cuda.synchronize()
+    plan.close()
+    return out.cpu().numpy(), rep
+
+
+def _oracle(img, dtype, blur, ss, sr, eps, R):
+    rng_ = 65535.0 if dtype == "u16" else 255.0
+    op = "iir" if blur == "iir_f32" else "fir"
+    return o.algorithm2(img.astype(np.float64), op, ss, R, sr, eps, rng_, True)
+
+
+MIXED = [  # (seed, H, W, dtype, blur, sigma_s, sigma_r)
+    (1, 150, 190, "u8", "toeplitz_f16x2", 2.5, 20.0),
+    (2, 97, 260, "u8", "toeplitz_f16x2", 5.0, 35.0),
+    (3, 200, 64, "f32", "toeplitz_f16x2", 3.0, 15.0),
+    (4, 130, 130, "u8", "toeplitz_f16", 4.0, 25.0),
+    (5, 64, 300, "u16", "toeplitz_bf16x2", 2.0, 25.0 * 257),
+    (6, 120, 140, "u8", "iir_f32", 3.5, 30.0),
+    (7, 33, 45, "u8", "toeplitz_f16x2", 1.5, 12.0),
+    (8, 180, 100, "u8", "toeplitz_f16x2", 16.0, 50.0),  # R = 48: sequential column pass of the range stage
+    (9, 90, 90, "f32", "toeplitz_f16", 6.0, 40.0),
+]
+
+
+def _mixed_batch():
+    imgs, params = [], []
+    from paper_1203_5128_amd import make_params
+    for seed, H, W, dt, blur, ss, sr in MIXED:
+        imgs.append(gen_random(300 + seed, H, W, dtype=dt))
+        params.append(make_params(H, W, dt, sigma_s=ss, sigma_r=sr, eps=1e-3, blur=blur))
+    return imgs, params
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_mixed_batch_equals_single_images_and_oracle(graph):
+    torch = _torch()
+    from paper_1203_5128_amd import Plan
+    imgs, params = _mixed_batch()
+    if not graph:
+        os.environ["BF_GRAPH"] = "0"
+    try:
+        plan = Plan.create(params)
+    finally:
+        os.environ.pop("BF_GRAPH", None)
+    outs, reps = plan.filter_batch([torch.from_numpy(im).to("cuda") for im in imgs])
+    torch.cuda.synchronize()
+    plan.close()
+    for (seed, H, W, dt, blur, ss, sr), im, p, out, rep in zip(MIXED, imgs, params, outs, reps):
+        got = out.cpu().numpy()
+        alone, rep1 = _single(im, p)
+        assert rep["variant"] == blur and (rep["T"], rep["N"], rep["M"]) == (rep1["T"], rep1["N"], rep1["M"])
+        assert np.array_equal(got, alone), f"batch output differs from the single-image plan ({blur} {H}x{W})"
+        R = int(np.ceil(3 * ss))
+        ref = _oracle(im, dt, blur, ss, sr, 1e-3, R)
+        assert (rep["N"], rep["M"]) == (ref["N"], ref["M"]) and rep["T"] == ref["T"]
+        sc = 257.0 if dt == "u16" else 1.0
+        err = np.abs(got.astype(np.float64) - ref["out"]).max()
+        print(f"[batch] {blur} {dt} {H}x{W} ss={ss} sr={sr} T={rep['T']} pairs={rep['pairs']} max={err:.3e}",
+              flush=True)
+        assert err <= TOL[blur] * sc
+        assert rep["q_nonpos"] == ref["n_nonpos"]
+
+
+def test_batch_graph_replays_and_prefix():
+    """Replays of the captured batch equal the eager batch bit for bit, and a
+    call over the first n images of the plan filters exactly those."""
+    torch = _torch()
+    from paper_1203_5128_amd import Plan
+    imgs, params = _mixed_batch()
+    xs = [torch.from_numpy(im).to("cuda") for im in imgs]
+    os.environ["BF_GRAPH"] = "0"
+    try:
+        pe = Plan.create(params)
+    finally:
+        os.environ.pop("BF_GRAPH", None)
+    eager, _ = pe.filter_batch(xs)
+    torch.cuda.synchronize()
+    pe.close()
+    pg = Plan.create(params)
+    outs = [torch.empty(x.shape, dtype=torch.float32, device="cuda") for x in xs]
+    for _ in range(3):
+        for t in outs:
+            t.fill_(-1.0)
+        pg.filter_batch(xs, outs, report=False)
+        torch.cuda.synchronize()
+        for a, b in zip(outs, eager):
+            assert torch.equal(a, b)
+        _ = (xs[0].float() * 3).sum().item()
+    part = [torch.full(x.shape, -7.0, dtype=torch.float32, device="cuda") for x in xs]
+    pg.filter_batch(xs[:4], part[:4], report=False)
+    torch.cuda.synchronize()
+    for i in range(4):
+        assert torch.equal(part[i], eager[i])
+    for i in range(4, len(xs)):
+        assert bool((part[i] == -7.0).all())
+    pg.close()
+
+
+def test_workload5_batch64_grouped_sampled():
+    """The 64-image workload (sizes 128..1024 per axis, per-image sigma_s in
+    [2,16] and sigma_r in [10,60]) as one grouped batch on the split FP16
+    variant: T, N, M of every image exactly, outputs at sampled pixels against
+    eq. (BF) evaluated directly, and the first two images in full."""
+    torch = _torch()
+    from paper_1203_5128_amd import Plan, make_params
+    items = batch_images()
+    assert len(items) == CONFIGS[5]["n_images"]
+    params = [make_params(im.shape[0], im.shape[1], "u8", sigma_s=ss, sigma_r=sr, eps=1e-3,
+                          blur="toeplitz_f16x2") for im, ss, sr in items]
+    plan = Plan.create(params)
+    outs, reps = plan.filter_batch([torch.from_numpy(im).to("cuda") for im, _, _ in items])
+    torch.cuda.synchronize()
+    plan.close()
+    rng = np.random.default_rng(55)
+    worst = 0.0
+    for i, ((im, ss, sr), out, rep) in enumerate(zip(items, outs, reps)):
+        f = im.astype(np.float64)
+        R = int(np.ceil(3 * ss))
+        T = o.range_T(f, R)
+        N = o.order(T, sr)
+        M = o.trunc_rule(N, sr, 1e-3)
+        assert (rep["T"], rep["N"], rep["M"]) == (T, N, M)
+        got = out.cpu().numpy().astype(np.float64)
+        H, W = im.shape
+        ys = np.concatenate([rng.integers(0, H, 40), [0, H - 1]])
+        xs = np.concatenate([rng.integers(0, W, 40), [W - 1, 0]])
+        ref = o.direct_fir_at(f, ss, R, N, M, sr, ys, xs)
+        err = np.abs(got[ys, xs] - ref).max()
+        worst = max(worst, err)
+        assert err <= 2e-3, (i, err)
+        if i < 2:
+            full = o.algorithm2(f, "fir", ss, R, sr, 1e-3, 255.0, True)
+            assert np.abs(got - full["out"]).max() <= 2e-3
+    print(f"[batch] workload5 64 images sampled max={worst:.3e}", flush=True)

@@ -284,3 +284,35 @@ def test_xcd_tile_map_is_a_bijection(n):
     per = (n + 7) // 8
     tiles = [xcd_tile(i, per) for i in range(8 * per)]
     assert sorted(t for t in tiles if t < n) == list(range(n))
+
+
+def group_find(start, n, bid):
+    lo, hi = 0, n - 1
+    while lo < hi:
+        mid = (lo + hi + 1) >> 1
+        if start[mid] <= bid:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
+
+
+@pytest.mark.parametrize("blocks", [[1], [3, 0, 5], [0, 0, 4, 0], [7, 1, 1, 9, 2], [0, 8, 0, 0, 8]])
+def test_grouped_launch_block_map(blocks):
+    """Blocks of a grouped launch -> (image, local block), as the grouped
+    kernels decompose them: every local block of every image exactly once,
+    images without blocks skipped."""
+    start = np.concatenate([[0], np.cumsum(blocks)]).astype(int)
+    n = len(blocks)
+    seen = []
+    for bid in range(start[-1]):
+        i = group_find(start, n, bid)
+        assert start[i] <= bid < start[i + 1]
+        seen.append((i, bid - start[i]))
+    assert seen == [(i, l) for i in range(n) for l in range(blocks[i])]
+
+
+@pytest.mark.parametrize("gx,gy,gz", [(1, 1, 1), (8, 3, 1), (5, 7, 2)])
+def test_group_grid_decomposition(gx, gy, gz):
+    got = [(l % gx, (l // gx) % gy, l // (gx * gy)) for l in range(gx * gy * gz)]
+    assert sorted(got) == [(x, y, z) for x in range(gx) for y in range(gy) for z in range(gz)]
