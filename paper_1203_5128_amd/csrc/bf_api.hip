@@ -1,10 +1,13 @@
 // Plan runtime and C ABI of libbf.so (declared in include/bf.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -62,12 +65,13 @@ bool is_split(int v) { return v == BF_BLUR_TOEPLITZ_F16X2 || v == BF_BLUR_TOEPLI
 // Tile shape of the Toeplitz path for radius R: the tallest vertical tile
 // (fewest recomputed halo rows) whose LDS leaves room for two workgroups per
 // CU, else for one.  False when the band of 2R+1 taps does not fit.
-bool toeplitz_shape(int variant, int R, int H, ToepCfg &tc) {
+bool toeplitz_shape(int variant, int R, int H, int lds_kb, ToepCfg &tc) {
   tc.R = R;
   tc.nks = (16 + 2 * R + 31) / 32;
   if (tc.nks > 8) return false;
   size_t pref = (size_t)kToepLdsMax / 2 - 2048;  // two workgroups per CU with their static tables
   if (const char *b = std::getenv("BF_TOEP_LDS_KB")) pref = (size_t)std::atoi(b) << 10;
+  if (lds_kb > 0) pref = (size_t)lds_kb << 10;
   const int top = std::min(256, (H + 15) / 16 * 16);
   tc.rows = 0;
   for (size_t budget : {std::min(pref, (size_t)kToepDynMax), (size_t)kToepDynMax}) {
@@ -180,7 +184,14 @@ bf_status upload(void **dst, const void *src, size_t bytes) {
   return BF_OK;
 }
 
-bf_status prepare_image(const bf_params &p, ImagePlan &ip) {
+// Per-image choices the autotuner makes (0 = default).
+struct Knobs {
+  int variant = 0;  // bf_blur other than AUTO
+  int hchunk = 0;   // pixels per thread of the recursive horizontal pass (16 or 32)
+  int lds_kb = 0;   // preferred LDS of a Toeplitz vertical tile
+};
+
+bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   ip.p = p;
   const double full = p.dtype == BF_U16 ? 65535.0 : 255.0;
   ip.range = p.value_range > 0.0 ? p.value_range : full;
@@ -195,11 +206,11 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip) {
   ip.T_cap = (int32_t)cap;
   ip.T_global = (int32_t)std::ceil(Tg);
   ip.T_global_raw = Tg;
-  int variant = p.blur == BF_BLUR_AUTO ? BF_BLUR_IIR_F32 : p.blur;
+  int variant = kn.variant ? kn.variant : (p.blur == BF_BLUR_AUTO ? BF_BLUR_IIR_F32 : p.blur);
   ip.variant = variant;
   if (!is_toeplitz(variant) && p.width > kMaxWidth)
     return fail(BF_ERR_UNSUPPORTED, "width above 8192 for the recursive blur");
-  if (is_toeplitz(variant) && !toeplitz_shape(variant, ip.R, p.height, ip.tc))
+  if (is_toeplitz(variant) && !toeplitz_shape(variant, ip.R, p.height, kn.lds_kb, ip.tc))
     return fail(BF_ERR_UNSUPPORTED, "radius above 120 for the Toeplitz blur");
   std::string err;
   if (!build_order_table(p.sigma_r, p.eps, ip.range, ip.T_cap, ip.tab, err)) return fail(BF_ERR_UNSUPPORTED, err);
@@ -221,6 +232,7 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip) {
   // registers (more waves in flight) but twice the scan steps per pixel
   int cC = kCSmall;
   if (const char *c = std::getenv("BF_HCHUNK")) cC = std::atoi(c) == kCLarge ? kCLarge : kCSmall;
+  if (kn.hchunk) cC = kn.hchunk == kCLarge ? kCLarge : kCSmall;
   if (g.W > kCSmall * kHThreads) cC = kCLarge;
   int S = 1, logS = 0;
   while (S * cC < g.W) { S <<= 1; logS++; }
@@ -671,20 +683,20 @@ const char *bf_status_string(bf_status s) {
 
 const char *bf_last_error_detail(void) { return g_detail.c_str(); }
 
-bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out) {
-  if (!out) return fail(BF_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  if (!params || n_images < 1) return fail(BF_ERR_INVALID_ARG, "params NULL or n_images < 1");
-  for (int i = 0; i < n_images; i++) {
-    bf_status s = check_params(params[i]);
-    if (s) return s;
-  }
+}  // extern "C"
+
+namespace {
+bf_status autotune(const bf_params &p, Knobs &kn);
+}
+
+// Plan creation with explicit per-image knobs (the autotuner's choices).
+static bf_status create_plan(const bf_params *params, int32_t n_images, const Knobs *knobs, bf_plan_t *out) {
   bf_plan_s *pl = new bf_plan_s();
   (void)hipGetDevice(&pl->device);
   pl->im.resize(n_images);
   size_t rowmax = 0, cb = 0, Z = 0, PQ = 0, lut = 0;
   for (int i = 0; i < n_images; i++) {
-    bf_status s = prepare_image(params[i], pl->im[i]);
+    bf_status s = prepare_image(params[i], pl->im[i], knobs ? knobs[i] : Knobs());
     if (s) {
       bf_plan_destroy(pl);
       return s;
@@ -743,6 +755,25 @@ bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out) {
   }
   *out = pl;
   return BF_OK;
+}
+
+extern "C" {
+
+bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out) {
+  if (!out) return fail(BF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!params || n_images < 1) return fail(BF_ERR_INVALID_ARG, "params NULL or n_images < 1");
+  for (int i = 0; i < n_images; i++) {
+    bf_status s = check_params(params[i]);
+    if (s) return s;
+  }
+  std::vector<Knobs> kn(n_images);
+  for (int i = 0; i < n_images; i++)
+    if (params[i].blur == BF_BLUR_AUTO) {
+      bf_status s = autotune(params[i], kn[i]);
+      if (s) return s;
+    }
+  return create_plan(params, n_images, kn.data(), out);
 }
 
 bf_status bf_profile(bf_plan_t pl, int32_t enable) {
@@ -862,3 +893,160 @@ bf_status bf_dynamic_range(bf_plan_t pl, const void *d_in, void *hip_stream, dou
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------- autotuner
+// BF_BLUR_AUTO: among the variants whose worst error over the parity suite
+// (adversarial noise included) stays within the 2e-3 target -- the FP32
+// recursive blur and the split-FP16 Toeplitz blur -- and their tile choices
+// (horizontal chunk of the recursive pass, LDS budget of the Toeplitz
+// vertical tile), take the fastest on this device at the image's shape and
+// dtype with every pair kept (T at the full range).  Choices are cached in
+// the process and, when BF_TUNE_CACHE names a file, in that file (one JSON
+// object per line).
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, Knobs> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const bf_params &p) {
+  char arch[64] = "gfx";
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "%s|d%d|%dx%d|ss%.9g|sr%.9g|e%.9g|R%d|t%d|tv%.9g|vr%.9g", arch, (int)p.dtype,
+                p.height, p.width, p.sigma_s, p.sigma_r, p.eps, p.radius, (int)p.t_mode, p.t_value, p.value_range);
+  return buf;
+}
+
+void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *path = std::getenv("BF_TUNE_CACHE");
+  if (!path) return;
+  FILE *fp = std::fopen(path, "r");
+  if (!fp) return;
+  char line[1024];
+  while (std::fgets(line, sizeof(line), fp)) {
+    const char *k = std::strstr(line, "\"key\": \"");
+    if (!k) continue;
+    k += 8;
+    const char *e = std::strchr(k, '"');
+    if (!e) continue;
+    Knobs kn;
+    const char *v = std::strstr(e, "\"variant\": ");
+    const char *h = std::strstr(e, "\"hchunk\": ");
+    const char *l = std::strstr(e, "\"lds_kb\": ");
+    if (!v || !h || !l) continue;
+    kn.variant = std::atoi(v + 11);
+    kn.hchunk = std::atoi(h + 10);
+    kn.lds_kb = std::atoi(l + 10);
+    if (kn.variant == BF_BLUR_IIR_F32 || kn.variant == BF_BLUR_TOEPLITZ_F16X2) g_tune[std::string(k, e)] = kn;
+  }
+  std::fclose(fp);
+}
+
+void tune_save(const std::string &key, const Knobs &kn, double ms) {
+  const char *path = std::getenv("BF_TUNE_CACHE");
+  if (!path) return;
+  FILE *fp = std::fopen(path, "a");
+  if (!fp) return;
+  std::fprintf(fp, "{\"key\": \"%s\", \"variant\": %d, \"hchunk\": %d, \"lds_kb\": %d, \"ms\": %.6f}\n",
+               key.c_str(), kn.variant, kn.hchunk, kn.lds_kb, ms);
+  std::fclose(fp);
+}
+
+// Device time of one filter call of a candidate (median of 5 after warm-up), or
+// a negative value when the candidate cannot run this image.
+double time_candidate(const bf_params &p, const Knobs &kn, void *d_in, float *d_out, hipStream_t s, hipEvent_t a,
+                      hipEvent_t b) {
+  bf_params q = p;
+  q.blur = (bf_blur)kn.variant;
+  q.in_pitch = q.out_pitch = 0;
+  if (q.t_mode == BF_T_LOCAL) {  // every pair kept: T at the full range
+    q.t_mode = BF_T_GLOBAL;
+    q.t_value = 0.0;
+  }
+  bf_plan_t pl = nullptr;
+  if (create_plan(&q, 1, &kn, &pl) != BF_OK) return -1.0;
+  std::vector<float> t;
+  bool ok = true;
+  for (int r = 0; r < 7 && ok; r++) {
+    ok = hipEventRecord(a, s) == hipSuccess && run_image(pl, pl->im[0], d_in, d_out, s) == BF_OK &&
+         hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+    float ms = 0.f;
+    if (ok && hipEventElapsedTime(&ms, a, b) == hipSuccess && r >= 2) t.push_back(ms);
+  }
+  bf_plan_destroy(pl);
+  if (!ok || t.empty()) return -1.0;
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
+bf_status autotune(const bf_params &p, Knobs &best) {
+  const std::string key = tune_key(p);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      best = it->second;
+      return BF_OK;
+    }
+  }
+  std::vector<Knobs> cand;
+  const int R = p.radius > 0 ? p.radius : (int)std::ceil(3.0 * p.sigma_s);
+  if (p.width <= kMaxWidth && p.sigma_s >= 0.5) {
+    cand.push_back(Knobs{BF_BLUR_IIR_F32, kCSmall, 0});
+    if (p.width > kCSmall) cand.push_back(Knobs{BF_BLUR_IIR_F32, kCLarge, 0});
+  }
+  if (R <= 120) {
+    cand.push_back(Knobs{BF_BLUR_TOEPLITZ_F16X2, 0, kToepLdsMax / 2048 - 2});
+    cand.push_back(Knobs{BF_BLUR_TOEPLITZ_F16X2, 0, kToepDynMax / 1024});
+  }
+  if (cand.empty()) return fail(BF_ERR_UNSUPPORTED, "no blur variant supports these parameters");
+  if (cand.size() == 1) {
+    best = cand[0];
+    return BF_OK;
+  }
+  // a full-range input: alternating 0 and the top of the range
+  const size_t px = (size_t)p.height * p.width;
+  void *d_in = nullptr;
+  float *d_out = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipMalloc(&d_in, px * elem_size(p.dtype));
+  if (e == hipSuccess) e = hipMalloc((void **)&d_out, px * sizeof(float));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  const double full = p.dtype == BF_U16 ? 65535.0 : 255.0;
+  const double range = p.value_range > 0.0 ? p.value_range : full;
+  if (e == hipSuccess) e = launch_fill_checker(s, p.dtype, d_in, p.height, p.width, range);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  double best_ms = -1.0;
+  if (e == hipSuccess) {
+    for (const Knobs &kn : cand) {
+      const double ms = time_candidate(p, kn, d_in, d_out, s, a, b);
+      if (ms > 0.0 && (best_ms < 0.0 || ms < best_ms)) {
+        best_ms = ms;
+        best = kn;
+      }
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (s) (void)hipStreamDestroy(s);
+  (void)hipFree(d_in);
+  (void)hipFree(d_out);
+  if (e != hipSuccess) return dev_fail(e, "autotune");
+  if (best_ms < 0.0) best = cand[0];
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = best;
+  tune_save(key, best, best_ms);
+  return BF_OK;
+}
+
+}  // namespace

@@ -156,6 +156,7 @@ struct StageRec {
 };
 
 // ---- launch wrappers (bf_kernels.hip) ----
+hipError_t launch_fill_checker(hipStream_t s, bf_dtype dt, void *f, int H, int W, double top);
 hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw);
 hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,
                         DevState st, int32_t T_cap, const StageRec &rec);

@@ -873,6 +873,25 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
 }
 
 // ------------------------------------------------------------- launchers
+// Full-range test input of the autotuner: 0 and `top` alternating like a
+// checkerboard, so that every window spans the whole range.
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_fill_checker(Tin *__restrict__ f, int H, int W, float top) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)H * W) return;
+  const int y = (int)(i / W), x = (int)(i % W);
+  f[i] = ((x ^ y) & 1) ? (Tin)top : (Tin)0;
+}
+hipError_t launch_fill_checker(hipStream_t s, bf_dtype dt, void *f, int H, int W, double top) {
+  const unsigned nb = (unsigned)(((int64_t)H * W + 255) / 256);
+  switch (dt) {
+    case BF_U8: hipLaunchKernelGGL(k_fill_checker<uint8_t>, dim3(nb), dim3(256), 0, s, (uint8_t *)f, H, W, (float)top); break;
+    case BF_U16: hipLaunchKernelGGL(k_fill_checker<uint16_t>, dim3(nb), dim3(256), 0, s, (uint16_t *)f, H, W, (float)top); break;
+    default: hipLaunchKernelGGL(k_fill_checker<float>, dim3(nb), dim3(256), 0, s, (float *)f, H, W, (float)top); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw) {
   ResetArgs a{GroupGrid{1, 1, 1}, st, T_used, T_raw};
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a);

@@ -167,3 +167,56 @@ def test_workload5_batch64_grouped_sampled():
             full = o.algorithm2(f, "fir", ss, R, sr, 1e-3, 255.0, True)
             assert np.abs(got - full["out"]).max() <= 2e-3
     print(f"[batch] workload5 64 images sampled max={worst:.3e}", flush=True)
+
+
+def test_autotune_picks_a_gated_variant_and_caches(tmp_path):
+    """BF_BLUR_AUTO takes the fastest of the variants that meet the 2e-3
+    target (FP32 recursive, split-FP16 Toeplitz); the output matches the
+    oracle run with the chosen operator, and the choice is written to and
+    read back from the cache file."""
+    torch = _torch()
+    from paper_1203_5128_amd import Plan, make_params
+    cache = tmp_path / "tune.jsonl"
+    os.environ["BF_TUNE_CACHE"] = str(cache)
+    try:
+        img = gen_random(61, 200, 330, dtype="u8")
+        p = make_params(200, 330, "u8", sigma_s=4.0, sigma_r=20.0, eps=1e-3, blur="auto")
+        plan = Plan.create(p)
+        out, rep = plan.filter(torch.from_numpy(img).to("cuda"))
+        torch.cuda.synchronize()
+        plan.close()
+        assert rep["variant"] in ("iir_f32", "toeplitz_f16x2")
+        lines = cache.read_text().strip().splitlines()
+        assert len(lines) == 1 and '"key": ' in lines[0]
+        ref = _oracle(img, "u8", rep["variant"], 4.0, 20.0, 1e-3, 12)
+        err = np.abs(out.cpu().numpy().astype(np.float64) - ref["out"]).max()
+        print(f"[tune] chose {rep['variant']} max={err:.3e} ({lines[0]})", flush=True)
+        assert err <= 2e-3
+        plan2 = Plan.create(p)  # served from the cache: no new line
+        _, rep2 = plan2.filter(torch.from_numpy(img).to("cuda"))
+        torch.cuda.synchronize()
+        plan2.close()
+        assert rep2["variant"] == rep["variant"]
+        assert len(cache.read_text().strip().splitlines()) == 1
+    finally:
+        os.environ.pop("BF_TUNE_CACHE", None)
+
+
+def test_autotuned_batch_uneven():
+    """A batch planned with AUTO for every image (each tuned on its own shape
+    and parameters) against the oracle with each image's chosen operator."""
+    torch = _torch()
+    from paper_1203_5128_amd import Plan, make_params
+    items = [(im[:min(im.shape[0], 300), :min(im.shape[1], 280)].copy(), ss, sr) for im, ss, sr in batch_images(6)]
+    params = [make_params(im.shape[0], im.shape[1], "u8", sigma_s=ss, sigma_r=sr, eps=1e-3, blur="auto")
+              for im, ss, sr in items]
+    plan = Plan.create(params)
+    outs, reps = plan.filter_batch([torch.from_numpy(im).to("cuda") for im, _, _ in items])
+    torch.cuda.synchronize()
+    plan.close()
+    for (im, ss, sr), out, rep in zip(items, outs, reps):
+        assert rep["variant"] in ("iir_f32", "toeplitz_f16x2")
+        ref = _oracle(im, "u8", rep["variant"], ss, sr, 1e-3, int(np.ceil(3 * ss)))
+        err = np.abs(out.cpu().numpy().astype(np.float64) - ref["out"]).max()
+        print(f"[tune] batch {im.shape} ss={ss:.2f} sr={sr:.2f} -> {rep['variant']} max={err:.3e}", flush=True)
+        assert err <= 2e-3
