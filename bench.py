@@ -7,6 +7,12 @@ every frequency pair's blur, and the combine/divide.  The output of the timed
 steps is checked against the FP64 oracle, and the oracle itself is timed on
 the host cores as the CPU baseline.
 
+Besides this plain FP32 line (`value`), the same JSON line carries the mixed
+path on the same workload (split-FP16 Toeplitz blur, its error against the
+oracle with the FIR operator) and the batched path (64 images of uneven
+sizes with per-image sigma_s, sigma_r, autotuned, one grouped graph launch per
+step, its error at sampled pixels against eq. (BF) evaluated directly).
+
 Prints one JSON line.  Only one GPU is supported: --gpus above 1 exits.
 """
 from __future__ import annotations
@@ -56,7 +62,13 @@ def measured_traffic(kernel: str):
     return rec["traffic_bytes"] if sha.startswith(rec["source_sha256_prefix"]) else None
 
 
-def cpu_baseline(img, c, budget_s=25.0):
+def cpu_baseline(img, c, mixed=None, batch=None, budget_s=25.0):
+    """The CPU leg: the FP64 oracle timed on the main workload (Algorithm 2
+    with the recursive operator, all host threads).  Its outputs, and the
+    oracle values it computes afterwards (untimed) for the mixed line (whole
+    image, FIR operator) and the batched line (sampled pixels of every image,
+    each with the operator its autotuned variant uses), are the references of
+    the error checks."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     f = img.astype(np.float64)
@@ -67,9 +79,84 @@ def cpu_baseline(img, c, budget_s=25.0):
         r = oracle.algorithm2(f, "iir", c["sigma_s"], c["radius"], c["sigma_r"], c["eps"], 255.0, True)
         times.append(time.perf_counter() - t0)
     med = float(np.median(times))
-    return r, dict(value=img.size / med / 1e6, unit="megapixels/sec", cores=threads, kind="oracle",
-                   sample=f"whole {img.shape[0]}x{img.shape[1]} image, Algorithm 2 end to end (FP64, IIR "
-                          f"operator), median of {len(times)} runs, {med:.2f} s each")
+    base = dict(value=img.size / med / 1e6, unit="megapixels/sec", cores=threads, kind="oracle",
+                sample=f"whole {img.shape[0]}x{img.shape[1]} image, Algorithm 2 end to end (FP64, IIR "
+                       f"operator), median of {len(times)} runs, {med:.2f} s each")
+    refs = dict(iir=r)
+    if mixed is not None:
+        refs["fir"] = oracle.algorithm2(f, "fir", c["sigma_s"], c["radius"], c["sigma_r"], c["eps"], 255.0, True)
+    if batch is not None:
+        vals = []
+        for (im, ss, sr), rep, (ys, xs) in batch:
+            g = im.astype(np.float64)
+            R = int(np.ceil(3 * ss))
+            if rep["variant"] == "iir_f32":  # no pointwise form of the recursive operator: whole image
+                vals.append(oracle.algorithm2(g, "iir", ss, R, sr, 1e-3, 255.0, True)["out"][ys, xs])
+            else:
+                vals.append(oracle.direct_fir_at(g, ss, R, rep["N"], rep["M"], sr, ys, xs))
+        refs["batch"] = vals
+    return refs, base
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def mixed_line(img, c, x, steps, warmup):
+    """The split-FP16 Toeplitz path on the same workload; returns the line
+    and the output (host) for the error check."""
+    import torch
+    from paper_1203_5128_amd import Plan, make_params
+    H, W = img.shape
+    out = torch.empty((H, W), dtype=torch.float32, device=x.device)
+    plan = Plan.create(make_params(H, W, "u8", c["sigma_s"], c["sigma_r"], c["eps"], c["radius"], "local",
+                                   blur="toeplitz_f16x2"))
+    _, rep = plan.filter(x, out, report=True)
+    sec = time_steps(lambda: plan.filter(x, out, report=False), steps, warmup)
+    plan.close()
+    line = dict(blur="toeplitz_f16x2", value=round(H * W / sec / 1e6, 3), unit="megapixels/sec",
+                ms_per_step=round(sec * 1e3, 5), dtype="f16 hi+lo operands, f32 accumulation",
+                N=rep["N"], M=rep["M"])
+    return line, out.cpu().numpy().astype(np.float64)
+
+
+def batched_line(steps, warmup):
+    """64 images of uneven sizes, per-image parameters, autotuned variants;
+    returns the line and (item, report, sampled pixels, sampled outputs)."""
+    import torch
+    from bfsynth import batch_images
+    from paper_1203_5128_amd import Plan, make_params
+    items = batch_images()
+    xs = [torch.from_numpy(im).to("cuda:0") for im, _, _ in items]
+    outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in xs]
+    t0 = time.perf_counter()
+    plan = Plan.create([make_params(im.shape[0], im.shape[1], "u8", sigma_s=ss, sigma_r=sr, eps=1e-3, blur="auto")
+                        for im, ss, sr in items])
+    plan_s = time.perf_counter() - t0
+    _, reps = plan.filter_batch(xs, outs, report=True)
+    sec = time_steps(lambda: plan.filter_batch(xs, outs, report=False), steps, warmup)
+    plan.close()
+    px = sum(im.size for im, _, _ in items)
+    chosen = {}
+    for r in reps:
+        chosen[r["variant"]] = chosen.get(r["variant"], 0) + 1
+    line = dict(workload="batch64_u8_local", images=len(items), megapixels=round(px / 1e6, 3),
+                value=round(px / sec / 1e6, 3), unit="megapixels/sec", ms_per_step=round(sec * 1e3, 5),
+                variants=chosen, plan_and_tune_s=round(plan_s, 2))
+    rng = np.random.default_rng(5)
+    samples = []
+    for it, out, r in zip(items, outs, reps):
+        ys, xs_ = rng.integers(0, it[0].shape[0], 12), rng.integers(0, it[0].shape[1], 12)
+        samples.append((it, r, (ys, xs_), out.cpu().numpy()[ys, xs_].astype(np.float64)))
+    return line, samples
 
 
 def main():
@@ -78,6 +165,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="plain FP32 line only (no mixed/batched lines)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB mebibytes (a kernel of known "
                          "traffic against which the HBM byte counters are scaled)")
@@ -160,16 +248,31 @@ def main():
                                 traffic=measured_traffic(dom)),
                   stages=stages)
 
-    # accuracy of the timed output against the FP64 oracle
     got = out.cpu().numpy().astype(np.float64)
+    plan.close()
+    mixed = batched = None
+    if not args.no_extra:
+        mixed, mixed_out = mixed_line(img, c, x, args.steps, args.warmup)
+        batched, samples = batched_line(max(3, args.steps // 20), 2)
+        result["mixed"] = mixed
+        result["batched"] = batched
+    # accuracy of the timed outputs against the FP64 oracle (the CPU leg)
     if not args.no_cpu_baseline:
-        ref, cpu = cpu_baseline(img, c)
+        refs, cpu = cpu_baseline(img, c, mixed=mixed,
+                                 batch=None if batched is None else [(it, r, p) for it, r, p, _ in samples])
+        ref = refs["iir"]
         err = np.abs(got - ref["out"])
         result["max_err"] = float(err.max())
         result["rms_err"] = float(np.sqrt((err ** 2).mean()))
         result["err_ok"] = bool(err.max() <= 2e-3 and (ref["N"], ref["M"]) == (rep["N"], rep["M"]))
         result["cpu_baseline"] = cpu
-    plan.close()
+        if mixed is not None:
+            e2 = np.abs(mixed_out - refs["fir"]["out"])
+            mixed.update(max_err=float(e2.max()), rms_err=float(np.sqrt((e2 ** 2).mean())),
+                         err_ok=bool(e2.max() <= 2e-3 and (refs["fir"]["N"], refs["fir"]["M"]) == (mixed["N"], mixed["M"])))
+        if batched is not None:
+            worst = max(float(np.abs(v - r).max()) for (_, _, _, v), r in zip(samples, refs["batch"]))
+            batched.update(sampled_max_err=worst, err_ok=bool(worst <= 2e-3))
     print(json.dumps(result), flush=True)
 
 
