@@ -68,30 +68,37 @@ constexpr int kHRows = 16;
 // then meet in that XCD's L2.  per = ceil(tiles / 8).
 __device__ __forceinline__ int xcd_tile(int id, int per) { return (id & 7) * per + (id >> 3); }
 
-// The 2R+1 taps (2R+1 <= 241) are first copied to LDS by the workgroup (one
-// load per thread); each lane then builds its fragments from there.
-constexpr int kMaxTaps = 256;
-__device__ __forceinline__ void load_taps(float *wsh, const float *__restrict__ taps, int R, int tid) {
-  if (tid <= 2 * R) wsh[tid] = taps[tid];
-}
-
-// Tap fragment of lane l for K-step ks: T[l%16][32 ks + 8 (l/16) + j], read
-// from the LDS copy with a clamped index (no branches).
-template <bool BF>
-__device__ __forceinline__ void tap_frag(const float *w, int R, int ks, int lane, typename MT<BF>::V &hi,
-                                         typename MT<BF>::V &lo) {
+// Tap fragments: lane l of K-step ks holds T[l%16][32 ks + 8 (l/16) + j],
+// j = 0..7, with T[i][t] = w[t - i] on the band and 0 off it (hi and, for the
+// split variants, lo halves).  The workgroup builds all nks x 64 fragments
+// once into LDS (branch-free clamped reads of the taps); every K-step of
+// every product then reads its fragment with one 16-byte LDS load.
+template <bool BF, bool SPLIT>
+__device__ __forceinline__ void build_tap_frags(typename MT<BF>::V *th, typename MT<BF>::V *tl,
+                                                const float *__restrict__ w, int R, int nks, int tid) {
   typedef typename MT<BF>::T E;
-  const int i = lane & 15;
+  typedef typename MT<BF>::V V;
+  for (int idx = tid; idx < nks * 64; idx += 256) {
+    const int ks = idx >> 6, ln = idx & 63, i = ln & 15;
+    float vals[8];
 #pragma unroll
-  for (int j = 0; j < 8; j++) {
-    const int d = 32 * ks + 8 * (lane >> 4) + j - i;
-    const float t = w[min(max(d, 0), 2 * R)];
-    const float v = (d >= 0 && d <= 2 * R) ? t : 0.f;
-    const E h = (E)v;
-    hi[j] = h;
-    lo[j] = (E)(v - (float)h);
+    for (int j = 0; j < 8; j++) {
+      const int d = 32 * ks + 8 * (ln >> 4) + j - i;
+      const float t = w[min(max(d, 0), 2 * R)];
+      vals[j] = (d >= 0 && d <= 2 * R) ? t : 0.f;
+    }
+    V h, l;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      h[j] = (E)vals[j];
+      l[j] = (E)(vals[j] - (float)h[j]);
+    }
+    th[idx] = h;
+    if (SPLIT) tl[idx] = l;
   }
 }
+// LDS bytes of the tap fragments.
+constexpr size_t tap_frag_bytes(int nks, bool split) { return (size_t)(split ? 2 : 1) * nks * 64 * 16; }
 
 // ------------------------------------------------------------ vertical pass
 // Workgroup: `rows` output rows x kVCols pixel columns of one frequency pair.
@@ -119,7 +126,6 @@ __device__ __forceinline__ void toep_v_body(const ToepVArgs &a, const Blk b) {
   constexpr int kCols = TShape<SPLIT>::kVCols;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float2 lut[PhaseLut<Tin>::kOn ? 256 : 1];
-  __shared__ float wsh[kMaxTaps];
   const int t = xcd_tile(b.x, per);
   if (t >= ntiles) return;
   const int kl = b.y;
@@ -134,10 +140,12 @@ __device__ __forceinline__ void toep_v_body(const ToepVArgs &a, const Blk b) {
   const int y0 = (t / ntx) * rows;
   const int Kl = rows - 16 + 32 * nks;  // rows read by the last 16-row block
   const int Kp = Kl + 8;
-  E *Bh = (E *)smem;
+  V *tfh = (V *)smem;
+  V *tfl = tfh + nks * 64;
+  E *Bh = (E *)(smem + tap_frag_bytes(nks, SPLIT));
   E *Bl = Bh + 4 * kCols * Kp;
   const float inv = 1.f / g.center;
-  load_taps(wsh, taps, R, tid);  // consumed after the staging barrier
+  build_tap_frags<BF, SPLIT>(tfh, tfl, taps, R, nks, tid);  // read after the staging barrier
   if constexpr (PhaseLut<Tin>::kOn) {
     build_lut(lut, m, q, at, tid, 256);
     __syncthreads();
@@ -181,10 +189,6 @@ __device__ __forceinline__ void toep_v_body(const ToepVArgs &a, const Blk b) {
     }
   }
   __syncthreads();
-  V th[8], tl[8];
-#pragma unroll
-  for (int ks = 0; ks < 8; ks++)
-    if (ks < nks) tap_frag<BF>(wsh, R, ks, lane, th[ks], tl[ks]);
   ZT *Z = (ZT *)Zv + (size_t)kl * 4 * zplane;
   const int nmb = rows / 16;
   const int ncomb = nmb * (kCols / 16);
@@ -194,39 +198,46 @@ __device__ __forceinline__ void toep_v_body(const ToepVArgs &a, const Blk b) {
   // y0 + 16 mb + l%16 and writes them with one packed store.
   typedef ZT Z4 __attribute__((ext_vector_type(4)));
   typedef ZT Z2 __attribute__((ext_vector_type(2)));
+  const size_t pstride = (size_t)kCols * Kp;  // LDS elements between planes
   for (int cb = wv; cb < ncomb; cb += 4) {
     const int mb = cb % nmb, nb = cb / nmb;
     const int px = nb * 16 + (lane & 15);
     const int y = y0 + 16 * mb + (lane & 15);
     const int xs = x0 + nb * 16 + 4 * (lane >> 4);
+    const E *colh = Bh + px * Kp + 16 * mb + 8 * (lane >> 4);
+    const E *coll = Bl + px * Kp + 16 * mb + 8 * (lane >> 4);
+    f4v acc[4];
 #pragma unroll
-    for (int p = 0; p < 4; p++) {
-      f4v acc = {0.f, 0.f, 0.f, 0.f};
-      const E *colh = Bh + (p * kCols + px) * Kp + 16 * mb + 8 * (lane >> 4);
-      const E *coll = Bl + (p * kCols + px) * Kp + 16 * mb + 8 * (lane >> 4);
+    for (int p = 0; p < 4; p++) acc[p] = (f4v){0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int ks = 0; ks < nks; ks++) {
+      const V tb = tfh[ks * 64 + lane];
 #pragma unroll
-      for (int ks = 0; ks < 8; ks++) {
-        if (ks < nks) {
-          const V bh = *(const V *)(colh + 32 * ks);
-          acc = MT<BF>::mfma(bh, th[ks], acc);
-          if (SPLIT) {
-            const V bl = *(const V *)(coll + 32 * ks);
-            acc = MT<BF>::mfma(bl, th[ks], acc);
-            acc = MT<BF>::mfma(bh, tl[ks], acc);
-          }
+      for (int p = 0; p < 4; p++) {
+        const V bh = *(const V *)(colh + p * pstride + 32 * ks);
+        acc[p] = MT<BF>::mfma(bh, tb, acc[p]);
+        if (SPLIT) {
+          const V tbl = tfl[ks * 64 + lane];
+          const V bl = *(const V *)(coll + p * pstride + 32 * ks);
+          acc[p] = MT<BF>::mfma(bl, tb, acc[p]);
+          acc[p] = MT<BF>::mfma(bh, tbl, acc[p]);
         }
       }
+    }
+#pragma unroll
+    for (int p = 0; p < 4; p++) {
       if (y < g.H && xs < g.W) {
         ZT *zp = Z + (size_t)p * zplane + (size_t)y * g.zpitch + g.padl + xs;
+        const f4v v = acc[p];
         if (xs + 4 <= g.W && (g.padl & 3) == 0) {
-          *(Z4 *)zp = (Z4){(ZT)acc[0], (ZT)acc[1], (ZT)acc[2], (ZT)acc[3]};
+          *(Z4 *)zp = (Z4){(ZT)v[0], (ZT)v[1], (ZT)v[2], (ZT)v[3]};
         } else if (xs + 4 <= g.W && (g.padl & 1) == 0) {
-          *(Z2 *)zp = (Z2){(ZT)acc[0], (ZT)acc[1]};
-          *(Z2 *)(zp + 2) = (Z2){(ZT)acc[2], (ZT)acc[3]};
+          *(Z2 *)zp = (Z2){(ZT)v[0], (ZT)v[1]};
+          *(Z2 *)(zp + 2) = (Z2){(ZT)v[2], (ZT)v[3]};
         } else {
 #pragma unroll
           for (int i = 0; i < 4; i++)
-            if (xs + i < g.W) zp[i] = (ZT)acc[i];
+            if (xs + i < g.W) zp[i] = (ZT)v[i];
         }
       }
     }
@@ -276,7 +287,6 @@ __device__ __forceinline__ void toep_h_body(const ToepHArgs &a, const Blk b) {
   constexpr int kNbw = kCols / 64;  // 16-column blocks per wave
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float2 lut[PhaseLut<Tin>::kOn ? 256 : 1];
-  __shared__ float wsh[kMaxTaps];
   const int t = xcd_tile(b.x, per);
   if (t >= ntiles) return;
   const OrderEntry &e = lookup(tab, st.T_used);
@@ -287,77 +297,45 @@ __device__ __forceinline__ void toep_h_body(const ToepHArgs &a, const Blk b) {
   const int y0 = (t / ntx) * kHRows;
   const int Kl = kCols - 16 + 32 * nks;  // columns read by the last 16-column block
   const int Kp = Kl + 8;
-  E *Ah = (E *)smem;
+  V *tfh = (V *)smem;
+  V *tfl = tfh + nks * 64;
+  E *Ah = (E *)(smem + tap_frag_bytes(nks, SPLIT));
   E *Al = Ah + 4 * kHRows * Kp;
-  load_taps(wsh, taps, R, tid);
-  __syncthreads();
-  V th[8], tl[8];
-#pragma unroll
-  for (int ks = 0; ks < 8; ks++)
-    if (ks < nks) tap_frag<BF>(wsh, R, ks, lane, th[ks], tl[ks]);
+  build_tap_frags<BF, SPLIT>(tfh, tfl, taps, R, nks, tid);  // read after the first barrier below
   const int rbase = 4 * (lane >> 4);
   Tin fv[kNbw][4];
   float P[kNbw][4], Q[kNbw][4];
 #pragma unroll
-  for (int b = 0; b < kNbw; b++)
+  for (int bb = 0; bb < kNbw; bb++)
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       const int y = min(y0 + rbase + i, g.H - 1);
-      const int x = min(x0 + (kNbw * wv + b) * 16 + (lane & 15), g.W - 1);
-      fv[b][i] = f[(int64_t)y * g.pitch + x];
-      P[b][i] = 0.f;
-      Q[b][i] = 0.f;
+      const int x = min(x0 + (kNbw * wv + bb) * 16 + (lane & 15), g.W - 1);
+      fv[bb][i] = f[(int64_t)y * g.pitch + x];
+      P[bb][i] = 0.f;
+      Q[bb][i] = 0.f;
     }
-  const int zc0 = x0 - R + g.padl;  // multiple of 8
-  const int nvec = Kl / 8;
   const ZT *Zb = (const ZT *)Zv;
   const uint64_t q = e.qfix;
   const double at = e.alpha_turn;
-  // Staging of one pair's Z tile: vector `it` of the tile is row rr = it / nvec
-  // (plane rr / 16), vectors v = it % nvec along the row.  Loads use an
-  // address inside the buffer for vectors off the image (then zeroed), so they
-  // carry no branches and several are in flight per thread.
+  // Staging of one pair's Z tile: the 64 LDS rows (plane * 16 + image row) are
+  // shared out to the waves, 16 each.  A row holds nvec = Kl / 8 <= 64 vectors
+  // of 8 elements (the window starts on an 8-element boundary); Lr = 16, 32 or
+  // 64 lanes (the smallest >= nvec) take one row, so one wave instruction
+  // covers 64 / Lr rows, and four such instructions are in flight.  Vectors
+  // that reach off the image are zeroed element-wise by a bit mask.
   typedef typename std::conditional<SPLIT, float4, V>::type LT;
   constexpr int kLw = SPLIT ? 2 : 1;  // LT loads per vector
-  const int total = 4 * kHRows * nvec;
-  auto load_vec = [&](int it, int kl, LT *dst) {
-    it = min(it, total - 1);
-    const int v = it % nvec, rr = it / nvec;
-    const int y = y0 + rr % kHRows;
-    const int zc = zc0 + 8 * v;
-    const bool inr = y < g.H && zc + 8 > g.padl && zc < g.padl + g.W;
-    const ZT *src = Zb + (inr ? ((size_t)kl * 4 + rr / kHRows) * zplane + (size_t)y * g.zpitch + zc : 0);
-    dst[0] = *(const LT *)src;
-    if constexpr (SPLIT) dst[kLw - 1] = *(const LT *)(src + 4);
-  };
-  auto store_vec = [&](int it, const LT *raw) {
-    const int v = it % nvec, rr = it / nvec;
-    const int y = y0 + rr % kHRows;
-    const int zc = zc0 + 8 * v;
-    const bool inr = y < g.H && zc + 8 > g.padl && zc < g.padl + g.W;
-    const bool full = inr && zc >= g.padl && zc + 8 <= g.padl + g.W;
-    V h, l;
-    if constexpr (SPLIT) {
-      const float4 a = raw[0], bq = raw[kLw - 1];
-      const float vals[8] = {a.x, a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w};
-#pragma unroll
-      for (int j = 0; j < 8; j++) {
-        const bool ok = full || (inr && zc + j >= g.padl && zc + j < g.padl + g.W);
-        const float v8 = ok ? vals[j] : 0.f;
-        h[j] = (E)v8;
-        l[j] = (E)(v8 - (float)h[j]);
-      }
-    } else {
-      h = raw[0];
-      if (!full) {
-#pragma unroll
-        for (int j = 0; j < 8; j++)
-          if (!(inr && zc + j >= g.padl && zc + j < g.padl + g.W)) h[j] = (E)0.f;
-      }
-    }
-    *(V *)(Ah + rr * Kp + 8 * v) = h;
-    if (SPLIT) *(V *)(Al + rr * Kp + 8 * v) = l;
-  };
+  const int nvec = Kl / 8;
+  const int lrs = nvec <= 16 ? 4 : (nvec <= 32 ? 5 : 6);  // log2 of lanes per row
+  const int vl = lane & ((1 << lrs) - 1);                 // this lane's vector in its row
+  const int sub = lane >> lrs;                            // this lane's row within an instruction
+  const int rpi = 64 >> lrs;                              // rows per instruction
+  const bool lane_on = vl < nvec;
+  const int zc = x0 - R + g.padl + 8 * vl;  // first Z column of this lane's vector (multiple of 8)
+  const int jlo = min(max(g.padl - zc, 0), 8), jhi = min(max(g.padl + g.W - zc, 0), 8);
+  const uint32_t xmask = jhi > jlo ? ((1u << jhi) - 1u) & ~((1u << jlo) - 1u) : 0u;  // valid elements
+  const int ninst = 16 >> (6 - lrs);  // instructions per wave per pair (16 rows / rpi)
   for (int k = kb; k < kend; k++) {
     const int kl = k - k0;
     const int32_t m = tab.pm[e.off + k];
@@ -365,39 +343,76 @@ __device__ __forceinline__ void toep_h_body(const ToepHArgs &a, const Blk b) {
     const Freq fq = make_freq(m, q, at);
     __syncthreads();  // the previous pair's tile and table are consumed
     if constexpr (PhaseLut<Tin>::kOn) build_lut(lut, m, q, at, tid, 256);
-    {
-      // batches of kU vectors per thread: every load of a batch is issued
-      // before the first is masked and stored
-      constexpr int kU = SPLIT ? 2 : 4;
-      for (int it0 = tid; it0 < total; it0 += 256 * kU) {
-        LT raw[kU][kLw];
+    const ZT *Zk = Zb + (size_t)kl * 4 * zplane;
+    constexpr int kRU = 4;  // instructions in flight per lane
+    for (int j0 = 0; j0 < ninst; j0 += kRU) {
+      LT raw[kRU][kLw];
+      uint32_t msk[kRU];
 #pragma unroll
-        for (int u = 0; u < kU; u++) load_vec(it0 + 256 * u, kl, raw[u]);
+      for (int u = 0; u < kRU; u++) {
+        const int rr = wv + 4 * ((j0 + u) * rpi + sub);  // LDS row: plane rr / 16, image row y0 + rr % 16
+        const int y = y0 + (rr & 15);
+        msk[u] = (lane_on && j0 + u < ninst && y < g.H) ? xmask : 0u;
+        const ZT *src = Zk + (msk[u] ? (size_t)(rr >> 4) * zplane + (size_t)y * g.zpitch + zc : 0);
+        raw[u][0] = *(const LT *)src;
+        if constexpr (SPLIT) raw[u][kLw - 1] = *(const LT *)(src + 4);
+      }
 #pragma unroll
-        for (int u = 0; u < kU; u++)
-          if (it0 + 256 * u < total) store_vec(it0 + 256 * u, raw[u]);
+      for (int u = 0; u < kRU; u++) {
+        const int rr = wv + 4 * ((j0 + u) * rpi + sub);
+        V h, l;
+        if constexpr (SPLIT) {
+          const float4 a0 = raw[u][0], a1 = raw[u][kLw - 1];
+          const float vals[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+          for (int j = 0; j < 8; j++) {
+            const float v8 = ((msk[u] >> j) & 1u) ? vals[j] : 0.f;
+            h[j] = (E)v8;
+            l[j] = (E)(v8 - (float)h[j]);
+          }
+        } else {
+          h = raw[u][0];
+          if (msk[u] != 0xFFu) {  // edge vectors only
+            union {
+              V v;
+              uint32_t w[4];
+            } cv;
+            cv.v = h;
+#pragma unroll
+            for (int w = 0; w < 4; w++)
+              cv.w[w] &= (((msk[u] >> (2 * w)) & 1u) ? 0x0000FFFFu : 0u) |
+                         (((msk[u] >> (2 * w + 1)) & 1u) ? 0xFFFF0000u : 0u);
+            h = cv.v;
+          }
+        }
+        if (lane_on && j0 + u < ninst) {
+          *(V *)(Ah + rr * Kp + 8 * vl) = h;
+          if (SPLIT) *(V *)(Al + rr * Kp + 8 * vl) = l;
+        }
       }
     }
     __syncthreads();
+    const size_t pstride = (size_t)kHRows * Kp;  // LDS elements between planes
 #pragma unroll
-    for (int b = 0; b < kNbw; b++) {
-      const int nb = kNbw * wv + b;
+    for (int bb = 0; bb < kNbw; bb++) {
+      const int nb = kNbw * wv + bb;
       f4v acc[4];
 #pragma unroll
-      for (int p = 0; p < 4; p++) {
-        acc[p] = (f4v){0.f, 0.f, 0.f, 0.f};
-        const E *rowh = Ah + (p * kHRows + (lane & 15)) * Kp + 16 * nb + 8 * (lane >> 4);
-        const E *rowl = Al + (p * kHRows + (lane & 15)) * Kp + 16 * nb + 8 * (lane >> 4);
+      for (int p = 0; p < 4; p++) acc[p] = (f4v){0.f, 0.f, 0.f, 0.f};
+      const E *rowh = Ah + (lane & 15) * Kp + 16 * nb + 8 * (lane >> 4);
+      const E *rowl = Al + (lane & 15) * Kp + 16 * nb + 8 * (lane >> 4);
+#pragma unroll 2
+      for (int ks = 0; ks < nks; ks++) {
+        const V tb = tfh[ks * 64 + lane];
 #pragma unroll
-        for (int ks = 0; ks < 8; ks++) {
-          if (ks < nks) {
-            const V ah = *(const V *)(rowh + 32 * ks);
-            acc[p] = MT<BF>::mfma(ah, th[ks], acc[p]);
-            if (SPLIT) {
-              const V al = *(const V *)(rowl + 32 * ks);
-              acc[p] = MT<BF>::mfma(al, th[ks], acc[p]);
-              acc[p] = MT<BF>::mfma(ah, tl[ks], acc[p]);
-            }
+        for (int p = 0; p < 4; p++) {
+          const V ah = *(const V *)(rowh + p * pstride + 32 * ks);
+          acc[p] = MT<BF>::mfma(ah, tb, acc[p]);
+          if (SPLIT) {
+            const V tbl = tfl[ks * 64 + lane];
+            const V al = *(const V *)(rowl + p * pstride + 32 * ks);
+            acc[p] = MT<BF>::mfma(al, tb, acc[p]);
+            acc[p] = MT<BF>::mfma(ah, tbl, acc[p]);
           }
         }
       }
@@ -405,27 +420,29 @@ __device__ __forceinline__ void toep_h_body(const ToepHArgs &a, const Blk b) {
       for (int i = 0; i < 4; i++) {
         float c, s;
         if constexpr (PhaseLut<Tin>::kOn) {
-          const float2 cs = lut[(int)fv[b][i]];
+          const float2 cs = lut[(int)fv[bb][i]];
           c = cs.x;
           s = cs.y;
         } else {
-          turn_sincos(phase_turn<Tin>(fv[b][i], fq), c, s);
+          turn_sincos(phase_turn<Tin>(fv[bb][i], fq), c, s);
         }
-        P[b][i] = fmaf(cp, fmaf(c, acc[0][i], s * acc[1][i]), P[b][i]);
-        Q[b][i] = fmaf(cp, fmaf(c, acc[2][i], s * acc[3][i]), Q[b][i]);
+        P[bb][i] = fmaf(cp, fmaf(c, acc[0][i], s * acc[1][i]), P[bb][i]);
+        Q[bb][i] = fmaf(cp, fmaf(c, acc[2][i], s * acc[3][i]), Q[bb][i]);
       }
+      // keep the column blocks apart: interleaving them only raises register pressure
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   if (kb >= kend && !first && !finish) return;  // no pairs here: partial sums unchanged
   float2 *PQg = PQ + (size_t)b.y * g.H * g.W;
   unsigned long long nbad = 0;
 #pragma unroll
-  for (int b = 0; b < kNbw; b++)
+  for (int bb = 0; bb < kNbw; bb++)
 #pragma unroll
     for (int i = 0; i < 4; i++) {
-      const int y = y0 + rbase + i, x = x0 + (kNbw * wv + b) * 16 + (lane & 15);
+      const int y = y0 + rbase + i, x = x0 + (kNbw * wv + bb) * 16 + (lane & 15);
       if (y >= g.H || x >= g.W) continue;
-      float Pv = P[b][i], Qv = Q[b][i];
+      float Pv = P[bb][i], Qv = Q[bb][i];
       const size_t pix = (size_t)y * g.W + x;
       if (!first) {
         const float2 pq = PQg[pix];
@@ -438,7 +455,7 @@ __device__ __forceinline__ void toep_h_body(const ToepHArgs &a, const Blk b) {
         if (Qv > 0.f && isfinite(r)) {
           v = fmaf(g.center, r, g.center);
         } else {
-          v = fval(fv[b][i]);
+          v = fval(fv[bb][i]);
           nbad++;
         }
         out[(int64_t)y * g.opitch + x] = v;
@@ -452,11 +469,11 @@ __device__ __forceinline__ void toep_h_body(const ToepHArgs &a, const Blk b) {
   }
 }
 template <typename Tin, bool BF, bool SPLIT>
-__global__ __launch_bounds__(256) void k_toep_h(ToepHArgs a) {
+__global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_toep_h(ToepHArgs a) {
   toep_h_body<Tin, BF, SPLIT>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
 }
 template <typename Tin, bool BF, bool SPLIT>
-__global__ __launch_bounds__(256) void k_toep_h_grp(const ToepHArgs *__restrict__ a, const int *__restrict__ start,
+__global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_toep_h_grp(const ToepHArgs *__restrict__ a, const int *__restrict__ start,
                                                     int n) {
   const int i = group_find(start, n, blockIdx.x);
   toep_h_body<Tin, BF, SPLIT>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
@@ -515,13 +532,13 @@ size_t toeplitz_v_lds(int variant, int rows, int nks) {
   const bool split = split_of(variant);
   const int cols = split ? TShape<true>::kVCols : TShape<false>::kVCols;
   const int Kp = rows - 16 + 32 * nks + 8;
-  return (size_t)(split ? 2 : 1) * 4 * cols * Kp * 2;
+  return tap_frag_bytes(nks, split) + (size_t)(split ? 2 : 1) * 4 * cols * Kp * 2;
 }
 size_t toeplitz_h_lds(int variant, int nks) {
   const bool split = split_of(variant);
   const int cols = split ? TShape<true>::kHCols : TShape<false>::kHCols;
   const int Kp = cols - 16 + 32 * nks + 8;
-  return (size_t)(split ? 2 : 1) * 4 * kHRows * Kp * 2;
+  return tap_frag_bytes(nks, split) + (size_t)(split ? 2 : 1) * 4 * kHRows * Kp * 2;
 }
 int toeplitz_h_tiles(int variant, int H, int W) {
   const int cols = split_of(variant) ? TShape<true>::kHCols : TShape<false>::kHCols;

@@ -26,14 +26,18 @@ def h_cols(split):
     return 64 if split else 128
 
 
+def tap_bytes(split, nks):
+    return (2 if split else 1) * nks * 64 * 16
+
+
 def v_lds(split, rows, nks):
     Kp = rows - 16 + 32 * nks + 8
-    return (2 if split else 1) * 4 * v_cols(split) * Kp * 2
+    return tap_bytes(split, nks) + (2 if split else 1) * 4 * v_cols(split) * Kp * 2
 
 
 def h_lds(split, nks):
     Kp = h_cols(split) - 16 + 32 * nks + 8
-    return (2 if split else 1) * 4 * 16 * Kp * 2
+    return tap_bytes(split, nks) + (2 if split else 1) * 4 * 16 * Kp * 2
 
 
 def shape(split, R, H):
@@ -99,7 +103,7 @@ def model(f, planes, sigma_s, R, split, K, coef_phase):
     # vertical kernel
     Kl = rows - 16 + 32 * nks
     Kp = Kl + 8
-    lds_elems = v_lds(split, rows, nks) // 2 // (2 if split else 1)
+    lds_elems = (v_lds(split, rows, nks) - tap_bytes(split, nks)) // 2 // (2 if split else 1)
     for kl in range(K):
         for by in range((H + rows - 1) // rows):
             for bx in range((W + cv - 1) // cv):
@@ -145,7 +149,7 @@ def model(f, planes, sigma_s, R, split, K, coef_phase):
     ch = h_cols(split)
     Klh = ch - 16 + 32 * nks
     Kph = Klh + 8
-    lds_h = h_lds(split, nks) // 2 // (2 if split else 1)
+    lds_h = (h_lds(split, nks) - tap_bytes(split, nks)) // 2 // (2 if split else 1)
     P = np.zeros((H, W))
     Q = np.zeros((H, W))
     Tm = tap_matrix(w, R, nks)
@@ -316,3 +320,23 @@ def test_grouped_launch_block_map(blocks):
 def test_group_grid_decomposition(gx, gy, gz):
     got = [(l % gx, (l // gx) % gy, l // (gx * gy)) for l in range(gx * gy * gz)]
     assert sorted(got) == [(x, y, z) for x in range(gx) for y in range(gy) for z in range(gz)]
+
+
+@pytest.mark.parametrize("nvec", [1, 15, 16, 17, 22, 30, 32, 33, 46, 64])
+def test_horizontal_staging_lane_map(nvec):
+    """Each wave stages 16 of the 64 LDS rows; Lr lanes (16, 32 or 64, the
+    smallest >= nvec) take one row, so an instruction covers 64 / Lr rows:
+    every (row, vector < nvec) is written exactly once, by lanes that exist."""
+    lrs = 4 if nvec <= 16 else (5 if nvec <= 32 else 6)
+    rpi = 64 >> lrs
+    ninst = 16 >> (6 - lrs)
+    seen = []
+    for wv in range(4):
+        for j in range(ninst):
+            for lane in range(64):
+                vl, sub = lane & ((1 << lrs) - 1), lane >> lrs
+                if vl >= nvec:
+                    continue
+                rr = wv + 4 * (j * rpi + sub)
+                seen.append((rr, vl))
+    assert sorted(seen) == [(rr, v) for rr in range(64) for v in range(nvec)]
