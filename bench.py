@@ -128,9 +128,12 @@ def mixed_line(img, c, x, steps, warmup):
     return line, out.cpu().numpy().astype(np.float64)
 
 
-def batched_line(steps, warmup):
-    """64 images of uneven sizes, per-image parameters, autotuned variants;
-    returns the line and (item, report, sampled pixels, sampled outputs)."""
+def batched_line(blur, steps, warmup):
+    """The 64-image workload (uneven sizes, per-image sigma_s, sigma_r) with
+    every image on `blur` ("auto": each image's autotuned variant); returns
+    the line and (item, report, sampled pixels, sampled outputs) of the
+    images whose outputs are checked (all for the FIR variants, every fourth
+    for the recursive one, whose oracle runs on the whole image)."""
     import torch
     from bfsynth import batch_images
     from paper_1203_5128_amd import Plan, make_params
@@ -138,7 +141,7 @@ def batched_line(steps, warmup):
     xs = [torch.from_numpy(im).to("cuda:0") for im, _, _ in items]
     outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in xs]
     t0 = time.perf_counter()
-    plan = Plan.create([make_params(im.shape[0], im.shape[1], "u8", sigma_s=ss, sigma_r=sr, eps=1e-3, blur="auto")
+    plan = Plan.create([make_params(im.shape[0], im.shape[1], "u8", sigma_s=ss, sigma_r=sr, eps=1e-3, blur=blur)
                         for im, ss, sr in items])
     plan_s = time.perf_counter() - t0
     _, reps = plan.filter_batch(xs, outs, report=True)
@@ -148,12 +151,14 @@ def batched_line(steps, warmup):
     chosen = {}
     for r in reps:
         chosen[r["variant"]] = chosen.get(r["variant"], 0) + 1
-    line = dict(workload="batch64_u8_local", images=len(items), megapixels=round(px / 1e6, 3),
-                value=round(px / sec / 1e6, 3), unit="megapixels/sec", ms_per_step=round(sec * 1e3, 5),
-                variants=chosen, plan_and_tune_s=round(plan_s, 2))
+    line = dict(blur=blur, images=len(items), megapixels=round(px / 1e6, 3), value=round(px / sec / 1e6, 3),
+                unit="megapixels/sec", ms_per_step=round(sec * 1e3, 5), variants=chosen,
+                plan_s=round(plan_s, 2))
     rng = np.random.default_rng(5)
     samples = []
-    for it, out, r in zip(items, outs, reps):
+    for i, (it, out, r) in enumerate(zip(items, outs, reps)):
+        if r["variant"] == "iir_f32" and i % 4:
+            continue
         ys, xs_ = rng.integers(0, it[0].shape[0], 12), rng.integers(0, it[0].shape[1], 12)
         samples.append((it, r, (ys, xs_), out.cpu().numpy()[ys, xs_].astype(np.float64)))
     return line, samples
@@ -166,6 +171,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="plain FP32 line only (no mixed/batched lines)")
+    ap.add_argument("--lines", default="mixed,batch",
+                    help="extra lines besides the plain one: any of mixed, batch (empty: none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB mebibytes (a kernel of known "
                          "traffic against which the HBM byte counters are scaled)")
@@ -250,16 +257,25 @@ def main():
 
     got = out.cpu().numpy().astype(np.float64)
     plan.close()
-    mixed = batched = None
-    if not args.no_extra:
+    mixed = None
+    batches = {}
+    lines = set() if args.no_extra else {t for t in args.lines.split(",") if t}
+    if "mixed" in lines:
         mixed, mixed_out = mixed_line(img, c, x, args.steps, args.warmup)
-        batched, samples = batched_line(max(3, args.steps // 20), 2)
         result["mixed"] = mixed
-        result["batched"] = batched
+    if "batch" in lines:
+        bsteps = max(3, args.steps // 20)
+        for key, blur in (("plain", "iir_f32"), ("mixed", "toeplitz_f16x2"), ("auto", "auto")):
+            batches[key] = batched_line(blur, bsteps, 2)
+        result["batched"] = dict(workload="batch64_u8_local", **{k: v[0] for k, v in batches.items()})
+        result["batched"]["speedup_mixed_vs_plain"] = round(
+            batches["mixed"][0]["value"] / batches["plain"][0]["value"], 3)
+        result["batched"]["speedup_auto_vs_plain"] = round(
+            batches["auto"][0]["value"] / batches["plain"][0]["value"], 3)
     # accuracy of the timed outputs against the FP64 oracle (the CPU leg)
     if not args.no_cpu_baseline:
-        refs, cpu = cpu_baseline(img, c, mixed=mixed,
-                                 batch=None if batched is None else [(it, r, p) for it, r, p, _ in samples])
+        samples = [smp for v in batches.values() for smp in v[1]]
+        refs, cpu = cpu_baseline(img, c, mixed=mixed, batch=[(it, r, p) for it, r, p, _ in samples] or None)
         ref = refs["iir"]
         err = np.abs(got - ref["out"])
         result["max_err"] = float(err.max())
@@ -270,9 +286,13 @@ def main():
             e2 = np.abs(mixed_out - refs["fir"]["out"])
             mixed.update(max_err=float(e2.max()), rms_err=float(np.sqrt((e2 ** 2).mean())),
                          err_ok=bool(e2.max() <= 2e-3 and (refs["fir"]["N"], refs["fir"]["M"]) == (mixed["N"], mixed["M"])))
-        if batched is not None:
-            worst = max(float(np.abs(v - r).max()) for (_, _, _, v), r in zip(samples, refs["batch"]))
-            batched.update(sampled_max_err=worst, err_ok=bool(worst <= 2e-3))
+        if batches:
+            errs = [float(np.abs(v - r).max()) for (_, _, _, v), r in zip(samples, refs["batch"])]
+            i0 = 0
+            for key, (line, smp) in batches.items():
+                worst = max(errs[i0:i0 + len(smp)])
+                i0 += len(smp)
+                line.update(sampled_max_err=worst, err_ok=bool(worst <= 2e-3))
     print(json.dumps(result), flush=True)
 
 

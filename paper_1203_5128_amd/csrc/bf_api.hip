@@ -687,6 +687,7 @@ const char *bf_last_error_detail(void) { return g_detail.c_str(); }
 
 namespace {
 bf_status autotune(const bf_params &p, Knobs &kn);
+void autotune_batch(const bf_params *params, int n, std::vector<Knobs> &kn);
 }
 
 // Plan creation with explicit per-image knobs (the autotuner's choices).
@@ -768,11 +769,14 @@ bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out) {
     if (s) return s;
   }
   std::vector<Knobs> kn(n_images);
+  bool any_auto = false;
   for (int i = 0; i < n_images; i++)
     if (params[i].blur == BF_BLUR_AUTO) {
+      any_auto = true;
       bf_status s = autotune(params[i], kn[i]);
       if (s) return s;
     }
+  if (n_images > 1 && any_auto) autotune_batch(params, n_images, kn);
   return create_plan(params, n_images, kn.data(), out);
 }
 
@@ -1047,6 +1051,91 @@ bf_status autotune(const bf_params &p, Knobs &best) {
   g_tune[key] = best;
   tune_save(key, best, best_ms);
   return BF_OK;
+}
+
+// Batch-level choice: a batch runs its Toeplitz images as grouped launches
+// (one launch per stage for all of them) and its recursive images one after
+// another, so the per-image choice can lose to putting every image on the
+// Toeplitz path.  Both assignments are timed on the whole batch (full-range
+// checkerboards, every pair kept) and the faster kept.
+double time_batch(const bf_params *params, int n, const std::vector<Knobs> &kn, std::vector<void *> &ins,
+                  std::vector<float *> &outs, hipStream_t s, hipEvent_t a, hipEvent_t b) {
+  std::vector<bf_params> q(params, params + n);
+  for (auto &p : q) {
+    p.in_pitch = p.out_pitch = 0;
+    if (p.t_mode == BF_T_LOCAL) {
+      p.t_mode = BF_T_GLOBAL;
+      p.t_value = 0.0;
+    }
+  }
+  bf_plan_t pl = nullptr;
+  if (create_plan(q.data(), n, kn.data(), &pl) != BF_OK) return -1.0;
+  BatchPlan bp;
+  build_batch(pl, n, ins.data(), outs.data(), bp);
+  void *d_args = nullptr;
+  double best = -1.0;
+  if (hipMalloc(&d_args, std::max<size_t>(bp.pack.buf.size(), 256)) == hipSuccess &&
+      (bp.pack.buf.empty() ||
+       hipMemcpy(d_args, bp.pack.buf.data(), bp.pack.buf.size(), hipMemcpyHostToDevice) == hipSuccess)) {
+    std::vector<float> t;
+    for (int r = 0; r < 5; r++) {
+      bool ok = hipEventRecord(a, s) == hipSuccess &&
+                enqueue_batch(pl, n, ins.data(), outs.data(), bp, (const char *)d_args, s) == BF_OK &&
+                hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+      float ms = 0.f;
+      if (!ok) break;
+      if (hipEventElapsedTime(&ms, a, b) == hipSuccess && r >= 1) t.push_back(ms);
+    }
+    if (!t.empty()) {
+      std::sort(t.begin(), t.end());
+      best = t[t.size() / 2];
+    }
+  }
+  (void)hipFree(d_args);
+  bf_plan_destroy(pl);
+  return best;
+}
+
+void autotune_batch(const bf_params *params, int n, std::vector<Knobs> &kn) {
+  std::vector<Knobs> alt = kn;
+  bool differs = false;
+  for (int i = 0; i < n; i++) {
+    const int R = params[i].radius > 0 ? params[i].radius : (int)std::ceil(3.0 * params[i].sigma_s);
+    if (params[i].blur == BF_BLUR_AUTO && kn[i].variant == BF_BLUR_IIR_F32 && R <= 120) {
+      alt[i] = Knobs{BF_BLUR_TOEPLITZ_F16X2, 0, 0};
+      differs = true;
+    }
+  }
+  if (!differs) return;
+  std::vector<void *> ins(n, nullptr);
+  std::vector<float *> outs(n, nullptr);
+  hipStream_t s = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  for (int i = 0; i < n && e == hipSuccess; i++) {
+    const bf_params &p = params[i];
+    const size_t px = (size_t)p.height * p.width;
+    e = hipMalloc(&ins[i], px * elem_size(p.dtype));
+    if (e == hipSuccess) e = hipMalloc((void **)&outs[i], px * sizeof(float));
+    const double full = p.dtype == BF_U16 ? 65535.0 : 255.0;
+    if (e == hipSuccess)
+      e = launch_fill_checker(s, p.dtype, ins[i], p.height, p.width, p.value_range > 0.0 ? p.value_range : full);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) {
+    const double t_own = time_batch(params, n, kn, ins, outs, s, a, b);
+    const double t_alt = time_batch(params, n, alt, ins, outs, s, a, b);
+    if (t_alt > 0.0 && (t_own < 0.0 || t_alt < t_own)) kn = alt;
+  }
+  for (int i = 0; i < n; i++) {
+    (void)hipFree(ins[i]);
+    (void)hipFree(outs[i]);
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (s) (void)hipStreamDestroy(s);
 }
 
 }  // namespace
