@@ -1047,6 +1047,9 @@ bf_status autotune(const bf_params &p, Knobs &best) {
   (void)hipFree(d_out);
   if (e != hipSuccess) return dev_fail(e, "autotune");
   if (best_ms < 0.0) best = cand[0];
+  if (std::getenv("BF_TUNE_LOG"))
+    std::fprintf(stderr, "[bf tune] %s -> variant %d hchunk %d lds %d KB (%.3f ms)\n", key.c_str(), best.variant,
+                 best.hchunk, best.lds_kb, best_ms);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune[key] = best;
   tune_save(key, best, best_ms);
@@ -1127,7 +1130,11 @@ void autotune_batch(const bf_params *params, int n, std::vector<Knobs> &kn) {
   if (e == hipSuccess) {
     const double t_own = time_batch(params, n, kn, ins, outs, s, a, b);
     const double t_alt = time_batch(params, n, alt, ins, outs, s, a, b);
-    if (t_alt > 0.0 && (t_own < 0.0 || t_alt < t_own)) kn = alt;
+    const bool take = t_alt > 0.0 && (t_own < 0.0 || t_alt < t_own);
+    if (std::getenv("BF_TUNE_LOG"))
+      std::fprintf(stderr, "[bf tune] batch of %d: per-image choice %.3f ms, all Toeplitz %.3f ms -> %s\n", n, t_own,
+                   t_alt, take ? "all Toeplitz" : "per-image choice");
+    if (take) kn = alt;
   }
   for (int i = 0; i < n; i++) {
     (void)hipFree(ins[i]);
