@@ -120,7 +120,7 @@ struct bf_plan_s {
   bool grouped = false;
   void *d_bws = nullptr;
   size_t bws_bytes = 0;
-  std::vector<size_t> rowmax_off, z_off, pq_off;
+  std::vector<size_t> rowmax_off, z_off, pq_off, cb_off, glut_off;
   struct BatchEntry {
     std::vector<const void *> in;
     std::vector<float *> out;
@@ -401,10 +401,9 @@ bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out
   return BF_OK;
 }
 
-// Whether an image of the plan runs inside the grouped launches of a batch.
-bool in_group(const bf_plan_s *pl, const ImagePlan &ip) {
-  return pl->grouped && is_toeplitz(ip.variant) && ip.KC == ip.tab.K_max;
-}
+// Whether an image of the plan runs inside the grouped launches of a batch
+// (all its pairs in one launch).
+bool in_group(const bf_plan_s *pl, const ImagePlan &ip) { return pl->grouped && ip.KC == ip.tab.K_max; }
 
 // Host image of the argument arrays of one batch, packed for one upload.
 struct ArgPack {
@@ -428,13 +427,14 @@ std::vector<int> starts_of(const std::vector<int> &blocks) {
 // The grouped launches of a batch: offsets of their argument arrays in the
 // packed buffer, block totals and LDS sizes.
 struct GLaunch {
-  int kind;  // 0 reset, 1 range, 2 Toeplitz stages
+  int kind;  // 0 reset, 1 range, 2 Toeplitz stages, 3 recursive stages
   bf_dtype dt;
   int variant;
   bool seq;
+  int S, cC;
   int cnt;
-  size_t o[6];
-  int t[3];
+  size_t o[8];
+  int t[4];
   size_t lds[2];
 };
 struct BatchPlan {
@@ -542,6 +542,39 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
       L.lds[1] = hl;
       bp.launches.push_back(L);
     }
+  for (bf_dtype dt : {BF_U8, BF_U16, BF_F32})
+    for (int cC : {kCSmall, kCLarge})
+      for (int S = 1; S <= kHThreads; S <<= 1) {
+        std::vector<IirArgs> ar[4];
+        std::vector<int> nb[4];
+        for (int i : gidx) {
+          const ImagePlan &ip = pl->im[i];
+          if (is_toeplitz(ip.variant) || ip.p.dtype != dt || ip.g.cC != cC || ip.g.S != S) continue;
+          char *ws = (char *)pl->d_bws;
+          IirArgs a[4];
+          iir_args(d_in[i], d_out[i], ip.g, tables_of(ip), state_of(ip), ip.d_iir, 0, ip.tab.K_max,
+                   (float4 *)(ws + pl->cb_off[i]), (float4 *)(ws + pl->z_off[i]), (float2 *)(ws + pl->pq_off[i]),
+                   true, true, (float2 *)(ws + pl->glut_off[i]), a);
+          for (int q = 0; q < 4; q++) {
+            ar[q].push_back(a[q]);
+            nb[q].push_back(a[q].gg.gx * a[q].gg.gy * a[q].gg.gz);
+          }
+        }
+        if (ar[0].empty()) continue;
+        GLaunch L{};
+        L.kind = 3;
+        L.dt = dt;
+        L.S = S;
+        L.cC = cC;
+        L.cnt = (int)ar[0].size();
+        for (int q = 0; q < 4; q++) {
+          const std::vector<int> st = starts_of(nb[q]);
+          L.o[2 * q] = bp.pack.add(ar[q]);
+          L.o[2 * q + 1] = bp.pack.add(st);
+          L.t[q] = st.back();
+        }
+        bp.launches.push_back(L);
+      }
 }
 
 // Device side of a batch: the grouped launches (their arguments already in
@@ -559,6 +592,15 @@ bf_status enqueue_batch(bf_plan_s *pl, int n, const void *const *d_in, float *co
                              L.t[0], (const ColmaxArgs *)(d_args + L.o[2]), (const int *)(d_args + L.o[3]), L.t[1],
                              L.cnt);
       pl->rec.end(BF_STAGE_RANGE, s);
+    } else if (L.kind == 3) {
+      IirGroup ig;
+      ig.n = L.cnt;
+      for (int q = 0; q < 4; q++) {
+        ig.a[q] = (const IirArgs *)(d_args + L.o[2 * q]);
+        ig.start[q] = (const int *)(d_args + L.o[2 * q + 1]);
+        ig.total[q] = L.t[q];
+      }
+      e = launch_iir_group(s, L.dt, L.S, L.cC, ig, pl->rec);
     } else {
       const ToepGroup tg{L.cnt,
                          (const ToepVArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]), L.t[0], L.lds[0],
@@ -730,18 +772,21 @@ static bf_status create_plan(const bf_params *params, int32_t n_images, const Kn
     };
     for (int i = 0; i < n_images; i++) {
       const ImagePlan &ip = pl->im[i];
+      const Geom &g = ip.g;
       const bool t = is_toeplitz(ip.variant);
-      const size_t zb = t ? (size_t)ip.tab.K_max * ip.z_per_pair : 0;
-      zsum += zb;
-      pl->rowmax_off.push_back(take((size_t)ip.g.H * ip.g.W * elem_size(ip.p.dtype)));
+      const size_t K = (size_t)ip.tab.K_max;
+      const size_t zb = K * ip.z_per_pair;
+      const size_t cbb = t ? 0 : K * g.nc * 6 * g.Spos * sizeof(float4);
+      zsum += zb + cbb;
+      pl->rowmax_off.push_back(take((size_t)g.H * g.W * elem_size(ip.p.dtype)));
       pl->z_off.push_back(take(zb));
-      pl->pq_off.push_back(take(t ? (size_t)ip.tc.groups * ip.g.H * ip.g.W * sizeof(float2) : 0));
+      pl->pq_off.push_back(take((size_t)(t ? ip.tc.groups : 1) * g.H * g.W * sizeof(float2)));
+      pl->cb_off.push_back(take(cbb));
+      pl->glut_off.push_back(take(t ? 0 : K * 256 * sizeof(float2)));
     }
     size_t budget = (size_t)64 << 30;
     if (const char *b = std::getenv("BF_Z_BUDGET_MB")) budget = (size_t)std::atoll(b) << 20;
-    bool any = false;
-    for (const auto &ip : pl->im) any = any || is_toeplitz(ip.variant);
-    if (any && zsum <= budget) {
+    if (zsum <= budget) {
       if ((s = ensure(&pl->d_bws, pl->bws_bytes, off))) {
         bf_plan_destroy(pl);
         return s;
@@ -1056,11 +1101,11 @@ bf_status autotune(const bf_params &p, Knobs &best) {
   return BF_OK;
 }
 
-// Batch-level choice: a batch runs its Toeplitz images as grouped launches
-// (one launch per stage for all of them) and its recursive images one after
-// another, so the per-image choice can lose to putting every image on the
-// Toeplitz path.  Both assignments are timed on the whole batch (full-range
-// checkerboards, every pair kept) and the faster kept.
+// Batch-level choice: a batch runs one set of grouped launches per variant
+// class, so a mix of classes can lose to putting every image on one class
+// (fuller launches).  The per-image choice and the two single-class
+// assignments are timed on the whole batch (full-range checkerboards, every
+// pair kept) and the fastest kept.
 double time_batch(const bf_params *params, int n, const std::vector<Knobs> &kn, std::vector<void *> &ins,
                   std::vector<float *> &outs, hipStream_t s, hipEvent_t a, hipEvent_t b) {
   std::vector<bf_params> q(params, params + n);
@@ -1100,16 +1145,27 @@ double time_batch(const bf_params *params, int n, const std::vector<Knobs> &kn, 
 }
 
 void autotune_batch(const bf_params *params, int n, std::vector<Knobs> &kn) {
-  std::vector<Knobs> alt = kn;
-  bool differs = false;
-  for (int i = 0; i < n; i++) {
-    const int R = params[i].radius > 0 ? params[i].radius : (int)std::ceil(3.0 * params[i].sigma_s);
-    if (params[i].blur == BF_BLUR_AUTO && kn[i].variant == BF_BLUR_IIR_F32 && R <= 120) {
-      alt[i] = Knobs{BF_BLUR_TOEPLITZ_F16X2, 0, 0};
+  // candidates: the per-image choice, every tuned image on the split-FP16
+  // Toeplitz path, every tuned image on the FP32 recursive path (each class
+  // then runs as one set of grouped launches)
+  std::vector<std::vector<Knobs>> cand(1, kn);
+  for (int v : {(int)BF_BLUR_TOEPLITZ_F16X2, (int)BF_BLUR_IIR_F32}) {
+    std::vector<Knobs> alt = kn;
+    bool differs = false, ok = true;
+    for (int i = 0; i < n; i++) {
+      if (params[i].blur != BF_BLUR_AUTO || kn[i].variant == v) continue;
+      const int R = params[i].radius > 0 ? params[i].radius : (int)std::ceil(3.0 * params[i].sigma_s);
+      const bool fits = v == BF_BLUR_TOEPLITZ_F16X2 ? R <= 120 : (params[i].width <= kMaxWidth && params[i].sigma_s >= 0.5);
+      if (!fits) {
+        ok = false;
+        break;
+      }
+      alt[i] = Knobs{v, v == BF_BLUR_IIR_F32 ? kCSmall : 0, 0};
       differs = true;
     }
+    if (ok && differs) cand.push_back(alt);
   }
-  if (!differs) return;
+  if (cand.size() == 1) return;
   std::vector<void *> ins(n, nullptr);
   std::vector<float *> outs(n, nullptr);
   hipStream_t s = nullptr;
@@ -1128,13 +1184,19 @@ void autotune_batch(const bf_params *params, int n, std::vector<Knobs> &kn) {
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) {
-    const double t_own = time_batch(params, n, kn, ins, outs, s, a, b);
-    const double t_alt = time_batch(params, n, alt, ins, outs, s, a, b);
-    const bool take = t_alt > 0.0 && (t_own < 0.0 || t_alt < t_own);
-    if (std::getenv("BF_TUNE_LOG"))
-      std::fprintf(stderr, "[bf tune] batch of %d: per-image choice %.3f ms, all Toeplitz %.3f ms -> %s\n", n, t_own,
-                   t_alt, take ? "all Toeplitz" : "per-image choice");
-    if (take) kn = alt;
+    double best = -1.0;
+    size_t pick = 0;
+    for (size_t c = 0; c < cand.size(); c++) {
+      const double t = time_batch(params, n, cand[c], ins, outs, s, a, b);
+      if (std::getenv("BF_TUNE_LOG"))
+        std::fprintf(stderr, "[bf tune] batch of %d, assignment %zu (%s): %.3f ms\n", n, c,
+                     c == 0 ? "per-image choice" : (c == 1 ? "all split-FP16 Toeplitz" : "all FP32 recursive"), t);
+      if (t > 0.0 && (best < 0.0 || t < best)) {
+        best = t;
+        pick = c;
+      }
+    }
+    kn = cand[pick];
   }
   for (int i = 0; i < n; i++) {
     (void)hipFree(ins[i]);

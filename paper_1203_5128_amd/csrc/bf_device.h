@@ -146,6 +146,22 @@ struct FinishArgs {  // sum of the groups' partial sums and the division
   int groups;
 };
 
+struct IirArgs {  // the four recursive-path kernels (each with its own grid)
+  GroupGrid gg;
+  const void *f;
+  float *out;
+  Geom g;
+  DevTables tab;
+  DevState st;
+  const float *iir;
+  int k0, kcount;
+  float4 *cb;
+  float4 *Z;
+  float2 *PQ;
+  int first, last;
+  float2 *glut;
+};
+
 // Optional recorder of stage boundaries (host side): called before and after
 // each stage's launches on the launch stream.
 struct StageRec {
@@ -173,6 +189,19 @@ hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *ou
                             DevTables tab, DevState st, const float *iir, int k0, int kcount,
                             float4 *cb, float4 *Z, float2 *PQ, bool first, bool last,
                             float2 *glut, const StageRec &rec);
+
+// Arguments of the recursive-path kernels of one image ([0] summary, [1]
+// carries, [2] final vertical, [3] horizontal + combine), and a grouped launch
+// of those stages over n images of one dtype, threads per row and chunk.
+void iir_args(const void *f, float *out, const Geom &g, DevTables tab, DevState st, const float *iir, int k0,
+              int kcount, float4 *cb, float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, IirArgs a[4]);
+struct IirGroup {
+  int n;
+  const IirArgs *a[4];
+  const int *start[4];
+  int total[4];
+};
+hipError_t launch_iir_group(hipStream_t s, bf_dtype dt, int S, int cC, const IirGroup &ig, const StageRec &rec);
 
 // ---- Toeplitz MFMA path (bf_toeplitz.hip) ----
 // LDS bytes of the two kernels' dynamic tiles, and the horizontal tile width.

@@ -475,13 +475,18 @@ __global__ __launch_bounds__(64) void k_colmax_T_seq_grp(const ColmaxArgs *__res
 // columns [t c, t c + c), reads consecutive addresses.
 
 template <typename Tin>
-__global__ __launch_bounds__(kVThreads) void k_iir_v_summary(const Tin *__restrict__ f, Geom g,
-                                                             DevTables tab, DevState st,
-                                                             const float *__restrict__ iir, int k0,
-                                                             float4 *__restrict__ cb) {
-  const int p = blockIdx.x * kVThreads + threadIdx.x;
-  const int j = blockIdx.y;
-  const int kl = blockIdx.z;
+__device__ __forceinline__ void iir_v_summary_body(const IirArgs &a, const Blk b) {
+  const Tin *__restrict__ f = (const Tin *)a.f;
+  const Geom g = a.g;
+  const DevTables tab = a.tab;
+  const DevState st = a.st;
+  const float *__restrict__ iir = a.iir;
+  const int k0 = a.k0;
+  float4 *__restrict__ cb = a.cb;
+
+  const int p = b.x * kVThreads + threadIdx.x;
+  const int j = b.y;
+  const int kl = b.z;
   const OrderEntry &e = lookup(tab, st.T_used);
   const int k = k0 + kl;
   if (k >= e.K) return;
@@ -523,12 +528,27 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_summary(const Tin *__restri
   cb[(base + 4) * g.Spos + p] = b1;
   cb[(base + 5) * g.Spos + p] = b2;
 }
+template <typename Tin>
+__global__ __launch_bounds__(kVThreads) void k_iir_v_summary(IirArgs a) {
+  iir_v_summary_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z});
+}
+template <typename Tin>
+__global__ __launch_bounds__(kVThreads) void k_iir_v_summary_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
+                                                     int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  iir_v_summary_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+}
 
-__global__ __launch_bounds__(kVThreads) void k_iir_v_fixup(Geom g, DevTables tab, DevState st,
-                                                           const float *__restrict__ iir, int k0,
-                                                           float4 *__restrict__ cb) {
-  const int p = blockIdx.x * kVThreads + threadIdx.x;
-  const int kl = blockIdx.y;
+__device__ __forceinline__ void iir_v_fixup_body(const IirArgs &a, const Blk b) {
+  const Geom g = a.g;
+  const DevTables tab = a.tab;
+  const DevState st = a.st;
+  const float *__restrict__ iir = a.iir;
+  const int k0 = a.k0;
+  float4 *__restrict__ cb = a.cb;
+
+  const int p = b.x * kVThreads + threadIdx.x;
+  const int kl = b.y;
   const OrderEntry &e = lookup(tab, st.T_used);
   const int k = k0 + kl;
   if (k >= e.K || p >= g.Spos) return;
@@ -588,17 +608,30 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_fixup(Geom g, DevTables tab
       }
   }
 }
+__global__ __launch_bounds__(kVThreads) void k_iir_v_fixup(IirArgs a) {
+  iir_v_fixup_body(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
+}
+__global__ __launch_bounds__(kVThreads) void k_iir_v_fixup_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
+                                                     int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  iir_v_fixup_body(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+}
 
 template <typename Tin>
-__global__ __launch_bounds__(kVThreads) void k_iir_v_final(const Tin *__restrict__ f, Geom g,
-                                                           DevTables tab, DevState st,
-                                                           const float *__restrict__ iir, int k0,
-                                                           const float4 *__restrict__ cb,
-                                                           float4 *__restrict__ Z,
-                                                           float2 *__restrict__ glut) {
-  const int p = blockIdx.x * kVThreads + threadIdx.x;
-  const int j = blockIdx.y;
-  const int kl = blockIdx.z;
+__device__ __forceinline__ void iir_v_final_body(const IirArgs &a, const Blk b) {
+  const Tin *__restrict__ f = (const Tin *)a.f;
+  const Geom g = a.g;
+  const DevTables tab = a.tab;
+  const DevState st = a.st;
+  const float *__restrict__ iir = a.iir;
+  const int k0 = a.k0;
+  const float4 *__restrict__ cb = a.cb;
+  float4 *__restrict__ Z = a.Z;
+  float2 *__restrict__ glut = a.glut;
+
+  const int p = b.x * kVThreads + threadIdx.x;
+  const int j = b.y;
+  const int kl = b.z;
   const OrderEntry &e = lookup(tab, st.T_used);
   const int k = k0 + kl;
   if (k >= e.K) return;
@@ -609,7 +642,7 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_final(const Tin *__restrict
   if constexpr (PhaseLut<Tin>::kOn) {
     build_lut(lut, m, q, at, threadIdx.x, kVThreads);
     // one workgroup per pair also leaves the table for the horizontal pass
-    if (blockIdx.x == 0 && j == 0) glut[(size_t)kl * 256 + threadIdx.x] = lut[threadIdx.x];
+    if (b.x == 0 && j == 0) glut[(size_t)kl * 256 + threadIdx.x] = lut[threadIdx.x];
     __syncthreads();
   }
   if (p >= g.Spos) return;
@@ -648,6 +681,16 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_final(const Tin *__restrict
     if (y < g.H) Zk[(size_t)y * g.Spos + p] = w;
   }
 }
+template <typename Tin>
+__global__ __launch_bounds__(kVThreads) void k_iir_v_final(IirArgs a) {
+  iir_v_final_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z});
+}
+template <typename Tin>
+__global__ __launch_bounds__(kVThreads) void k_iir_v_final_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
+                                                     int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  iir_v_final_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+}
 
 // ------------------------------------ horizontal pass + accumulate (a4, a5)
 // One workgroup per image row; S threads per row group, NG = 256/S groups each
@@ -682,13 +725,19 @@ __device__ __forceinline__ void scan_down(float4 v[3], const float *__restrict__
 }
 
 template <typename Tin, int S, int kC>
-__global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict__ f,
-                                                           float *__restrict__ out, Geom g,
-                                                           DevTables tab, DevState st,
-                                                           const float *__restrict__ iir, int k0,
-                                                           int kcount, const float4 *__restrict__ Z,
-                                                           float2 *__restrict__ PQ, int first,
-                                                           int last, const float2 *__restrict__ glut) {
+__device__ __forceinline__ void iir_h_accum_body(const IirArgs &a, const Blk b) {
+  const Tin *__restrict__ f = (const Tin *)a.f;
+  float *__restrict__ out = a.out;
+  const Geom g = a.g;
+  const DevTables tab = a.tab;
+  const DevState st = a.st;
+  const float *__restrict__ iir = a.iir;
+  const int k0 = a.k0, kcount = a.kcount;
+  const float4 *__restrict__ Z = a.Z;
+  float2 *__restrict__ PQ = a.PQ;
+  const int first = a.first, last = a.last;
+  const float2 *__restrict__ glut = a.glut;
+
   constexpr int NG = kHThreads / S;
   constexpr int SW = S < 64 ? S : 64;
   constexpr int NW = S > 64 ? S / 64 : 1;
@@ -697,7 +746,7 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
   // groups are summed at the end
   __shared__ float2 spq[NG * PAD];
   __shared__ float4 xw[NG][NW][3];
-  const int y = blockIdx.x;
+  const int y = b.x;
   const int tid = threadIdx.x;
   const int t = tid % S;
   const int grp = tid / S;
@@ -871,6 +920,16 @@ __global__ __launch_bounds__(kHThreads) void k_iir_h_accum(const Tin *__restrict
     if ((tid & 63) == 0 && nbad) atomicAdd(st.q_nonpos, nbad);
   }
 }
+template <typename Tin, int S, int kC>
+__global__ __launch_bounds__(kHThreads) void k_iir_h_accum(IirArgs a) {
+  iir_h_accum_body<Tin, S, kC>(a, Blk{(int)blockIdx.x, 0, 0});
+}
+template <typename Tin, int S, int kC>
+__global__ __launch_bounds__(kHThreads) void k_iir_h_accum_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
+                                                     int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  iir_h_accum_body<Tin, S, kC>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+}
 
 // ------------------------------------------------------------- launchers
 // Full-range test input of the autotuner: 0 and `top` alternating like a
@@ -958,57 +1017,103 @@ hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g
   }
 }
 
-template <typename Tin, int S, int C>
-static void launch_h(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab, DevState st,
-                     const float *iir, int k0, int kcount, const float4 *Z, float2 *PQ, bool first,
-                     bool last, const float2 *glut) {
-  hipLaunchKernelGGL((k_iir_h_accum<Tin, S, C>), dim3(g.H), dim3(kHThreads), 0, s, f, out, g, tab, st, iir,
-                     k0, kcount, Z, PQ, (int)first, (int)last, glut);
+// Per-image arguments of the four recursive-path kernels for pairs
+// [k0, k0+kcount) (also the per-image entries of grouped launches).
+void iir_args(const void *f, float *out, const Geom &g, DevTables tab, DevState st, const float *iir, int k0,
+              int kcount, float4 *cb, float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, IirArgs a[4]) {
+  const int nbx = (g.Spos + kVThreads - 1) / kVThreads;
+  const IirArgs base{GroupGrid{1, 1, 1}, f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, (int)first, (int)last, glut};
+  for (int i = 0; i < 4; i++) a[i] = base;
+  a[0].gg = GroupGrid{nbx, g.nc, kcount};  // summary
+  a[1].gg = GroupGrid{nbx, kcount, 1};     // carries
+  a[2].gg = GroupGrid{nbx, g.nc, kcount};  // final
+  a[3].gg = GroupGrid{g.H, 1, 1};          // horizontal + combine
 }
 
+// Launch of the horizontal kernel for threads-per-row S and chunk C, single
+// image (args) or grouped (arr, start, n, total).
+template <typename Tin, int S, int C>
+static void launch_h(hipStream_t s, const IirArgs *one, const IirArgs *arr, const int *start, int n, int total) {
+  if (one)
+    hipLaunchKernelGGL((k_iir_h_accum<Tin, S, C>), dim3(one->gg.gx), dim3(kHThreads), 0, s, *one);
+  else if (total > 0)
+    hipLaunchKernelGGL((k_iir_h_accum_grp<Tin, S, C>), dim3(total), dim3(kHThreads), 0, s, arr, start, n);
+}
 template <typename Tin, int C>
-static bool launch_h_S(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab, DevState st,
-                       const float *iir, int k0, int kcount, const float4 *Z, float2 *PQ, bool first,
-                       bool last, const float2 *glut) {
-  switch (g.S) {
-    case 1: launch_h<Tin, 1, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
-    case 2: launch_h<Tin, 2, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
-    case 4: launch_h<Tin, 4, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
-    case 8: launch_h<Tin, 8, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
-    case 16: launch_h<Tin, 16, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
-    case 32: launch_h<Tin, 32, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
-    case 64: launch_h<Tin, 64, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
-    case 128: launch_h<Tin, 128, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
-    case 256: launch_h<Tin, 256, C>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut); return true;
+static bool launch_h_S(hipStream_t s, int S, const IirArgs *one, const IirArgs *arr, const int *start, int n,
+                       int total) {
+  switch (S) {
+    case 1: launch_h<Tin, 1, C>(s, one, arr, start, n, total); return true;
+    case 2: launch_h<Tin, 2, C>(s, one, arr, start, n, total); return true;
+    case 4: launch_h<Tin, 4, C>(s, one, arr, start, n, total); return true;
+    case 8: launch_h<Tin, 8, C>(s, one, arr, start, n, total); return true;
+    case 16: launch_h<Tin, 16, C>(s, one, arr, start, n, total); return true;
+    case 32: launch_h<Tin, 32, C>(s, one, arr, start, n, total); return true;
+    case 64: launch_h<Tin, 64, C>(s, one, arr, start, n, total); return true;
+    case 128: launch_h<Tin, 128, C>(s, one, arr, start, n, total); return true;
+    case 256: launch_h<Tin, 256, C>(s, one, arr, start, n, total); return true;
     default: return false;
   }
+}
+template <typename Tin>
+static bool launch_h_any(hipStream_t s, int S, int cC, const IirArgs *one, const IirArgs *arr, const int *start,
+                         int n, int total) {
+  return cC == kCSmall ? launch_h_S<Tin, kCSmall>(s, S, one, arr, start, n, total)
+                       : launch_h_S<Tin, kCLarge>(s, S, one, arr, start, n, total);
 }
 
 template <typename Tin>
 static hipError_t iir_chunk_t(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab,
                               DevState st, const float *iir, int k0, int kcount, float4 *cb, float4 *Z,
                               float2 *PQ, bool first, bool last, float2 *glut, const StageRec &rec) {
-  const int nbx = (g.Spos + kVThreads - 1) / kVThreads;
+  IirArgs a[4];
+  iir_args(f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, first, last, glut, a);
   if (kcount > 0) {
     rec.begin(BF_STAGE_V_SUMMARY, s);
-    hipLaunchKernelGGL(k_iir_v_summary<Tin>, dim3(nbx, g.nc, kcount), dim3(kVThreads), 0, s, f, g, tab,
-                       st, iir, k0, cb);
+    hipLaunchKernelGGL(k_iir_v_summary<Tin>, dim3(a[0].gg.gx, a[0].gg.gy, a[0].gg.gz), dim3(kVThreads), 0, s, a[0]);
     rec.end(BF_STAGE_V_SUMMARY, s);
     rec.begin(BF_STAGE_V_CARRY, s);
-    hipLaunchKernelGGL(k_iir_v_fixup, dim3(nbx, kcount), dim3(kVThreads), 0, s, g, tab, st, iir, k0, cb);
+    hipLaunchKernelGGL(k_iir_v_fixup, dim3(a[1].gg.gx, a[1].gg.gy), dim3(kVThreads), 0, s, a[1]);
     rec.end(BF_STAGE_V_CARRY, s);
     rec.begin(BF_STAGE_V_FINAL, s);
-    hipLaunchKernelGGL(k_iir_v_final<Tin>, dim3(nbx, g.nc, kcount), dim3(kVThreads), 0, s, f, g, tab, st,
-                       iir, k0, (const float4 *)cb, Z, glut);
+    hipLaunchKernelGGL(k_iir_v_final<Tin>, dim3(a[2].gg.gx, a[2].gg.gy, a[2].gg.gz), dim3(kVThreads), 0, s, a[2]);
     rec.end(BF_STAGE_V_FINAL, s);
   }
   rec.begin(BF_STAGE_H_COMBINE, s);
-  const bool ok = g.cC == kCSmall
-                      ? launch_h_S<Tin, kCSmall>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut)
-                      : launch_h_S<Tin, kCLarge>(s, f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut);
+  const bool ok = launch_h_any<Tin>(s, g.S, g.cC, &a[3], nullptr, nullptr, 0, 0);
   if (!ok) return hipErrorInvalidValue;
   rec.end(BF_STAGE_H_COMBINE, s);
   return hipGetLastError();
+}
+
+// Grouped recursive-path stages over n images of one dtype, threads-per-row
+// S and chunk cC (single launch of all their pairs each).
+template <typename Tin>
+static hipError_t iir_group_t(hipStream_t s, int S, int cC, const IirGroup &ig, const StageRec &rec) {
+  rec.begin(BF_STAGE_V_SUMMARY, s);
+  if (ig.total[0] > 0)
+    hipLaunchKernelGGL(k_iir_v_summary_grp<Tin>, dim3(ig.total[0]), dim3(kVThreads), 0, s, ig.a[0], ig.start[0], ig.n);
+  rec.end(BF_STAGE_V_SUMMARY, s);
+  rec.begin(BF_STAGE_V_CARRY, s);
+  if (ig.total[1] > 0)
+    hipLaunchKernelGGL(k_iir_v_fixup_grp, dim3(ig.total[1]), dim3(kVThreads), 0, s, ig.a[1], ig.start[1], ig.n);
+  rec.end(BF_STAGE_V_CARRY, s);
+  rec.begin(BF_STAGE_V_FINAL, s);
+  if (ig.total[2] > 0)
+    hipLaunchKernelGGL(k_iir_v_final_grp<Tin>, dim3(ig.total[2]), dim3(kVThreads), 0, s, ig.a[2], ig.start[2], ig.n);
+  rec.end(BF_STAGE_V_FINAL, s);
+  rec.begin(BF_STAGE_H_COMBINE, s);
+  const bool ok = launch_h_any<Tin>(s, S, cC, nullptr, ig.a[3], ig.start[3], ig.n, ig.total[3]);
+  rec.end(BF_STAGE_H_COMBINE, s);
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+hipError_t launch_iir_group(hipStream_t s, bf_dtype dt, int S, int cC, const IirGroup &ig, const StageRec &rec) {
+  switch (dt) {
+    case BF_U8: return iir_group_t<uint8_t>(s, S, cC, ig, rec);
+    case BF_U16: return iir_group_t<uint16_t>(s, S, cC, ig, rec);
+    default: return iir_group_t<float>(s, S, cC, ig, rec);
+  }
 }
 
 hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *out, const Geom &g,

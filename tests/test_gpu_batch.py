@@ -1,11 +1,10 @@
 """GPU batches: images of uneven sizes with per-image sigma_s, sigma_r (and
 dtypes and variants) filtered by one bf_filter_batch call.
 
-Images on the Toeplitz path run as grouped launches (one launch per stage for
-all of them); each grouped output must equal, bit for bit, the same image
-filtered alone by its own plan, and match the FP64 oracle within the
-variant's tolerance.  Images on the recursive path in the same batch run
-their own launch sequences inside the same graph.
+Images run as grouped launches (one launch per stage for all images of one
+dtype and variant class); each grouped output must equal, bit for bit, the
+same image filtered alone by its own plan, and match the FP64 oracle within
+the variant's tolerance.
 """
 import os
 
