@@ -475,14 +475,7 @@ __global__ __launch_bounds__(64) void k_colmax_T_seq_grp(const ColmaxArgs *__res
 // columns [t c, t c + c), reads consecutive addresses.
 
 template <typename Tin>
-__device__ __forceinline__ void iir_v_summary_body(const IirArgs &a, const Blk b) {
-  const Tin *__restrict__ f = (const Tin *)a.f;
-  const Geom g = a.g;
-  const DevTables tab = a.tab;
-  const DevState st = a.st;
-  const float *__restrict__ iir = a.iir;
-  const int k0 = a.k0;
-  float4 *__restrict__ cb = a.cb;
+__device__ __forceinline__ void iir_v_summary_impl(const Tin *__restrict__ f, const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, float4 *__restrict__ cb, const Blk b) {
 
   const int p = b.x * kVThreads + threadIdx.x;
   const int j = b.y;
@@ -529,6 +522,11 @@ __device__ __forceinline__ void iir_v_summary_body(const IirArgs &a, const Blk b
   cb[(base + 5) * g.Spos + p] = b2;
 }
 template <typename Tin>
+__device__ __forceinline__ void iir_v_summary_body(const IirArgs &a, const Blk b) {
+  iir_v_summary_impl<Tin>((const Tin *)a.f, a.g, a.tab, a.st, a.iir, a.k0, a.cb, b);
+}
+
+template <typename Tin>
 __global__ __launch_bounds__(kVThreads) void k_iir_v_summary(IirArgs a) {
   iir_v_summary_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z});
 }
@@ -539,13 +537,7 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_summary_grp(const IirArgs *
   iir_v_summary_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
 }
 
-__device__ __forceinline__ void iir_v_fixup_body(const IirArgs &a, const Blk b) {
-  const Geom g = a.g;
-  const DevTables tab = a.tab;
-  const DevState st = a.st;
-  const float *__restrict__ iir = a.iir;
-  const int k0 = a.k0;
-  float4 *__restrict__ cb = a.cb;
+__device__ __forceinline__ void iir_v_fixup_impl(const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, float4 *__restrict__ cb, const Blk b) {
 
   const int p = b.x * kVThreads + threadIdx.x;
   const int kl = b.y;
@@ -608,6 +600,10 @@ __device__ __forceinline__ void iir_v_fixup_body(const IirArgs &a, const Blk b) 
       }
   }
 }
+__device__ __forceinline__ void iir_v_fixup_body(const IirArgs &a, const Blk b) {
+  iir_v_fixup_impl(a.g, a.tab, a.st, a.iir, a.k0, a.cb, b);
+}
+
 __global__ __launch_bounds__(kVThreads) void k_iir_v_fixup(IirArgs a) {
   iir_v_fixup_body(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
 }
@@ -618,16 +614,7 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_fixup_grp(const IirArgs *__
 }
 
 template <typename Tin>
-__device__ __forceinline__ void iir_v_final_body(const IirArgs &a, const Blk b) {
-  const Tin *__restrict__ f = (const Tin *)a.f;
-  const Geom g = a.g;
-  const DevTables tab = a.tab;
-  const DevState st = a.st;
-  const float *__restrict__ iir = a.iir;
-  const int k0 = a.k0;
-  const float4 *__restrict__ cb = a.cb;
-  float4 *__restrict__ Z = a.Z;
-  float2 *__restrict__ glut = a.glut;
+__device__ __forceinline__ void iir_v_final_impl(const Tin *__restrict__ f, const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, const float4 *__restrict__ cb, float4 *__restrict__ Z, float2 *__restrict__ glut, const Blk b) {
 
   const int p = b.x * kVThreads + threadIdx.x;
   const int j = b.y;
@@ -682,6 +669,11 @@ __device__ __forceinline__ void iir_v_final_body(const IirArgs &a, const Blk b) 
   }
 }
 template <typename Tin>
+__device__ __forceinline__ void iir_v_final_body(const IirArgs &a, const Blk b) {
+  iir_v_final_impl<Tin>((const Tin *)a.f, a.g, a.tab, a.st, a.iir, a.k0, a.cb, a.Z, a.glut, b);
+}
+
+template <typename Tin>
 __global__ __launch_bounds__(kVThreads) void k_iir_v_final(IirArgs a) {
   iir_v_final_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z});
 }
@@ -725,18 +717,7 @@ __device__ __forceinline__ void scan_down(float4 v[3], const float *__restrict__
 }
 
 template <typename Tin, int S, int kC>
-__device__ __forceinline__ void iir_h_accum_body(const IirArgs &a, const Blk b) {
-  const Tin *__restrict__ f = (const Tin *)a.f;
-  float *__restrict__ out = a.out;
-  const Geom g = a.g;
-  const DevTables tab = a.tab;
-  const DevState st = a.st;
-  const float *__restrict__ iir = a.iir;
-  const int k0 = a.k0, kcount = a.kcount;
-  const float4 *__restrict__ Z = a.Z;
-  float2 *__restrict__ PQ = a.PQ;
-  const int first = a.first, last = a.last;
-  const float2 *__restrict__ glut = a.glut;
+__device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, float *__restrict__ out, const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, int kcount, const float4 *__restrict__ Z, float2 *__restrict__ PQ, int first, int last, const float2 *__restrict__ glut, const Blk b) {
 
   constexpr int NG = kHThreads / S;
   constexpr int SW = S < 64 ? S : 64;
@@ -921,11 +902,16 @@ __device__ __forceinline__ void iir_h_accum_body(const IirArgs &a, const Blk b) 
   }
 }
 template <typename Tin, int S, int kC>
-__global__ __launch_bounds__(kHThreads) void k_iir_h_accum(IirArgs a) {
+__device__ __forceinline__ void iir_h_accum_body(const IirArgs &a, const Blk b) {
+  iir_h_accum_impl<Tin, S, kC>((const Tin *)a.f, a.out, a.g, a.tab, a.st, a.iir, a.k0, a.kcount, a.Z, a.PQ, a.first, a.last, a.glut, b);
+}
+
+template <typename Tin, int S, int kC>
+__global__ __launch_bounds__(kHThreads, kC == kCSmall ? 2 : 1) void k_iir_h_accum(IirArgs a) {
   iir_h_accum_body<Tin, S, kC>(a, Blk{(int)blockIdx.x, 0, 0});
 }
 template <typename Tin, int S, int kC>
-__global__ __launch_bounds__(kHThreads) void k_iir_h_accum_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
+__global__ __launch_bounds__(kHThreads, kC == kCSmall ? 2 : 1) void k_iir_h_accum_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
                                                      int n) {
   const int i = group_find(start, n, blockIdx.x);
   iir_h_accum_body<Tin, S, kC>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));

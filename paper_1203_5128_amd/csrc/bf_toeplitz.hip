@@ -100,6 +100,26 @@ __device__ __forceinline__ void build_tap_frags(typename MT<BF>::V *th, typename
 // LDS bytes of the tap fragments.
 constexpr size_t tap_frag_bytes(int nks, bool split) { return (size_t)(split ? 2 : 1) * nks * 64 * 16; }
 
+// Eight FP32 values as 16-bit operands: hi alone (single variants, rounded to
+// nearest), or hi + lo (split variants), where hi keeps the leading bits that
+// the 16-bit format holds (a mask of the FP32 word, so hi converts exactly
+// and lo = v - hi is exact in FP32) and lo is v - hi rounded.
+template <bool BF, bool SPLIT>
+__device__ __forceinline__ void to_operands(const float v[8], typename MT<BF>::V &h, typename MT<BF>::V &l) {
+  typedef typename MT<BF>::T E;
+  constexpr uint32_t kKeep = BF ? 0xFFFF0000u : 0xFFFFE000u;
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    if constexpr (SPLIT) {
+      const float hf = __uint_as_float(__float_as_uint(v[j]) & kKeep);
+      h[j] = (E)hf;
+      l[j] = (E)(v[j] - hf);
+    } else {
+      h[j] = (E)v[j];
+    }
+  }
+}
+
 // ------------------------------------------------------------ vertical pass
 // Workgroup: `rows` output rows x kVCols pixel columns of one frequency pair.
 // The four images of the pair on the input rows [y0 - R, y0 + rows + R) are
@@ -158,32 +178,36 @@ __device__ __forceinline__ void toep_v_body(const ToepVArgs &a, const Blk b) {
   for (int it = tid; it < nstrip * kCols; it += 256) {
     const int c = it % kCols, sidx = it / kCols;
     const int x = x0 + c;
-    const int xc = min(x, g.W - 1);
     const int ybase = y0 - R + 8 * sidx;
+    const bool inner = x < g.W && ybase >= 0 && ybase + 8 <= g.H;  // all eight pixels in the image
     Tin raw[8];
+    if (inner) {
+      const Tin *src = f + (int64_t)ybase * g.pitch + x;
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const int yc = min(max(ybase + j, 0), g.H - 1);
-      raw[j] = f[(int64_t)yc * g.pitch + xc];
+      for (int j = 0; j < 8; j++) raw[j] = src[(int64_t)j * g.pitch];
+    } else {
+      const int xc = min(x, g.W - 1);
+#pragma unroll
+      for (int j = 0; j < 8; j++) raw[j] = f[(int64_t)min(max(ybase + j, 0), g.H - 1) * g.pitch + xc];
     }
     float pv[4][8];
 #pragma unroll
     for (int j = 0; j < 8; j++) {
-      const bool ok = ybase + j >= 0 && ybase + j < g.H && x < g.W;
       const float4 p = planes_any<Tin>(raw[j], lut, fq, g.center);
-      pv[0][j] = ok ? p.x * inv : 0.f;
-      pv[1][j] = ok ? p.y * inv : 0.f;
-      pv[2][j] = ok ? p.z : 0.f;
-      pv[3][j] = ok ? p.w : 0.f;
+      pv[0][j] = p.x * inv;
+      pv[1][j] = p.y * inv;
+      pv[2][j] = p.z;
+      pv[3][j] = p.w;
+    }
+    if (!inner) {  // pixels off the image contribute zeros
+#pragma unroll
+      for (int j = 0; j < 8; j++)
+        if (!(x < g.W && ybase + j >= 0 && ybase + j < g.H)) pv[0][j] = pv[1][j] = pv[2][j] = pv[3][j] = 0.f;
     }
 #pragma unroll
     for (int p = 0; p < 4; p++) {
       V h, l;
-#pragma unroll
-      for (int j = 0; j < 8; j++) {
-        h[j] = (E)pv[p][j];
-        l[j] = (E)(pv[p][j] - (float)h[j]);
-      }
+      to_operands<BF, SPLIT>(pv[p], h, l);
       *(V *)(Bh + (p * kCols + c) * Kp + 8 * sidx) = h;
       if (SPLIT) *(V *)(Bl + (p * kCols + c) * Kp + 8 * sidx) = l;
     }
@@ -363,13 +387,12 @@ __device__ __forceinline__ void toep_h_body(const ToepHArgs &a, const Blk b) {
         V h, l;
         if constexpr (SPLIT) {
           const float4 a0 = raw[u][0], a1 = raw[u][kLw - 1];
-          const float vals[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+          float vals[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+          if (msk[u] != 0xFFu) {  // edge vectors only
 #pragma unroll
-          for (int j = 0; j < 8; j++) {
-            const float v8 = ((msk[u] >> j) & 1u) ? vals[j] : 0.f;
-            h[j] = (E)v8;
-            l[j] = (E)(v8 - (float)h[j]);
+            for (int j = 0; j < 8; j++) vals[j] = ((msk[u] >> j) & 1u) ? vals[j] : 0.f;
           }
+          to_operands<BF, true>(vals, h, l);
         } else {
           h = raw[u][0];
           if (msk[u] != 0xFFu) {  // edge vectors only
