@@ -265,6 +265,20 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   size_t kc = budget / per_pair;
   if (kc < 1) kc = 1;
   ip.KC = (int)std::min<size_t>(std::min<size_t>(kc, (size_t)ip.tab.K_max), 65535);
+  g.hgroups = 1;
+  g.hkpg = ip.KC;
+  if (!is_toeplitz(variant)) {
+    // horizontal pass: split the pairs of a launch over enough rows of
+    // workgroups to fill the GPU, each group a whole number of the NG pairs a
+    // workgroup handles at once
+    const int ng = kHThreads / g.S;
+    const int slots = (ip.KC + ng - 1) / ng;
+    int target = kHWorkgroups;
+    if (const char *w = std::getenv("BF_H_WG")) target = std::max(1, std::atoi(w));
+    const int groups = std::max(1, std::min(slots, (target + g.H - 1) / g.H));
+    g.hkpg = (slots + groups - 1) / groups * ng;
+    g.hgroups = (ip.KC + g.hkpg - 1) / g.hkpg;
+  }
   if (is_toeplitz(variant)) {
     // split the pairs of a launch over enough horizontal workgroups to fill the GPU
     const int tiles = toeplitz_h_tiles(variant, g.H, g.W);
@@ -433,8 +447,8 @@ struct GLaunch {
   bool seq;
   int S, cC;
   int cnt;
-  size_t o[8];
-  int t[4];
+  size_t o[10];
+  int t[5];
   size_t lds[2];
 };
 struct BatchPlan {
@@ -546,19 +560,23 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
     for (int cC : {kCSmall, kCLarge})
       for (int S = 1; S <= kHThreads; S <<= 1) {
         std::vector<IirArgs> ar[4];
-        std::vector<int> nb[4];
+        std::vector<FinishArgs> fa;
+        std::vector<int> nb[5];
         for (int i : gidx) {
           const ImagePlan &ip = pl->im[i];
           if (is_toeplitz(ip.variant) || ip.p.dtype != dt || ip.g.cC != cC || ip.g.S != S) continue;
           char *ws = (char *)pl->d_bws;
           IirArgs a[4];
+          FinishArgs c;
           iir_args(d_in[i], d_out[i], ip.g, tables_of(ip), state_of(ip), ip.d_iir, 0, ip.tab.K_max,
                    (float4 *)(ws + pl->cb_off[i]), (float4 *)(ws + pl->z_off[i]), (float2 *)(ws + pl->pq_off[i]),
-                   true, true, (float2 *)(ws + pl->glut_off[i]), a);
+                   true, true, (float2 *)(ws + pl->glut_off[i]), a, c);
           for (int q = 0; q < 4; q++) {
             ar[q].push_back(a[q]);
             nb[q].push_back(a[q].gg.gx * a[q].gg.gy * a[q].gg.gz);
           }
+          fa.push_back(c);
+          nb[4].push_back(ip.g.hgroups > 1 ? c.gg.gx : 0);
         }
         if (ar[0].empty()) continue;
         GLaunch L{};
@@ -573,6 +591,10 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
           L.o[2 * q + 1] = bp.pack.add(st);
           L.t[q] = st.back();
         }
+        const std::vector<int> fs = starts_of(nb[4]);
+        L.o[8] = bp.pack.add(fa);
+        L.o[9] = bp.pack.add(fs);
+        L.t[4] = fs.back();
         bp.launches.push_back(L);
       }
 }
@@ -600,6 +622,9 @@ bf_status enqueue_batch(bf_plan_s *pl, int n, const void *const *d_in, float *co
         ig.start[q] = (const int *)(d_args + L.o[2 * q + 1]);
         ig.total[q] = L.t[q];
       }
+      ig.fa = (const FinishArgs *)(d_args + L.o[8]);
+      ig.fstart = (const int *)(d_args + L.o[9]);
+      ig.ftotal = L.t[4];
       e = launch_iir_group(s, L.dt, L.S, L.cC, ig, pl->rec);
     } else {
       const ToepGroup tg{L.cnt,
@@ -752,7 +777,7 @@ static bf_status create_plan(const bf_params *params, int32_t n_images, const Kn
       lut = std::max(lut, (size_t)ip.KC * 256 * sizeof(float2));
     }
     Z = std::max(Z, (size_t)ip.KC * ip.z_per_pair);
-    PQ = std::max(PQ, (size_t)(is_toeplitz(ip.variant) ? ip.tc.groups : 1) * g.H * g.W * sizeof(float2));
+    PQ = std::max(PQ, (size_t)(is_toeplitz(ip.variant) ? ip.tc.groups : g.hgroups) * g.H * g.W * sizeof(float2));
   }
   bf_status s;
   if ((s = ensure(&pl->d_rowmax, pl->rowmax_bytes, rowmax)) || (s = ensure((void **)&pl->d_cb, pl->cb_bytes, cb)) ||
@@ -780,7 +805,7 @@ static bf_status create_plan(const bf_params *params, int32_t n_images, const Kn
       zsum += zb + cbb;
       pl->rowmax_off.push_back(take((size_t)g.H * g.W * elem_size(ip.p.dtype)));
       pl->z_off.push_back(take(zb));
-      pl->pq_off.push_back(take((size_t)(t ? ip.tc.groups : 1) * g.H * g.W * sizeof(float2)));
+      pl->pq_off.push_back(take((size_t)(t ? ip.tc.groups : g.hgroups) * g.H * g.W * sizeof(float2)));
       pl->cb_off.push_back(take(cbb));
       pl->glut_off.push_back(take(t ? 0 : K * 256 * sizeof(float2)));
     }

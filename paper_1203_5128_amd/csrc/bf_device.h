@@ -4,10 +4,17 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "bf_internal.h"
 
 namespace bfi {
+
+// bf_dtype of an element type
+template <typename Tin>
+constexpr bf_dtype dtype_of() {
+  return std::is_same<Tin, uint8_t>::value ? BF_U8 : (std::is_same<Tin, uint16_t>::value ? BF_U16 : BF_F32);
+}
 
 // Order table on the device (uploaded copy of OrderTable).
 struct DevTables {
@@ -35,6 +42,9 @@ struct Geom {
   int cC;             // pixels per thread in the horizontal pass (kCSmall or kCLarge)
   int Spos;           // S * cC positions per padded row
   int nc;             // vertical chunks of kB rows
+  // horizontal pass: the pairs of a launch are split into hgroups groups of
+  // hkpg pairs, each a row of workgroups with its own partial sums
+  int hgroups, hkpg;
   float center;       // intensity subtracted from f in the f*cos, f*sin images
   // Toeplitz path: smoothed images stored with a left pad of padl elements
   // (padl = R mod 8) and a row pitch of zpitch elements (multiple of 8)
@@ -144,6 +154,7 @@ struct FinishArgs {  // sum of the groups' partial sums and the division
   DevState st;
   const float2 *PQ;
   int groups;
+  float rscale;  // out = center + rscale * P / Q
 };
 
 struct IirArgs {  // the four recursive-path kernels (each with its own grid)
@@ -191,16 +202,25 @@ hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *ou
                             float2 *glut, const StageRec &rec);
 
 // Arguments of the recursive-path kernels of one image ([0] summary, [1]
-// carries, [2] final vertical, [3] horizontal + combine), and a grouped launch
-// of those stages over n images of one dtype, threads per row and chunk.
+// carries, [2] final vertical, [3] horizontal + combine, and the sum of the
+// pair groups when there are several), and a grouped launch of those stages
+// over n images of one dtype, threads per row and chunk.
 void iir_args(const void *f, float *out, const Geom &g, DevTables tab, DevState st, const float *iir, int k0,
-              int kcount, float4 *cb, float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, IirArgs a[4]);
+              int kcount, float4 *cb, float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, IirArgs a[4],
+              FinishArgs &fa);
 struct IirGroup {
   int n;
   const IirArgs *a[4];
   const int *start[4];
   int total[4];
+  const FinishArgs *fa;
+  const int *fstart;
+  int ftotal;
 };
+// Sum of the pair groups' partial sums and the division (one image, or
+// grouped over n images of one dtype).
+hipError_t launch_finish(hipStream_t s, bf_dtype dt, const FinishArgs *one, const FinishArgs *arr,
+                         const int *start, int n, int total);
 hipError_t launch_iir_group(hipStream_t s, bf_dtype dt, int S, int cC, const IirGroup &ig, const StageRec &rec);
 
 // ---- Toeplitz MFMA path (bf_toeplitz.hip) ----

@@ -19,8 +19,15 @@ constexpr int kCSmall = 16;
 constexpr int kCLarge = 32;
 // Threads per workgroup of the horizontal pass.
 constexpr int kHThreads = 256;
+// Workgroups the horizontal pass aims for (rows x pair groups): two per CU.
+// Short images split their pairs into groups to get there; taller ones keep
+// one group (the partial sums and their reduction cost more than they gain).
+constexpr int kHWorkgroups = 512;
 // Threads per workgroup of the vertical passes.
 constexpr int kVThreads = 256;
+// Threads per workgroup of the carry chain between them (one wave: the chain
+// moves little data per column, so it is spread over as many CUs as possible).
+constexpr int kFThreads = 64;
 // Largest supported width: one row group of kHThreads threads.
 constexpr int kMaxWidth = kCLarge * kHThreads;
 
@@ -61,7 +68,7 @@ bool build_order_table(double sigma_r, double eps, double value_range, int32_t T
 // in the padding are exactly the continuation of the zero-extended signal, so
 // the result is the same as at the true end and no chunk is ever short.
 // Float layout of the constant block (offsets in floats):
-constexpr int kIirCoef = 0;                      // g1, g2, c2, 0
+constexpr int kIirCoef = 0;                      // 1-g1, g2, c2, g1
 constexpr int kIirMts = 4;                       // 3x3: end boundary (zero extension)
 constexpr int kIirApFull = kIirMts + 9;          // 3 x kB: chunk end state per input
 constexpr int kIirAeFull = kIirApFull + 3 * kB;  // 3 x kB: chunk head state per input

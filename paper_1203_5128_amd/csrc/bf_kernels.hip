@@ -12,6 +12,7 @@
 
 namespace bfi {
 
+
 // ------------------------------------------------------------ small helpers
 __device__ __forceinline__ float4 f4(float a) { return make_float4(a, a, a, a); }
 __device__ __forceinline__ float4 add4(float4 a, float4 b) {
@@ -45,30 +46,14 @@ __device__ __forceinline__ void matvec3_acc(const float *__restrict__ M, const f
     v[i] = fma4(M[3 * i + 2], u[2], v[i]);
   }
 }
-// dot of row 1 of a 3x3 M with u (the w-component response)
-__device__ __forceinline__ float4 row1dot(const float *__restrict__ M, const float4 u[3]) {
-  float4 a = f4(0.0f);
-  a = fma4(M[3], u[0], a);
-  a = fma4(M[4], u[1], a);
-  a = fma4(M[5], u[2], a);
-  return a;
-}
-
-__device__ __forceinline__ float4 shfl_up4(float4 v, int d, int w) {
-  return make_float4(__shfl_up(v.x, d, w), __shfl_up(v.y, d, w), __shfl_up(v.z, d, w),
-                     __shfl_up(v.w, d, w));
-}
-__device__ __forceinline__ float4 shfl_down4(float4 v, int d, int w) {
-  return make_float4(__shfl_down(v.x, d, w), __shfl_down(v.y, d, w), __shfl_down(v.z, d, w),
-                     __shfl_down(v.w, d, w));
-}
-
 // One step of the recursive Gaussian cascade on the state (s, w, d):
-// first-order section s += g1 (x - s), then the second-order section carried
-// as w[n] = w[n-1] + d[n], d[n] = g2 (s - w[n-1]) - c2 d[n-1].
-__device__ __forceinline__ void casc_step(float g1, float g2, float c2, float4 x, float4 &s, float4 &w,
+// first-order section s = a1 s + x (a1 = 1 - g1; the input gain g1 is left
+// out, a constant factor per pass common to all smoothed images, which
+// cancels in P / Q), then the second-order section carried as
+// w[n] = w[n-1] + d[n], d[n] = g2 (s - w[n-1]) - c2 d[n-1].
+__device__ __forceinline__ void casc_step(float a1, float g2, float c2, float4 x, float4 &s, float4 &w,
                                           float4 &d) {
-  s = fma4(g1, sub4(x, s), s);
+  s = fma4(a1, s, x);
   float4 nd = fma4(-c2, d, make_float4(g2 * (s.x - w.x), g2 * (s.y - w.y), g2 * (s.z - w.z), g2 * (s.w - w.w)));
   w = add4(w, nd);
   d = nd;
@@ -539,7 +524,7 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_summary_grp(const IirArgs *
 
 __device__ __forceinline__ void iir_v_fixup_impl(const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, float4 *__restrict__ cb, const Blk b) {
 
-  const int p = b.x * kVThreads + threadIdx.x;
+  const int p = b.x * kFThreads + threadIdx.x;
   const int kl = b.y;
   const OrderEntry &e = lookup(tab, st.T_used);
   const int k = k0 + kl;
@@ -604,10 +589,10 @@ __device__ __forceinline__ void iir_v_fixup_body(const IirArgs &a, const Blk b) 
   iir_v_fixup_impl(a.g, a.tab, a.st, a.iir, a.k0, a.cb, b);
 }
 
-__global__ __launch_bounds__(kVThreads) void k_iir_v_fixup(IirArgs a) {
+__global__ __launch_bounds__(kFThreads) void k_iir_v_fixup(IirArgs a) {
   iir_v_fixup_body(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
 }
-__global__ __launch_bounds__(kVThreads) void k_iir_v_fixup_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
+__global__ __launch_bounds__(kFThreads) void k_iir_v_fixup_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
                                                      int n) {
   const int i = group_find(start, n, blockIdx.x);
   iir_v_fixup_body(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
@@ -641,7 +626,7 @@ __device__ __forceinline__ void iir_v_final_impl(const Tin *__restrict__ f, cons
       if (y0 + i < g.H) Zk[(size_t)(y0 + i) * g.Spos + p] = f4(0.f);
     return;
   }
-  const float g1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
+  const float a1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
   const size_t base = ((size_t)kl * g.nc + j) * 6;
   float4 s = cb[(base + 0) * g.Spos + p];
   float4 w = cb[(base + 1) * g.Spos + p];
@@ -655,7 +640,7 @@ __device__ __forceinline__ void iir_v_final_impl(const Tin *__restrict__ f, cons
   for (int i = 0; i < kB; i++) {
     float4 xv = f4(0.f);
     if (i < n) xv = planes_any<Tin>(fv[i], lut, m, q, at, g.center);
-    casc_step(g1, g2, c2, xv, s, w, d);
+    casc_step(a1, g2, c2, xv, s, w, d);
     wv[i] = w;
   }
   s = cb[(base + 3) * g.Spos + p];
@@ -663,7 +648,7 @@ __device__ __forceinline__ void iir_v_final_impl(const Tin *__restrict__ f, cons
   d = cb[(base + 5) * g.Spos + p];
 #pragma unroll
   for (int i = kB - 1; i >= 0; i--) {
-    casc_step(g1, g2, c2, wv[i], s, w, d);
+    casc_step(a1, g2, c2, wv[i], s, w, d);
     const int y = y0 + i;
     if (y < g.H) Zk[(size_t)y * g.Spos + p] = w;
   }
@@ -685,35 +670,100 @@ __global__ __launch_bounds__(kVThreads) void k_iir_v_final_grp(const IirArgs *__
 }
 
 // ------------------------------------ horizontal pass + accumulate (a4, a5)
-// One workgroup per image row; S threads per row group, NG = 256/S groups each
-// taking every NG-th frequency.  Thread t owns kC consecutive columns: a causal
+// One workgroup per (image row, pair group); S threads per row group, NG =
+// 256/S groups each taking every NG-th frequency of the pair group.  Thread t owns kC consecutive columns: a causal
 // sweep from rest, an inclusive scan of the chunk end states across the row
 // group (Hillis-Steele with powers of A^kC, across waves through LDS when the
 // row spans several waves), the correction w += h . carry; the same for the
 // anticausal sweep, seeded at the padded end with the zero-extension boundary.
 // The smoothed images are combined on the fly into the numerator and the
 // denominator (eqs. (f1), (f2)) with the phases regenerated at each pixel.
-template <int SW>
-__device__ __forceinline__ void scan_up(float4 v[3], const float *__restrict__ scanM, int ls) {
+// Lane moves inside a wave through DPP (VALU only, no LDS round trip).  Lanes
+// whose source falls outside the pattern, or whose row the row mask leaves
+// out, read zero.
+template <int CTRL, int ROWMASK = 0xF, bool BOUND0 = true>
+__device__ __forceinline__ float4 dpp4(float4 v) {
+  auto m = [](float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWMASK, 0xF, BOUND0));
+  };
+  return make_float4(m(v.x), m(v.y), m(v.z), m(v.w));
+}
+__device__ __forceinline__ float4 keep4(bool k, float4 v) { return k ? v : f4(0.f); }
+constexpr int kDppRowShl = 0x100, kDppRowShr = 0x110, kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138,
+              kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+// Inclusive scans of the chunk states across the SW lanes of a row group
+// (SW a power of two, groups aligned within the wave): state(t) =
+// sum_i A^{c |t - i|} x_i over i <= t (up) or i >= t (down).  sA holds A^{c m}
+// for m = 0..64.  Inside each 16-lane row a Hillis-Steele scan with DPP row
+// shifts; then the row totals are carried to the following rows with the
+// lane's own power of A^c.
+template <int D, int SW>
+__device__ __forceinline__ void up_step(float4 v[3], const float *__restrict__ M, int ls) {
+  float4 o[3];
 #pragma unroll
-  for (int k = 0; (1 << k) < SW; k++) {
-    const int d = 1 << k;
+  for (int r = 0; r < 3; r++) o[r] = keep4(SW >= 16 || ls >= D, dpp4<kDppRowShr + D>(v[r]));
+  matvec3_acc(M, o, v);
+}
+template <int D, int SW>
+__device__ __forceinline__ void down_step(float4 v[3], const float *__restrict__ M, int ls) {
+  float4 o[3];
+#pragma unroll
+  for (int r = 0; r < 3; r++) o[r] = keep4(SW >= 16 || ls + D < SW, dpp4<kDppRowShl + D>(v[r]));
+  matvec3_acc(M, o, v);
+}
+template <int SW>
+__device__ __forceinline__ void scan_up(float4 v[3], const float *__restrict__ sA, int ls, int lane) {
+  if constexpr (SW > 1) up_step<1, SW>(v, sA + 9 * 1, ls);
+  if constexpr (SW > 2) up_step<2, SW>(v, sA + 9 * 2, ls);
+  if constexpr (SW > 4) up_step<4, SW>(v, sA + 9 * 4, ls);
+  if constexpr (SW > 8) up_step<8, SW>(v, sA + 9 * 8, ls);
+  const int j = lane & 15;
+  if constexpr (SW >= 32) {  // rows 1 and 3 take the totals of rows 0 and 2
     float4 o[3];
 #pragma unroll
-    for (int r = 0; r < 3; r++) o[r] = shfl_up4(v[r], d, SW);
-    if (ls >= d) matvec3_acc(scanM + 9 * k, o, v);
+    for (int r = 0; r < 3; r++) o[r] = dpp4<kDppRowBcast15, 0xA, false>(v[r]);
+    matvec3_acc(sA + 9 * (j + 1), o, v);
+  }
+  if constexpr (SW == 64) {  // rows 2 and 3 take the total of lanes 0..31
+    float4 o[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) o[r] = dpp4<kDppRowBcast31, 0xC, false>(v[r]);
+    matvec3_acc(sA + 9 * max(lane - 31, 0), o, v);
   }
 }
 template <int SW>
-__device__ __forceinline__ void scan_down(float4 v[3], const float *__restrict__ scanM, int ls) {
-#pragma unroll
-  for (int k = 0; (1 << k) < SW; k++) {
-    const int d = 1 << k;
+__device__ __forceinline__ void scan_down(float4 v[3], const float *__restrict__ sA, int ls, int lane) {
+  if constexpr (SW > 1) down_step<1, SW>(v, sA + 9 * 1, ls);
+  if constexpr (SW > 2) down_step<2, SW>(v, sA + 9 * 2, ls);
+  if constexpr (SW > 4) down_step<4, SW>(v, sA + 9 * 4, ls);
+  if constexpr (SW > 8) down_step<8, SW>(v, sA + 9 * 8, ls);
+  const int j = lane & 15;
+  if constexpr (SW >= 32) {  // rows 0 and 2 take the totals of rows 1 and 3 (from their first lane)
+    const int src = (lane & 32) + 16;
+    const bool even = ((lane >> 4) & 1) == 0;
     float4 o[3];
 #pragma unroll
-    for (int r = 0; r < 3; r++) o[r] = shfl_down4(v[r], d, SW);
-    if (ls + d < SW) matvec3_acc(scanM + 9 * k, o, v);
+    for (int r = 0; r < 3; r++)
+      o[r] = keep4(even, make_float4(__shfl(v[r].x, src, 64), __shfl(v[r].y, src, 64), __shfl(v[r].z, src, 64),
+                                     __shfl(v[r].w, src, 64)));
+    matvec3_acc(sA + 9 * (16 - j), o, v);
   }
+  if constexpr (SW == 64) {  // rows 0 and 1 take the total of lanes 32..63
+    const bool lo = lane < 32;
+    float4 o[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+      o[r] = keep4(lo, make_float4(lane_value(v[r].x, 32), lane_value(v[r].y, 32), lane_value(v[r].z, 32),
+                                   lane_value(v[r].w, 32)));
+    matvec3_acc(sA + 9 * max(32 - lane, 0), o, v);
+  }
+}
+// z += row 1 of M times u (the w-component response to the state u)
+__device__ __forceinline__ void row1_acc(const float *__restrict__ M, const float4 u[3], float4 &z) {
+  z = fma4(M[3], u[0], z);
+  z = fma4(M[4], u[1], z);
+  z = fma4(M[5], u[2], z);
 }
 
 template <typename Tin, int S, int kC>
@@ -723,25 +773,42 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   constexpr int SW = S < 64 ? S : 64;
   constexpr int NW = S > 64 ? S / 64 : 1;
   constexpr int PAD = S * (kC + 1);  // LDS row of one group, one slot skipped per kC
+  // 8-bit inputs: the cos/sin tables of the groups' current pairs, copied to
+  // LDS when that still leaves room for two workgroups per CU
+  constexpr bool kLutLds = PhaseLut<Tin>::kOn && NG <= 8 && NG * PAD * 8 + NG * 2048 <= 80 * 1024;
   // (P, Q) per group and pixel; slot (grp, t, i) belongs to one thread until the
   // groups are summed at the end
   __shared__ float2 spq[NG * PAD];
   __shared__ float4 xw[NG][NW][3];
+  __shared__ float2 slut[kLutLds ? NG * 256 : 1];
   const int y = b.x;
+  const int pg = b.y;  // pair group: launch-local pairs [kb, kb + hkpg)
   const int tid = threadIdx.x;
   const int t = tid % S;
   const int grp = tid / S;
   const int ls = t % SW;
   const int wig = t / 64;
   const OrderEntry &e = lookup(tab, st.T_used);
-  const int kend = min(k0 + kcount, e.K);
-  const int niter = kend > k0 ? (kend - k0 + NG - 1) / NG : 0;
-  const float g1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
+  const int kb = pg * g.hkpg;
+  const int kend = min(min(kb + g.hkpg, kcount), e.K - k0);
+  const int niter = kend > kb ? (kend - kb + NG - 1) / NG : 0;
+  const bool finish = last && g.hgroups == 1;
+  if (niter == 0 && !first && !finish) return;  // no pairs here: partial sums unchanged
+  const float a1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
   const float *hb = iir + (kC == kCSmall ? kIirHSmall : kIirHLarge);
   const float *Apow = hb + iir_h_apow(kC);
-  const float *scanM = hb + iir_h_scan(kC);
-  const float *laneM = hb + iir_h_lane(kC);
-  const float *waveM = hb + iir_h_wave(kC);
+  // A^{c m} for m = 0..64 and the end boundary, in LDS: the scans read them
+  // in divergent code, where constants from memory would cost a round trip
+  __shared__ float sA[65 * 9];
+  __shared__ float sMts[9];
+  for (int i = tid; i < 64 * 9; i += kHThreads) sA[i] = hb[iir_h_lane(kC) + i];
+  if (tid < 9) {
+    sA[64 * 9 + tid] = hb[iir_h_wave(kC) + tid];
+    sMts[tid] = iir[kIirMts + tid];
+  }
+  __syncthreads();
+  const float *waveM = sA + 9 * 64;
+  const int lane = tid & 63;
   const Tin *frow = f + (int64_t)y * g.pitch;
   const int x0 = t * kC;
   float2 *mypq = spq + grp * PAD + t * (kC + 1);
@@ -752,8 +819,14 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   for (int i = 0; i < kC; i++) fv[i] = frow[min(x0 + i, g.W - 1)];
 
   for (int it = 0; it < niter; it++) {
-    const int kl = it * NG + grp;
-    const bool act = k0 + kl < kend;
+    const int kl = kb + it * NG + grp;
+    const bool act = kl < kend;
+    if constexpr (kLutLds) {
+      __syncthreads();  // the previous pairs' tables are no longer read
+      if (act)
+        for (int i = t; i < 256; i += S) slut[grp * 256 + i] = glut[(size_t)kl * 256 + i];
+      __syncthreads();
+    }
     const float4 *Zr = Z + ((size_t)(act ? kl : 0) * g.H + y) * g.Spos;
     float4 zv[kC];
 #pragma unroll
@@ -762,17 +835,14 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
     float4 s = f4(0.f), w = f4(0.f), d = f4(0.f);
 #pragma unroll
     for (int i = 0; i < kC; i++) {
-      casc_step(g1, g2, c2, zv[i], s, w, d);
+      casc_step(a1, g2, c2, zv[i], s, w, d);
       zv[i] = w;
     }
     float4 inc[3] = {s, w, d};
-    scan_up<SW>(inc, scanM, ls);
+    scan_up<SW>(inc, sA, ls, lane);
     float4 exc[3];
 #pragma unroll
-    for (int r = 0; r < 3; r++) {
-      exc[r] = shfl_up4(inc[r], 1, SW);
-      if (ls == 0) exc[r] = f4(0.f);
-    }
+    for (int r = 0; r < 3; r++) exc[r] = keep4(ls != 0, dpp4<kDppWaveShr1>(inc[r]));
     if constexpr (NW > 1) {
       if (ls == 63) {
 #pragma unroll
@@ -787,33 +857,30 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
         for (int r = 0; r < 3; r++) Kc[r] = add4(xw[grp][w][r], tk[r]);
       }
       __syncthreads();
-      matvec3_acc(laneM + 9 * ls, Kc, exc);
+      matvec3_acc(sA + 9 * ls, Kc, exc);
       if (t == S - 1) matvec3_acc(waveM, Kc, inc);
     }
     // true causal outputs
 #pragma unroll
-    for (int i = 0; i < kC; i++) zv[i] = add4(zv[i], row1dot(Apow + 9 * (i + 1), exc));
+    for (int i = 0; i < kC; i++) row1_acc(Apow + 9 * (i + 1), exc, zv[i]);
     // zero extension beyond the padded row end
     float4 Eb[3] = {f4(0.f), f4(0.f), f4(0.f)};
-    if (t == S - 1) matvec3(iir + kIirMts, inc, Eb);
+    if (t == S - 1) matvec3(sMts, inc, Eb);
     // anticausal sweep from rest
     s = f4(0.f);
     w = f4(0.f);
     d = f4(0.f);
 #pragma unroll
     for (int i = kC - 1; i >= 0; i--) {
-      casc_step(g1, g2, c2, zv[i], s, w, d);
+      casc_step(a1, g2, c2, zv[i], s, w, d);
       zv[i] = w;
     }
     float4 hd[3] = {s, w, d};
-    if (t == S - 1) matvec3_acc(Apow + 9 * kC, Eb, hd);
-    scan_down<SW>(hd, scanM, ls);
+    if (t == S - 1) matvec3_acc(sA + 9, Eb, hd);  // A^c
+    scan_down<SW>(hd, sA, ls, lane);
     float4 ein[3];
 #pragma unroll
-    for (int r = 0; r < 3; r++) {
-      ein[r] = shfl_down4(hd[r], 1, SW);
-      if (ls == SW - 1) ein[r] = f4(0.f);
-    }
+    for (int r = 0; r < 3; r++) ein[r] = keep4(ls != SW - 1, dpp4<kDppWaveShl1>(hd[r]));
     if constexpr (NW > 1) {
       if (ls == 0) {
 #pragma unroll
@@ -828,14 +895,14 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
         for (int r = 0; r < 3; r++) Kc[r] = add4(xw[grp][w][r], tk[r]);
       }
       __syncthreads();
-      matvec3_acc(laneM + 9 * (63 - ls), Kc, ein);
+      matvec3_acc(sA + 9 * (63 - ls), Kc, ein);
     }
     if (t == S - 1) {
 #pragma unroll
       for (int r = 0; r < 3; r++) ein[r] = Eb[r];
     }
 #pragma unroll
-    for (int i = 0; i < kC; i++) zv[i] = add4(zv[i], row1dot(Apow + 9 * (kC - i), ein));
+    for (int i = 0; i < kC; i++) row1_acc(Apow + 9 * (kC - i), ein, zv[i]);
     // eqs. (f1), (f2): weight by the phase at the output pixel
     if (act) {
       const int k = k0 + kl;
@@ -850,7 +917,7 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
         if (x < g.W) {
           float c, sn;
           if constexpr (PhaseLut<Tin>::kOn) {
-            const float2 cs = lk[(int)fv[i]];
+            const float2 cs = kLutLds ? slut[grp * 256 + (int)fv[i]] : lk[(int)fv[i]];
             c = cs.x;
             sn = cs.y;
           } else {
@@ -866,6 +933,7 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   }
   // sum the groups in a fixed order
   __syncthreads();
+  float2 *PQg = PQ + (size_t)pg * g.H * g.W;
   unsigned long long nbad = 0;
   for (int x = tid; x < g.W; x += kHThreads) {
     const int o = (x / kC) * (kC + 1) + (x % kC);
@@ -878,11 +946,11 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
     }
     const size_t pix = (size_t)y * g.W + x;
     if (!first) {
-      float2 pq = PQ[pix];
+      float2 pq = PQg[pix];
       P += pq.x;
       Q += pq.y;
     }
-    if (last) {
+    if (finish) {
       float r = P / Q;
       float v;
       if (Q > 0.f && isfinite(r)) {
@@ -893,10 +961,10 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
       }
       out[(int64_t)y * g.opitch + x] = v;
     } else {
-      PQ[pix] = make_float2(P, Q);
+      PQg[pix] = make_float2(P, Q);
     }
   }
-  if (last) {
+  if (finish) {
     for (int off = 32; off > 0; off >>= 1) nbad += __shfl_xor(nbad, off, 64);
     if ((tid & 63) == 0 && nbad) atomicAdd(st.q_nonpos, nbad);
   }
@@ -908,13 +976,59 @@ __device__ __forceinline__ void iir_h_accum_body(const IirArgs &a, const Blk b) 
 
 template <typename Tin, int S, int kC>
 __global__ __launch_bounds__(kHThreads, kC == kCSmall ? 2 : 1) void k_iir_h_accum(IirArgs a) {
-  iir_h_accum_body<Tin, S, kC>(a, Blk{(int)blockIdx.x, 0, 0});
+  iir_h_accum_body<Tin, S, kC>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
 }
 template <typename Tin, int S, int kC>
 __global__ __launch_bounds__(kHThreads, kC == kCSmall ? 2 : 1) void k_iir_h_accum_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
                                                      int n) {
   const int i = group_find(start, n, blockIdx.x);
   iir_h_accum_body<Tin, S, kC>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+}
+
+// ------------------------------------------------ sum of the pair groups (a5)
+// The groups' partial numerators and denominators summed in a fixed order,
+// then eqs. (f1), (f2) divided out: one thread per pixel.
+template <typename Tin>
+__device__ __forceinline__ void finish_impl(const Tin *__restrict__ f, float *__restrict__ out, const Geom &g,
+                                            const DevState &st, const float2 *__restrict__ PQ, int groups,
+                                            float rscale, const Blk b) {
+  const int64_t npx = (int64_t)g.H * g.W;
+  const int64_t pix = (int64_t)b.x * 256 + threadIdx.x;
+  unsigned long long nbad = 0;
+  if (pix < npx) {
+    float Pv = 0.f, Qv = 0.f;
+    for (int gi = 0; gi < groups; gi++) {
+      const float2 pq = PQ[gi * npx + pix];
+      Pv += pq.x;
+      Qv += pq.y;
+    }
+    const int y = (int)(pix / g.W), x = (int)(pix % g.W);
+    const float r = Pv / Qv;
+    float v;
+    if (Qv > 0.f && isfinite(r)) {
+      v = fmaf(rscale, r, g.center);
+    } else {
+      v = fval(f[(int64_t)y * g.pitch + x]);
+      nbad = 1;
+    }
+    out[(int64_t)y * g.opitch + x] = v;
+  }
+  for (int off = 32; off > 0; off >>= 1) nbad += __shfl_xor(nbad, off, 64);
+  if ((threadIdx.x & 63) == 0 && nbad) atomicAdd(st.q_nonpos, nbad);
+}
+template <typename Tin>
+__device__ __forceinline__ void finish_body(const FinishArgs &a, const Blk b) {
+  finish_impl<Tin>((const Tin *)a.f, a.out, a.g, a.st, a.PQ, a.groups, a.rscale, b);
+}
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_finish(FinishArgs a) {
+  finish_body<Tin>(a, Blk{(int)blockIdx.x, 0, 0});
+}
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_finish_grp(const FinishArgs *__restrict__ a, const int *__restrict__ start,
+                                                    int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  finish_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
 }
 
 // ------------------------------------------------------------- launchers
@@ -1006,14 +1120,38 @@ hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g
 // Per-image arguments of the four recursive-path kernels for pairs
 // [k0, k0+kcount) (also the per-image entries of grouped launches).
 void iir_args(const void *f, float *out, const Geom &g, DevTables tab, DevState st, const float *iir, int k0,
-              int kcount, float4 *cb, float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, IirArgs a[4]) {
+              int kcount, float4 *cb, float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, IirArgs a[4],
+              FinishArgs &fa) {
   const int nbx = (g.Spos + kVThreads - 1) / kVThreads;
+  const int nfx = (g.Spos + kFThreads - 1) / kFThreads;
   const IirArgs base{GroupGrid{1, 1, 1}, f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, (int)first, (int)last, glut};
   for (int i = 0; i < 4; i++) a[i] = base;
-  a[0].gg = GroupGrid{nbx, g.nc, kcount};  // summary
-  a[1].gg = GroupGrid{nbx, kcount, 1};     // carries
-  a[2].gg = GroupGrid{nbx, g.nc, kcount};  // final
-  a[3].gg = GroupGrid{g.H, 1, 1};          // horizontal + combine
+  a[0].gg = GroupGrid{nbx, g.nc, kcount};      // summary
+  a[1].gg = GroupGrid{nfx, kcount, 1};         // carries
+  a[2].gg = GroupGrid{nbx, g.nc, kcount};      // final
+  a[3].gg = GroupGrid{g.H, g.hgroups, 1};      // horizontal + combine
+  const int64_t npx = (int64_t)g.H * g.W;
+  const int nfin = (last && g.hgroups > 1) ? (int)((npx + 255) / 256) : 0;
+  fa = FinishArgs{GroupGrid{nfin > 0 ? nfin : 1, 1, 1}, f, out, g, st, (const float2 *)PQ, g.hgroups, 1.0f};
+}
+
+hipError_t launch_finish(hipStream_t s, bf_dtype dt, const FinishArgs *one, const FinishArgs *arr,
+                         const int *start, int n, int total) {
+  switch (dt) {
+    case BF_U8:
+      if (one) hipLaunchKernelGGL(k_finish<uint8_t>, dim3(one->gg.gx), dim3(256), 0, s, *one);
+      else if (total > 0) hipLaunchKernelGGL(k_finish_grp<uint8_t>, dim3(total), dim3(256), 0, s, arr, start, n);
+      break;
+    case BF_U16:
+      if (one) hipLaunchKernelGGL(k_finish<uint16_t>, dim3(one->gg.gx), dim3(256), 0, s, *one);
+      else if (total > 0) hipLaunchKernelGGL(k_finish_grp<uint16_t>, dim3(total), dim3(256), 0, s, arr, start, n);
+      break;
+    default:
+      if (one) hipLaunchKernelGGL(k_finish<float>, dim3(one->gg.gx), dim3(256), 0, s, *one);
+      else if (total > 0) hipLaunchKernelGGL(k_finish_grp<float>, dim3(total), dim3(256), 0, s, arr, start, n);
+      break;
+  }
+  return hipGetLastError();
 }
 
 // Launch of the horizontal kernel for threads-per-row S and chunk C, single
@@ -1021,7 +1159,7 @@ void iir_args(const void *f, float *out, const Geom &g, DevTables tab, DevState 
 template <typename Tin, int S, int C>
 static void launch_h(hipStream_t s, const IirArgs *one, const IirArgs *arr, const int *start, int n, int total) {
   if (one)
-    hipLaunchKernelGGL((k_iir_h_accum<Tin, S, C>), dim3(one->gg.gx), dim3(kHThreads), 0, s, *one);
+    hipLaunchKernelGGL((k_iir_h_accum<Tin, S, C>), dim3(one->gg.gx, one->gg.gy), dim3(kHThreads), 0, s, *one);
   else if (total > 0)
     hipLaunchKernelGGL((k_iir_h_accum_grp<Tin, S, C>), dim3(total), dim3(kHThreads), 0, s, arr, start, n);
 }
@@ -1052,14 +1190,17 @@ template <typename Tin>
 static hipError_t iir_chunk_t(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab,
                               DevState st, const float *iir, int k0, int kcount, float4 *cb, float4 *Z,
                               float2 *PQ, bool first, bool last, float2 *glut, const StageRec &rec) {
+  if (g.hgroups < 1 || g.hgroups > 65535 || g.hkpg < 1 || (int64_t)g.hgroups * g.hkpg < kcount)
+    return hipErrorInvalidValue;
   IirArgs a[4];
-  iir_args(f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, first, last, glut, a);
+  FinishArgs fa;
+  iir_args(f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, first, last, glut, a, fa);
   if (kcount > 0) {
     rec.begin(BF_STAGE_V_SUMMARY, s);
     hipLaunchKernelGGL(k_iir_v_summary<Tin>, dim3(a[0].gg.gx, a[0].gg.gy, a[0].gg.gz), dim3(kVThreads), 0, s, a[0]);
     rec.end(BF_STAGE_V_SUMMARY, s);
     rec.begin(BF_STAGE_V_CARRY, s);
-    hipLaunchKernelGGL(k_iir_v_fixup, dim3(a[1].gg.gx, a[1].gg.gy), dim3(kVThreads), 0, s, a[1]);
+    hipLaunchKernelGGL(k_iir_v_fixup, dim3(a[1].gg.gx, a[1].gg.gy), dim3(kFThreads), 0, s, a[1]);
     rec.end(BF_STAGE_V_CARRY, s);
     rec.begin(BF_STAGE_V_FINAL, s);
     hipLaunchKernelGGL(k_iir_v_final<Tin>, dim3(a[2].gg.gx, a[2].gg.gy, a[2].gg.gz), dim3(kVThreads), 0, s, a[2]);
@@ -1068,6 +1209,7 @@ static hipError_t iir_chunk_t(hipStream_t s, const Tin *f, float *out, const Geo
   rec.begin(BF_STAGE_H_COMBINE, s);
   const bool ok = launch_h_any<Tin>(s, g.S, g.cC, &a[3], nullptr, nullptr, 0, 0);
   if (!ok) return hipErrorInvalidValue;
+  if (last && g.hgroups > 1) (void)launch_finish(s, dtype_of<Tin>(), &fa, nullptr, nullptr, 0, 0);
   rec.end(BF_STAGE_H_COMBINE, s);
   return hipGetLastError();
 }
@@ -1082,7 +1224,7 @@ static hipError_t iir_group_t(hipStream_t s, int S, int cC, const IirGroup &ig, 
   rec.end(BF_STAGE_V_SUMMARY, s);
   rec.begin(BF_STAGE_V_CARRY, s);
   if (ig.total[1] > 0)
-    hipLaunchKernelGGL(k_iir_v_fixup_grp, dim3(ig.total[1]), dim3(kVThreads), 0, s, ig.a[1], ig.start[1], ig.n);
+    hipLaunchKernelGGL(k_iir_v_fixup_grp, dim3(ig.total[1]), dim3(kFThreads), 0, s, ig.a[1], ig.start[1], ig.n);
   rec.end(BF_STAGE_V_CARRY, s);
   rec.begin(BF_STAGE_V_FINAL, s);
   if (ig.total[2] > 0)
@@ -1090,6 +1232,7 @@ static hipError_t iir_group_t(hipStream_t s, int S, int cC, const IirGroup &ig, 
   rec.end(BF_STAGE_V_FINAL, s);
   rec.begin(BF_STAGE_H_COMBINE, s);
   const bool ok = launch_h_any<Tin>(s, S, cC, nullptr, ig.a[3], ig.start[3], ig.n, ig.total[3]);
+  if (ig.ftotal > 0) (void)launch_finish(s, dtype_of<Tin>(), nullptr, ig.fa, ig.fstart, ig.n, ig.ftotal);
   rec.end(BF_STAGE_H_COMBINE, s);
   if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();

@@ -154,9 +154,12 @@ M3 mpow(const M3 &x, long e) {
 }
 struct Casc {
   double g1, g2, c2;
-  // one step of the cascade on state (s, w, d) with input x, d = w[n] - w[n-1]
+  // one step of the cascade on state (s, w, d) with input x, d = w[n] - w[n-1].
+  // The first-order section runs without its input gain g1 (s = (1-g1) s + x):
+  // each pass then scales its output by 1/g1, a constant shared by every
+  // smoothed image that cancels in the ratio of eqs. (f1), (f2).
   void step(double st[3], double x) const {
-    double s = st[0] + g1 * (x - st[0]);
+    double s = (1.0 - g1) * st[0] + x;
     double d = g2 * (s - st[1]) - c2 * st[2];
     st[1] = st[1] + d;
     st[2] = d;
@@ -198,9 +201,10 @@ bool build_iir_consts(double sigma_s, std::vector<float> &out, std::string &err)
   if (!yvv_cascade(sigma_s, g1, g2, c1, c2, err)) return false;
   Casc cs{g1, g2, c2};
   out.assign(kIirSize, 0.0f);
-  out[kIirCoef + 0] = (float)g1;
+  out[kIirCoef + 0] = (float)(1.0 - g1);
   out[kIirCoef + 1] = (float)g2;
   out[kIirCoef + 2] = (float)c2;
+  out[kIirCoef + 3] = (float)g1;  // the gain left out (not read by the kernels)
   // zero-input step of Casc as a matrix on (s, w, d)
   M3 A{};
   A.a[0] = 1.0 - g1;

@@ -502,52 +502,6 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_toep_h_grp(const ToepHAr
   toep_h_body<Tin, BF, SPLIT>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
 }
 
-// Sum of the groups' partial numerators and denominators, then eqs. (f1),
-// (f2) divided out: one thread per pixel.
-template <typename Tin>
-__device__ __forceinline__ void toep_finish_body(const FinishArgs &a, const Blk b) {
-  const Tin *__restrict__ f = (const Tin *)a.f;
-  float *__restrict__ out = a.out;
-  const Geom g = a.g;
-  const DevState st = a.st;
-  const float2 *__restrict__ PQ = a.PQ;
-  const int groups = a.groups;
-
-  const int64_t npx = (int64_t)g.H * g.W;
-  const int64_t pix = (int64_t)b.x * 256 + threadIdx.x;
-  unsigned long long nbad = 0;
-  if (pix < npx) {
-    float Pv = 0.f, Qv = 0.f;
-    for (int gi = 0; gi < groups; gi++) {
-      const float2 pq = PQ[gi * npx + pix];
-      Pv += pq.x;
-      Qv += pq.y;
-    }
-    const int y = (int)(pix / g.W), x = (int)(pix % g.W);
-    const float r = Pv / Qv;
-    float v;
-    if (Qv > 0.f && isfinite(r)) {
-      v = fmaf(g.center, r, g.center);
-    } else {
-      v = fval(f[(int64_t)y * g.pitch + x]);
-      nbad = 1;
-    }
-    out[(int64_t)y * g.opitch + x] = v;
-  }
-  for (int off = 32; off > 0; off >>= 1) nbad += __shfl_xor(nbad, off, 64);
-  if ((threadIdx.x & 63) == 0 && nbad) atomicAdd(st.q_nonpos, nbad);
-}
-template <typename Tin>
-__global__ __launch_bounds__(256) void k_toep_finish(FinishArgs a) {
-  toep_finish_body<Tin>(a, Blk{(int)blockIdx.x, 0, 0});
-}
-template <typename Tin>
-__global__ __launch_bounds__(256) void k_toep_finish_grp(const FinishArgs *__restrict__ a,
-                                                         const int *__restrict__ start, int n) {
-  const int i = group_find(start, n, blockIdx.x);
-  toep_finish_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
-}
-
 // ------------------------------------------------------------- launchers
 static bool split_of(int variant) { return variant == BF_BLUR_TOEPLITZ_F16X2 || variant == BF_BLUR_TOEPLITZ_BF16X2; }
 
@@ -588,7 +542,8 @@ void toeplitz_args(int variant, const void *f, float *out, const Geom &g, DevTab
   }
   const int64_t npx = (int64_t)g.H * g.W;
   const int nfin = (last && tc.groups > 1) ? (int)((npx + 255) / 256) : 0;
-  fa = FinishArgs{GroupGrid{nfin > 0 ? nfin : 1, 1, 1}, f, out, g, st, (const float2 *)PQ, tc.groups};
+  // the difference images were divided by the center value
+  fa = FinishArgs{GroupGrid{nfin > 0 ? nfin : 1, 1, 1}, f, out, g, st, (const float2 *)PQ, tc.groups, g.center};
 }
 
 template <typename Tin, bool BF, bool SPLIT>
@@ -611,7 +566,7 @@ static hipError_t toep_t(hipStream_t s, const Tin *f, float *out, const Geom &g,
   rec.begin(BF_STAGE_H_COMBINE, s);
   hipLaunchKernelGGL((k_toep_h<Tin, BF, SPLIT>), dim3(ha.gg.gx, ha.gg.gy), dim3(256), toeplitz_h_lds(variant, tc.nks),
                      s, ha);
-  if (last && !ha.finish) hipLaunchKernelGGL((k_toep_finish<Tin>), dim3(fa.gg.gx), dim3(256), 0, s, fa);
+  if (last && !ha.finish) (void)launch_finish(s, dtype_of<Tin>(), &fa, nullptr, nullptr, 0, 0);
   rec.end(BF_STAGE_H_COMBINE, s);
   return hipGetLastError();
 }
@@ -630,8 +585,7 @@ static hipError_t toep_group_t(hipStream_t s, const ToepGroup &tg, const StageRe
   if (tg.htotal > 0)
     hipLaunchKernelGGL((k_toep_h_grp<Tin, BF, SPLIT>), dim3(tg.htotal), dim3(256), tg.hlds, s, tg.ha, tg.hstart,
                        tg.n);
-  if (tg.ftotal > 0)
-    hipLaunchKernelGGL((k_toep_finish_grp<Tin>), dim3(tg.ftotal), dim3(256), 0, s, tg.fa, tg.fstart, tg.n);
+  if (tg.ftotal > 0) (void)launch_finish(s, dtype_of<Tin>(), nullptr, tg.fa, tg.fstart, tg.n, tg.ftotal);
   rec.end(BF_STAGE_H_COMBINE, s);
   return hipGetLastError();
 }
