@@ -33,13 +33,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 def algorithmic_bytes(stage: str, H: int, W: int, pairs: int, b_in: int, kcount: int) -> float:
-    """Bytes a stage must move per launch ('Measurement').
+    """Bytes a stage must move per launch.
 
-    v_final writes the four smoothed images of each of its pairs (16 B per
-    pixel and pair, FP32); h_combine reads them back and writes the output.
-    The range stage reads f twice and writes/reads the row maxima once."""
+    v_iir generates the four images of each pair from f and writes them
+    smoothed down the columns (16 B per pixel and pair, FP32); h_combine reads
+    them back and writes the output.  The range stage reads f twice and
+    writes/reads the row maxima once."""
     px = H * W
-    if stage == "v_final":
+    if stage == "v_iir":
         return px * (16.0 * pairs + b_in)
     if stage == "h_combine":
         return px * (16.0 * pairs + b_in + 4.0)

@@ -106,7 +106,8 @@ typedef struct bf_plan_s *bf_plan_t;
  * the operator constants are computed and uploaded; the workspace is
  * allocated on the current device.  No image data is read.
  * Errors: BF_ERR_INVALID_ARG (bad params, n_images < 1, NULL pointers),
- * BF_ERR_UNSUPPORTED (order or width beyond the build limits),
+ * BF_ERR_UNSUPPORTED (order beyond the build limits; width or height above
+ * 8192 for the recursive blur; radius above 120 for the Toeplitz blur),
  * BF_ERR_OUT_OF_MEMORY, BF_ERR_DEVICE.  On error *out is set to NULL. */
 bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out);
 
@@ -128,19 +129,18 @@ bf_status bf_filter_batch(bf_plan_t plan, int32_t n, const void *const *d_in, fl
 bf_status bf_dynamic_range(bf_plan_t plan, const void *d_in, void *hip_stream, double *T_out);
 
 /* Stage timing.  While enabled, every filter call of the plan records HIP
- * events on its stream between the stages it launches (range, vertical
- * summaries, carry chain, vertical sweeps, horizontal pass + combine).
- * bf_profile_read synchronises the plan's last stream, returns the summed
- * device milliseconds and launch counts per stage since the last read, and
- * clears them.  Stage indices are the BF_STAGE_* values. */
+ * events on its stream between the stages it launches (range; vertical pass
+ * of the recursive blur; vertical pass of the Toeplitz blur; horizontal pass +
+ * combine of either, with the sum of the pair groups).  bf_profile_read
+ * synchronises the plan's last stream, returns the summed device milliseconds
+ * and launch counts per stage since the last read, and clears them.  Stage
+ * indices are the BF_STAGE_* values. */
 enum {
   BF_STAGE_RANGE = 0,
-  BF_STAGE_V_SUMMARY = 1,
-  BF_STAGE_V_CARRY = 2,
-  BF_STAGE_V_FINAL = 3,
-  BF_STAGE_H_COMBINE = 4,
-  BF_STAGE_TOEPLITZ = 5,
-  BF_STAGE_COUNT = 6
+  BF_STAGE_V_IIR = 1,
+  BF_STAGE_V_TOEPLITZ = 2,
+  BF_STAGE_H_COMBINE = 3,
+  BF_STAGE_COUNT = 4
 };
 bf_status bf_profile(bf_plan_t plan, int32_t enable);
 bf_status bf_profile_read(bf_plan_t plan, double *ms /* [BF_STAGE_COUNT] */,

@@ -38,7 +38,7 @@ BLUR_NAMES = {v: k for k, v in BLURS.items()}
 
 EXPORTS = ["bf_plan", "bf_filter", "bf_filter_batch", "bf_dynamic_range", "bf_profile", "bf_profile_read",
            "bf_plan_destroy", "bf_status_string", "bf_last_error_detail"]
-STAGES = ["range", "v_summary", "v_carry", "v_final", "h_combine", "toeplitz"]
+STAGES = ["range", "v_iir", "v_toeplitz", "h_combine"]
 
 
 class bf_params(ctypes.Structure):

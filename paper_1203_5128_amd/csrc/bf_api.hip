@@ -95,11 +95,10 @@ struct bf_plan_s {
   std::vector<ImagePlan> im;
   // workspace shared by the images of the plan (they run one after another)
   void *d_rowmax = nullptr;
-  float4 *d_cb = nullptr;
   float4 *d_Z = nullptr;
   float2 *d_PQ = nullptr;
   float2 *d_lut = nullptr;  // cos/sin tables of the pairs in flight (8-bit inputs)
-  size_t rowmax_bytes = 0, cb_bytes = 0, Z_bytes = 0, PQ_bytes = 0, lut_bytes = 0;
+  size_t rowmax_bytes = 0, Z_bytes = 0, PQ_bytes = 0, lut_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // stage timing (bf_profile)
   bool prof = false;
@@ -120,7 +119,7 @@ struct bf_plan_s {
   bool grouped = false;
   void *d_bws = nullptr;
   size_t bws_bytes = 0;
-  std::vector<size_t> rowmax_off, z_off, pq_off, cb_off, glut_off;
+  std::vector<size_t> rowmax_off, z_off, pq_off, glut_off;
   struct BatchEntry {
     std::vector<const void *> in;
     std::vector<float *> out;
@@ -208,8 +207,8 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   ip.T_global_raw = Tg;
   int variant = kn.variant ? kn.variant : (p.blur == BF_BLUR_AUTO ? BF_BLUR_IIR_F32 : p.blur);
   ip.variant = variant;
-  if (!is_toeplitz(variant) && p.width > kMaxWidth)
-    return fail(BF_ERR_UNSUPPORTED, "width above 8192 for the recursive blur");
+  if (!is_toeplitz(variant) && (p.width > kMaxWidth || p.height > kMaxWidth))
+    return fail(BF_ERR_UNSUPPORTED, "width or height above 8192 for the recursive blur");
   if (is_toeplitz(variant) && !toeplitz_shape(variant, ip.R, p.height, kn.lds_kb, ip.tc))
     return fail(BF_ERR_UNSUPPORTED, "radius above 120 for the Toeplitz blur");
   std::string err;
@@ -240,7 +239,16 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   g.logS = logS;
   g.cC = cC;
   g.Spos = S * cC;
-  g.nc = (g.H + kB - 1) / kB;
+  // vertical pass: one row group per column, kCSmall rows per thread (the long
+  // chunk only for columns taller than a workgroup of short ones)
+  g.vC = g.H > kCSmall * kHThreads ? kCLarge : kCSmall;
+  g.vS = 1;
+  while (g.vS * g.vC < g.H) g.vS <<= 1;
+  // a vertical workgroup covers 256 / vS columns: below 8 (one 128-byte line
+  // of a row) the smoothed images are stored in tiles of 8 vS / 256 rows
+  g.zlog = 0;
+  while ((kHThreads / g.vS) << g.zlog < 8) g.zlog++;
+  g.Hz = (g.H + (1 << g.zlog) - 1) >> g.zlog << g.zlog;
   g.center = (float)(0.5 * ip.range);
   if (!(g.center > 0.f)) return fail(BF_ERR_INVALID_ARG, "value_range too small");
   g.padl = ip.R & 7;
@@ -257,7 +265,7 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   hipError_t e = hipMalloc(&ip.d_state, 64);
   if (e != hipSuccess) return dev_fail(e, "hipMalloc(state)");
   // pairs per launch: bounded by a workspace budget for the smoothed images
-  size_t per_pair = (size_t)g.H * g.Spos * sizeof(float4);
+  size_t per_pair = (size_t)g.Hz * g.Spos * sizeof(float4);
   if (is_toeplitz(variant)) per_pair = (size_t)4 * g.H * g.zpitch * (is_split(variant) ? 4 : 2);
   ip.z_per_pair = per_pair;
   size_t budget = (size_t)64 << 30;
@@ -408,7 +416,7 @@ bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out
   }
   for (int k0 = 0; k0 < Kmax; k0 += ip.KC) {
     const int kcount = std::min(ip.KC, Kmax - k0);
-    e = launch_iir_chunk(s, ip.p.dtype, d_in, d_out, g, tab, st, ip.d_iir, k0, kcount, pl->d_cb, pl->d_Z,
+    e = launch_iir_chunk(s, ip.p.dtype, d_in, d_out, g, tab, st, ip.d_iir, k0, kcount, pl->d_Z,
                          pl->d_PQ, k0 == 0, k0 + ip.KC >= Kmax, pl->d_lut, pl->rec);
     if (e != hipSuccess) return dev_fail(e, "blur");
   }
@@ -441,7 +449,7 @@ std::vector<int> starts_of(const std::vector<int> &blocks) {
 // The grouped launches of a batch: offsets of their argument arrays in the
 // packed buffer, block totals and LDS sizes.
 struct GLaunch {
-  int kind;  // 0 reset, 1 range, 2 Toeplitz stages, 3 recursive stages
+  int kind;  // 0 reset, 1 range, 2 Toeplitz stages, 3 recursive vertical, 4 recursive horizontal
   bf_dtype dt;
   int variant;
   bool seq;
@@ -556,47 +564,46 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
       L.lds[1] = hl;
       bp.launches.push_back(L);
     }
-  for (bf_dtype dt : {BF_U8, BF_U16, BF_F32})
-    for (int cC : {kCSmall, kCLarge})
-      for (int S = 1; S <= kHThreads; S <<= 1) {
-        std::vector<IirArgs> ar[4];
-        std::vector<FinishArgs> fa;
-        std::vector<int> nb[5];
-        for (int i : gidx) {
-          const ImagePlan &ip = pl->im[i];
-          if (is_toeplitz(ip.variant) || ip.p.dtype != dt || ip.g.cC != cC || ip.g.S != S) continue;
-          char *ws = (char *)pl->d_bws;
-          IirArgs a[4];
-          FinishArgs c;
-          iir_args(d_in[i], d_out[i], ip.g, tables_of(ip), state_of(ip), ip.d_iir, 0, ip.tab.K_max,
-                   (float4 *)(ws + pl->cb_off[i]), (float4 *)(ws + pl->z_off[i]), (float2 *)(ws + pl->pq_off[i]),
-                   true, true, (float2 *)(ws + pl->glut_off[i]), a, c);
-          for (int q = 0; q < 4; q++) {
-            ar[q].push_back(a[q]);
-            nb[q].push_back(a[q].gg.gx * a[q].gg.gy * a[q].gg.gz);
+  // recursive images: every vertical pass (grouped by dtype, threads per column
+  // and chunk), then every horizontal pass (by dtype, threads per row, chunk)
+  for (int pass = 0; pass < 2; pass++)
+    for (bf_dtype dt : {BF_U8, BF_U16, BF_F32})
+      for (int cC : {kCSmall, kCLarge})
+        for (int S = 1; S <= kHThreads; S <<= 1) {
+          std::vector<IirArgs> ar;
+          std::vector<FinishArgs> fa;
+          std::vector<int> nb, fb;
+          for (int i : gidx) {
+            const ImagePlan &ip = pl->im[i];
+            if (is_toeplitz(ip.variant) || ip.p.dtype != dt) continue;
+            if (pass == 0 ? (ip.g.vC != cC || ip.g.vS != S) : (ip.g.cC != cC || ip.g.S != S)) continue;
+            char *ws = (char *)pl->d_bws;
+            IirArgs a[2];
+            FinishArgs c;
+            iir_args(d_in[i], d_out[i], ip.g, tables_of(ip), state_of(ip), ip.d_iir, 0, ip.tab.K_max,
+                     (float4 *)(ws + pl->z_off[i]), (float2 *)(ws + pl->pq_off[i]), true, true,
+                     (float2 *)(ws + pl->glut_off[i]), a, c);
+            ar.push_back(a[pass]);
+            nb.push_back(a[pass].gg.gx * a[pass].gg.gy * a[pass].gg.gz);
+            fa.push_back(c);
+            fb.push_back(pass == 1 && ip.g.hgroups > 1 ? c.gg.gx : 0);
           }
-          fa.push_back(c);
-          nb[4].push_back(ip.g.hgroups > 1 ? c.gg.gx : 0);
+          if (ar.empty()) continue;
+          GLaunch L{};
+          L.kind = 3 + pass;
+          L.dt = dt;
+          L.S = S;
+          L.cC = cC;
+          L.cnt = (int)ar.size();
+          const std::vector<int> st = starts_of(nb), fs = starts_of(fb);
+          L.o[0] = bp.pack.add(ar);
+          L.o[1] = bp.pack.add(st);
+          L.t[0] = st.back();
+          L.o[2] = bp.pack.add(fa);
+          L.o[3] = bp.pack.add(fs);
+          L.t[1] = fs.back();
+          bp.launches.push_back(L);
         }
-        if (ar[0].empty()) continue;
-        GLaunch L{};
-        L.kind = 3;
-        L.dt = dt;
-        L.S = S;
-        L.cC = cC;
-        L.cnt = (int)ar[0].size();
-        for (int q = 0; q < 4; q++) {
-          const std::vector<int> st = starts_of(nb[q]);
-          L.o[2 * q] = bp.pack.add(ar[q]);
-          L.o[2 * q + 1] = bp.pack.add(st);
-          L.t[q] = st.back();
-        }
-        const std::vector<int> fs = starts_of(nb[4]);
-        L.o[8] = bp.pack.add(fa);
-        L.o[9] = bp.pack.add(fs);
-        L.t[4] = fs.back();
-        bp.launches.push_back(L);
-      }
 }
 
 // Device side of a batch: the grouped launches (their arguments already in
@@ -615,17 +622,12 @@ bf_status enqueue_batch(bf_plan_s *pl, int n, const void *const *d_in, float *co
                              L.cnt);
       pl->rec.end(BF_STAGE_RANGE, s);
     } else if (L.kind == 3) {
-      IirGroup ig;
-      ig.n = L.cnt;
-      for (int q = 0; q < 4; q++) {
-        ig.a[q] = (const IirArgs *)(d_args + L.o[2 * q]);
-        ig.start[q] = (const int *)(d_args + L.o[2 * q + 1]);
-        ig.total[q] = L.t[q];
-      }
-      ig.fa = (const FinishArgs *)(d_args + L.o[8]);
-      ig.fstart = (const int *)(d_args + L.o[9]);
-      ig.ftotal = L.t[4];
-      e = launch_iir_group(s, L.dt, L.S, L.cC, ig, pl->rec);
+      e = launch_iir_v_group(s, L.dt, L.S, L.cC, (const IirArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]),
+                             L.cnt, L.t[0], pl->rec);
+    } else if (L.kind == 4) {
+      e = launch_iir_h_group(s, L.dt, L.S, L.cC, (const IirArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]),
+                             L.cnt, L.t[0], (const FinishArgs *)(d_args + L.o[2]), (const int *)(d_args + L.o[3]),
+                             L.t[1], pl->rec);
     } else {
       const ToepGroup tg{L.cnt,
                          (const ToepVArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]), L.t[0], L.lds[0],
@@ -762,7 +764,7 @@ static bf_status create_plan(const bf_params *params, int32_t n_images, const Kn
   bf_plan_s *pl = new bf_plan_s();
   (void)hipGetDevice(&pl->device);
   pl->im.resize(n_images);
-  size_t rowmax = 0, cb = 0, Z = 0, PQ = 0, lut = 0;
+  size_t rowmax = 0, Z = 0, PQ = 0, lut = 0;
   for (int i = 0; i < n_images; i++) {
     bf_status s = prepare_image(params[i], pl->im[i], knobs ? knobs[i] : Knobs());
     if (s) {
@@ -773,14 +775,13 @@ static bf_status create_plan(const bf_params *params, int32_t n_images, const Kn
     const Geom &g = ip.g;
     rowmax = std::max(rowmax, (size_t)g.H * g.W * elem_size(ip.p.dtype));
     if (!is_toeplitz(ip.variant)) {
-      cb = std::max(cb, (size_t)ip.KC * g.nc * 6 * g.Spos * sizeof(float4));
       lut = std::max(lut, (size_t)ip.KC * 256 * sizeof(float2));
     }
     Z = std::max(Z, (size_t)ip.KC * ip.z_per_pair);
     PQ = std::max(PQ, (size_t)(is_toeplitz(ip.variant) ? ip.tc.groups : g.hgroups) * g.H * g.W * sizeof(float2));
   }
   bf_status s;
-  if ((s = ensure(&pl->d_rowmax, pl->rowmax_bytes, rowmax)) || (s = ensure((void **)&pl->d_cb, pl->cb_bytes, cb)) ||
+  if ((s = ensure(&pl->d_rowmax, pl->rowmax_bytes, rowmax)) ||
       (s = ensure((void **)&pl->d_Z, pl->Z_bytes, Z)) || (s = ensure((void **)&pl->d_PQ, pl->PQ_bytes, PQ)) ||
       (s = ensure((void **)&pl->d_lut, pl->lut_bytes, lut))) {
     bf_plan_destroy(pl);
@@ -801,12 +802,10 @@ static bf_status create_plan(const bf_params *params, int32_t n_images, const Kn
       const bool t = is_toeplitz(ip.variant);
       const size_t K = (size_t)ip.tab.K_max;
       const size_t zb = K * ip.z_per_pair;
-      const size_t cbb = t ? 0 : K * g.nc * 6 * g.Spos * sizeof(float4);
-      zsum += zb + cbb;
+      zsum += zb;
       pl->rowmax_off.push_back(take((size_t)g.H * g.W * elem_size(ip.p.dtype)));
       pl->z_off.push_back(take(zb));
       pl->pq_off.push_back(take((size_t)(t ? ip.tc.groups : g.hgroups) * g.H * g.W * sizeof(float2)));
-      pl->cb_off.push_back(take(cbb));
       pl->glut_off.push_back(take(t ? 0 : K * 256 * sizeof(float2)));
     }
     size_t budget = (size_t)64 << 30;
@@ -899,7 +898,6 @@ void bf_plan_destroy(bf_plan_t pl) {
     if (e) (void)hipEventDestroy(e);
   for (auto &ip : pl->im) free_image(ip);
   (void)hipFree(pl->d_rowmax);
-  (void)hipFree(pl->d_cb);
   (void)hipFree(pl->d_Z);
   (void)hipFree(pl->d_PQ);
   (void)hipFree(pl->d_lut);

@@ -41,7 +41,13 @@ struct Geom {
   int S, logS;        // threads per row in the horizontal pass (power of two)
   int cC;             // pixels per thread in the horizontal pass (kCSmall or kCLarge)
   int Spos;           // S * cC positions per padded row
-  int nc;             // vertical chunks of kB rows
+  int vS, vC;         // vertical pass: threads per column (power of two), rows per thread
+  // smoothed images of the recursive path, stored in tiles of zth = 2^zlog
+  // rows: element (y, p) at ((y >> zlog) Spos + p) zth + (y mod zth), Hz rows
+  // per pair (H rounded up to zth).  zth = 8 / (columns per vertical
+  // workgroup), at least 1 (row-major): each vertical workgroup then writes
+  // whole 128-byte lines.
+  int Hz, zlog;
   // horizontal pass: the pairs of a launch are split into hgroups groups of
   // hkpg pairs, each a row of workgroups with its own partial sums
   int hgroups, hkpg;
@@ -94,6 +100,11 @@ __device__ __forceinline__ int group_find(const int *__restrict__ start, int n, 
 }
 __device__ __forceinline__ Blk group_blk(const GroupGrid &gg, int local) {
   return Blk{local % gg.gx, (local / gg.gx) % gg.gy, local / (gg.gx * gg.gy)};
+}
+
+// Offset of element (y, p) of one pair's smoothed images (recursive path).
+__host__ __device__ inline size_t z_index(const Geom &g, int y, int p) {
+  return (((size_t)(y >> g.zlog) * g.Spos + p) << g.zlog) + (y & ((1 << g.zlog) - 1));
 }
 
 // Per-image arguments of the kernels that also run as grouped launches.
@@ -157,7 +168,7 @@ struct FinishArgs {  // sum of the groups' partial sums and the division
   float rscale;  // out = center + rscale * P / Q
 };
 
-struct IirArgs {  // the four recursive-path kernels (each with its own grid)
+struct IirArgs {  // the two recursive-path kernels (each with its own grid)
   GroupGrid gg;
   const void *f;
   float *out;
@@ -166,7 +177,6 @@ struct IirArgs {  // the four recursive-path kernels (each with its own grid)
   DevState st;
   const float *iir;
   int k0, kcount;
-  float4 *cb;
   float4 *Z;
   float2 *PQ;
   int first, last;
@@ -198,30 +208,27 @@ hipError_t launch_range_group(hipStream_t s, bf_dtype dt, bool seq, const Rowmax
                               int rtotal, const ColmaxArgs *ca, const int *cstart, int ctotal, int n);
 hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *out, const Geom &g,
                             DevTables tab, DevState st, const float *iir, int k0, int kcount,
-                            float4 *cb, float4 *Z, float2 *PQ, bool first, bool last,
-                            float2 *glut, const StageRec &rec);
+                            float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, const StageRec &rec);
 
-// Arguments of the recursive-path kernels of one image ([0] summary, [1]
-// carries, [2] final vertical, [3] horizontal + combine, and the sum of the
-// pair groups when there are several), and a grouped launch of those stages
-// over n images of one dtype, threads per row and chunk.
+// Arguments of the recursive-path kernels of one image ([0] vertical, [1]
+// horizontal + combine) and of the sum of its pair groups when there are
+// several.
 void iir_args(const void *f, float *out, const Geom &g, DevTables tab, DevState st, const float *iir, int k0,
-              int kcount, float4 *cb, float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, IirArgs a[4],
+              int kcount, float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, IirArgs a[2],
               FinishArgs &fa);
-struct IirGroup {
-  int n;
-  const IirArgs *a[4];
-  const int *start[4];
-  int total[4];
-  const FinishArgs *fa;
-  const int *fstart;
-  int ftotal;
-};
+// Grouped launches over n images of one dtype: the vertical pass of images
+// with SV threads per column and cV rows per thread; the horizontal pass (and
+// the finishing sums) of images with S threads per row and cC columns per
+// thread.
+hipError_t launch_iir_v_group(hipStream_t s, bf_dtype dt, int SV, int cV, const IirArgs *a, const int *start,
+                              int n, int total, const StageRec &rec);
+hipError_t launch_iir_h_group(hipStream_t s, bf_dtype dt, int S, int cC, const IirArgs *a, const int *start,
+                              int n, int total, const FinishArgs *fa, const int *fstart, int ftotal,
+                              const StageRec &rec);
 // Sum of the pair groups' partial sums and the division (one image, or
 // grouped over n images of one dtype).
 hipError_t launch_finish(hipStream_t s, bf_dtype dt, const FinishArgs *one, const FinishArgs *arr,
                          const int *start, int n, int total);
-hipError_t launch_iir_group(hipStream_t s, bf_dtype dt, int S, int cC, const IirGroup &ig, const StageRec &rec);
 
 // ---- Toeplitz MFMA path (bf_toeplitz.hip) ----
 // LDS bytes of the two kernels' dynamic tiles, and the horizontal tile width.

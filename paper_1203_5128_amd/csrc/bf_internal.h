@@ -11,24 +11,19 @@
 namespace bfi {
 
 // ---------------------------------------------------------------- geometry
-// Vertical pass: rows per chunk of the blocked recursive filter.
-constexpr int kB = 32;
-// Horizontal pass: pixels of a row owned by one thread (a per-plan choice
-// between the two values below; each has its own block of scan constants).
+// Blocked recursive Gaussian: samples of a row (or column) owned by one
+// thread (a per-plan choice between the two values below; each has its own
+// block of scan constants).
 constexpr int kCSmall = 16;
 constexpr int kCLarge = 32;
-// Threads per workgroup of the horizontal pass.
+// Threads per workgroup of both recursive passes.
 constexpr int kHThreads = 256;
 // Workgroups the horizontal pass aims for (rows x pair groups): two per CU.
 // Short images split their pairs into groups to get there; taller ones keep
 // one group (the partial sums and their reduction cost more than they gain).
 constexpr int kHWorkgroups = 512;
-// Threads per workgroup of the vertical passes.
-constexpr int kVThreads = 256;
-// Threads per workgroup of the carry chain between them (one wave: the chain
-// moves little data per column, so it is spread over as many CUs as possible).
-constexpr int kFThreads = 64;
-// Largest supported width: one row group of kHThreads threads.
+// Largest supported width and height of the recursive path: one row (column)
+// group of kHThreads threads.
 constexpr int kMaxWidth = kCLarge * kHThreads;
 
 // ------------------------------------------------------- order tables (a1)
@@ -63,24 +58,20 @@ bool build_order_table(double sigma_r, double eps, double value_range, int32_t T
 // d[n] = w[n] - w[n-1].  Carrying the difference instead of w[n-1] keeps the
 // FP32 rounding of the second-order section from being fed back through its
 // poles, which sit close to z = 1 for wide Gaussians.
-// Rows and columns are padded with zeros to a multiple of the chunk length and
-// the zero-extension boundary is applied at the padded end: the causal outputs
-// in the padding are exactly the continuation of the zero-extended signal, so
-// the result is the same as at the true end and no chunk is ever short.
+// Rows and columns are padded with zeros to whole chunks and the
+// zero-extension boundary is applied at the padded end: the causal outputs in
+// the padding are exactly the continuation of the zero-extended signal, so the
+// result is the same as at the true end and no chunk is ever short.
 // Float layout of the constant block (offsets in floats):
 constexpr int kIirCoef = 0;                      // 1-g1, g2, c2, g1
 constexpr int kIirMts = 4;                       // 3x3: end boundary (zero extension)
-constexpr int kIirApFull = kIirMts + 9;          // 3 x kB: chunk end state per input
-constexpr int kIirAeFull = kIirApFull + 3 * kB;  // 3 x kB: chunk head state per input
-constexpr int kIirPhiFull = kIirAeFull + 3 * kB; // 3x3: A^kB
-constexpr int kIirCmFull = kIirPhiFull + 9;      // 3x3: causal carry -> anticausal head
-// Horizontal-pass block for a chunk of c pixels per thread:
+// Block for a chunk of c samples per thread:
 //   A^v, v = 0..c (9 each); A^(c l), l = 0..63; A^(c 2^k), k = 0..7; A^(64 c).
 constexpr int iir_hblock_size(int c) { return 9 * (c + 1) + 9 * 64 + 9 * 8 + 9; }
-constexpr int kIirHSmall = kIirCmFull + 9;
+constexpr int kIirHSmall = kIirMts + 9;
 constexpr int kIirHLarge = kIirHSmall + iir_hblock_size(kCSmall);
 constexpr int kIirSize = kIirHLarge + iir_hblock_size(kCLarge);
-// offsets inside a horizontal block
+// offsets inside a block
 constexpr int iir_h_apow(int) { return 0; }
 constexpr int iir_h_lane(int c) { return 9 * (c + 1); }
 constexpr int iir_h_scan(int c) { return 9 * (c + 1) + 9 * 64; }

@@ -447,237 +447,19 @@ __global__ __launch_bounds__(64) void k_colmax_T_seq_grp(const ColmaxArgs *__res
 }
 
 // --------------------------------------------- blocked recursive Gaussian
-// Vertical pass over the images of one frequency, one lane per column.  The
-// padded column (nc chunks of kB rows) is filtered by the causal and the
-// anticausal cascade; chunk j needs the causal state entering it and the
-// anticausal state entering it from below.  Stage 1 sums, per chunk, the end
-// state and the anticausal head the chunk would produce from rest (both linear
-// in its input); stage 2 chains them down and up the column; stage 3 reruns
-// each chunk from its true states and writes the smoothed images.
+// Both passes filter a padded line (a column in the vertical pass, a row in
+// the horizontal one) with the causal and then the anticausal cascade.  The
+// line is split over a row group of S threads, thread t owning the kC
+// consecutive samples [t kC, t kC + kC): each thread runs its samples from
+// rest, the chunk end states are scanned across the group (powers of A^kC),
+// and each sample takes the correction w += (row 1 of A^i) . carry; the same
+// for the anticausal direction, seeded at the padded end with the
+// zero-extension boundary.
 //
 // Positions p index the padded row in an interleaved order: p -> column
 // x = (p mod S) * c + p / S, so that the horizontal pass, where thread t owns
 // columns [t c, t c + c), reads consecutive addresses.
 
-template <typename Tin>
-__device__ __forceinline__ void iir_v_summary_impl(const Tin *__restrict__ f, const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, float4 *__restrict__ cb, const Blk b) {
-
-  const int p = b.x * kVThreads + threadIdx.x;
-  const int j = b.y;
-  const int kl = b.z;
-  const OrderEntry &e = lookup(tab, st.T_used);
-  const int k = k0 + kl;
-  if (k >= e.K) return;
-  const int32_t m = tab.pm[e.off + k];
-  const uint64_t q = e.qfix;
-  const double at = e.alpha_turn;
-  __shared__ float2 lut[PhaseLut<Tin>::kOn ? 256 : 1];
-  if constexpr (PhaseLut<Tin>::kOn) {
-    build_lut(lut, m, q, at, threadIdx.x, kVThreads);
-    __syncthreads();
-  }
-  if (p >= g.Spos) return;
-  const int x = (p & (g.S - 1)) * g.cC + (p >> g.logS);
-  if (x >= g.W) return;
-  const float *Ap = iir + kIirApFull;
-  const float *Ae = iir + kIirAeFull;
-  float4 a0 = f4(0.f), a1 = f4(0.f), a2 = f4(0.f), b0 = f4(0.f), b1 = f4(0.f), b2 = f4(0.f);
-  const int y0 = j * kB;
-  const int n = min(kB, g.H - y0);
-  Tin fv[kB];
-#pragma unroll
-  for (int i = 0; i < kB; i++) fv[i] = f[(int64_t)(y0 + min(i, n - 1)) * g.pitch + x];
-#pragma unroll
-  for (int i = 0; i < kB; i++) {
-    // rows past the image contribute nothing (zero input)
-    const float4 xv = i < n ? planes_any<Tin>(fv[i], lut, m, q, at, g.center) : f4(0.f);
-    a0 = fma4(Ap[0 * kB + i], xv, a0);
-    a1 = fma4(Ap[1 * kB + i], xv, a1);
-    a2 = fma4(Ap[2 * kB + i], xv, a2);
-    b0 = fma4(Ae[0 * kB + i], xv, b0);
-    b1 = fma4(Ae[1 * kB + i], xv, b1);
-    b2 = fma4(Ae[2 * kB + i], xv, b2);
-  }
-  const size_t base = ((size_t)kl * g.nc + j) * 6;
-  cb[(base + 0) * g.Spos + p] = a0;
-  cb[(base + 1) * g.Spos + p] = a1;
-  cb[(base + 2) * g.Spos + p] = a2;
-  cb[(base + 3) * g.Spos + p] = b0;
-  cb[(base + 4) * g.Spos + p] = b1;
-  cb[(base + 5) * g.Spos + p] = b2;
-}
-template <typename Tin>
-__device__ __forceinline__ void iir_v_summary_body(const IirArgs &a, const Blk b) {
-  iir_v_summary_impl<Tin>((const Tin *)a.f, a.g, a.tab, a.st, a.iir, a.k0, a.cb, b);
-}
-
-template <typename Tin>
-__global__ __launch_bounds__(kVThreads) void k_iir_v_summary(IirArgs a) {
-  iir_v_summary_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z});
-}
-template <typename Tin>
-__global__ __launch_bounds__(kVThreads) void k_iir_v_summary_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
-                                                     int n) {
-  const int i = group_find(start, n, blockIdx.x);
-  iir_v_summary_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
-}
-
-__device__ __forceinline__ void iir_v_fixup_impl(const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, float4 *__restrict__ cb, const Blk b) {
-
-  const int p = b.x * kFThreads + threadIdx.x;
-  const int kl = b.y;
-  const OrderEntry &e = lookup(tab, st.T_used);
-  const int k = k0 + kl;
-  if (k >= e.K || p >= g.Spos) return;
-  const int x = (p & (g.S - 1)) * g.cC + (p >> g.logS);
-  if (x >= g.W) return;
-  const float *Phi = iir + kIirPhiFull;
-  const float *Cm = iir + kIirCmFull;
-  const float *Mts = iir + kIirMts;
-  constexpr int U = 8;  // chunks whose summaries are loaded ahead
-  float4 P[3] = {f4(0.f), f4(0.f), f4(0.f)};
-  for (int j0 = 0; j0 < g.nc; j0 += U) {
-    float4 pb[U][3];
-#pragma unroll
-    for (int u = 0; u < U; u++)
-      if (j0 + u < g.nc) {
-        const size_t base = ((size_t)kl * g.nc + j0 + u) * 6;
-#pragma unroll
-        for (int r = 0; r < 3; r++) pb[u][r] = cb[(base + r) * g.Spos + p];
-      }
-#pragma unroll
-    for (int u = 0; u < U; u++)
-      if (j0 + u < g.nc) {
-        const size_t base = ((size_t)kl * g.nc + j0 + u) * 6;
-#pragma unroll
-        for (int r = 0; r < 3; r++) cb[(base + r) * g.Spos + p] = P[r];  // causal state entering the chunk
-        float4 np[3];
-        matvec3(Phi, P, np);
-#pragma unroll
-        for (int r = 0; r < 3; r++) P[r] = add4(pb[u][r], np[r]);
-      }
-  }
-  float4 E[3];
-  matvec3(Mts, P, E);  // zero extension below the padded column
-  for (int j0 = g.nc - 1; j0 >= 0; j0 -= U) {
-    float4 eb[U][3], pin[U][3];
-#pragma unroll
-    for (int u = 0; u < U; u++)
-      if (j0 - u >= 0) {
-        const size_t base = ((size_t)kl * g.nc + j0 - u) * 6;
-#pragma unroll
-        for (int r = 0; r < 3; r++) {
-          eb[u][r] = cb[(base + 3 + r) * g.Spos + p];
-          pin[u][r] = cb[(base + r) * g.Spos + p];
-        }
-      }
-#pragma unroll
-    for (int u = 0; u < U; u++)
-      if (j0 - u >= 0) {
-        const size_t base = ((size_t)kl * g.nc + j0 - u) * 6;
-#pragma unroll
-        for (int r = 0; r < 3; r++) cb[(base + 3 + r) * g.Spos + p] = E[r];  // anticausal state entering it
-        float4 t1[3];
-        matvec3(Phi, E, t1);
-        matvec3_acc(Cm, pin[u], t1);
-#pragma unroll
-        for (int r = 0; r < 3; r++) E[r] = add4(eb[u][r], t1[r]);
-      }
-  }
-}
-__device__ __forceinline__ void iir_v_fixup_body(const IirArgs &a, const Blk b) {
-  iir_v_fixup_impl(a.g, a.tab, a.st, a.iir, a.k0, a.cb, b);
-}
-
-__global__ __launch_bounds__(kFThreads) void k_iir_v_fixup(IirArgs a) {
-  iir_v_fixup_body(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
-}
-__global__ __launch_bounds__(kFThreads) void k_iir_v_fixup_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
-                                                     int n) {
-  const int i = group_find(start, n, blockIdx.x);
-  iir_v_fixup_body(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
-}
-
-template <typename Tin>
-__device__ __forceinline__ void iir_v_final_impl(const Tin *__restrict__ f, const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, const float4 *__restrict__ cb, float4 *__restrict__ Z, float2 *__restrict__ glut, const Blk b) {
-
-  const int p = b.x * kVThreads + threadIdx.x;
-  const int j = b.y;
-  const int kl = b.z;
-  const OrderEntry &e = lookup(tab, st.T_used);
-  const int k = k0 + kl;
-  if (k >= e.K) return;
-  const int32_t m = tab.pm[e.off + k];
-  const uint64_t q = e.qfix;
-  const double at = e.alpha_turn;
-  __shared__ float2 lut[PhaseLut<Tin>::kOn ? 256 : 1];
-  if constexpr (PhaseLut<Tin>::kOn) {
-    build_lut(lut, m, q, at, threadIdx.x, kVThreads);
-    // one workgroup per pair also leaves the table for the horizontal pass
-    if (b.x == 0 && j == 0) glut[(size_t)kl * 256 + threadIdx.x] = lut[threadIdx.x];
-    __syncthreads();
-  }
-  if (p >= g.Spos) return;
-  const int x = (p & (g.S - 1)) * g.cC + (p >> g.logS);
-  const int y0 = j * kB;
-  float4 *Zk = Z + (size_t)kl * g.H * g.Spos;
-  if (x >= g.W) {  // padding columns of the horizontal pass hold zeros
-    for (int i = 0; i < kB; i++)
-      if (y0 + i < g.H) Zk[(size_t)(y0 + i) * g.Spos + p] = f4(0.f);
-    return;
-  }
-  const float a1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
-  const size_t base = ((size_t)kl * g.nc + j) * 6;
-  float4 s = cb[(base + 0) * g.Spos + p];
-  float4 w = cb[(base + 1) * g.Spos + p];
-  float4 d = cb[(base + 2) * g.Spos + p];
-  const int n = min(kB, g.H - y0);
-  Tin fv[kB];
-#pragma unroll
-  for (int i = 0; i < kB; i++) fv[i] = f[(int64_t)(y0 + min(i, n - 1)) * g.pitch + x];
-  float4 wv[kB];
-#pragma unroll
-  for (int i = 0; i < kB; i++) {
-    float4 xv = f4(0.f);
-    if (i < n) xv = planes_any<Tin>(fv[i], lut, m, q, at, g.center);
-    casc_step(a1, g2, c2, xv, s, w, d);
-    wv[i] = w;
-  }
-  s = cb[(base + 3) * g.Spos + p];
-  w = cb[(base + 4) * g.Spos + p];
-  d = cb[(base + 5) * g.Spos + p];
-#pragma unroll
-  for (int i = kB - 1; i >= 0; i--) {
-    casc_step(a1, g2, c2, wv[i], s, w, d);
-    const int y = y0 + i;
-    if (y < g.H) Zk[(size_t)y * g.Spos + p] = w;
-  }
-}
-template <typename Tin>
-__device__ __forceinline__ void iir_v_final_body(const IirArgs &a, const Blk b) {
-  iir_v_final_impl<Tin>((const Tin *)a.f, a.g, a.tab, a.st, a.iir, a.k0, a.cb, a.Z, a.glut, b);
-}
-
-template <typename Tin>
-__global__ __launch_bounds__(kVThreads) void k_iir_v_final(IirArgs a) {
-  iir_v_final_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z});
-}
-template <typename Tin>
-__global__ __launch_bounds__(kVThreads) void k_iir_v_final_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
-                                                     int n) {
-  const int i = group_find(start, n, blockIdx.x);
-  iir_v_final_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
-}
-
-// ------------------------------------ horizontal pass + accumulate (a4, a5)
-// One workgroup per (image row, pair group); S threads per row group, NG =
-// 256/S groups each taking every NG-th frequency of the pair group.  Thread t owns kC consecutive columns: a causal
-// sweep from rest, an inclusive scan of the chunk end states across the row
-// group (Hillis-Steele with powers of A^kC, across waves through LDS when the
-// row spans several waves), the correction w += h . carry; the same for the
-// anticausal sweep, seeded at the padded end with the zero-extension boundary.
-// The smoothed images are combined on the fly into the numerator and the
-// denominator (eqs. (f1), (f2)) with the phases regenerated at each pixel.
 // Lane moves inside a wave through DPP (VALU only, no LDS round trip).  Lanes
 // whose source falls outside the pattern, or whose row the row mask leaves
 // out, read zero.
@@ -766,11 +548,193 @@ __device__ __forceinline__ void row1_acc(const float *__restrict__ M, const floa
   z = fma4(M[5], u[2], z);
 }
 
+// Constants of the blocked filter in LDS: A^{c m} for m = 0..64 and the end
+// boundary (the scans read them in divergent code, where constants from
+// memory would cost a round trip).
+struct IirLds {
+  float A[65 * 9];
+  float Mts[9];
+};
+template <int kC>
+__device__ __forceinline__ void load_iir_lds(IirLds &L, const float *__restrict__ iir, int tid) {
+  const float *hb = iir + (kC == kCSmall ? kIirHSmall : kIirHLarge);
+  for (int i = tid; i < 64 * 9; i += kHThreads) L.A[i] = hb[iir_h_lane(kC) + i];
+  if (tid < 9) {
+    L.A[64 * 9 + tid] = hb[iir_h_wave(kC) + tid];
+    L.Mts[tid] = iir[kIirMts + tid];
+  }
+}
+
+// The causal and anticausal cascade over one line held by a row group of S
+// threads (zv: this thread's kC samples, in place).  xw: this group's LDS
+// slots for the wave carries (S > 64); every thread of the workgroup calls it
+// (it holds barriers when S > 64).
+template <int S, int kC>
+__device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, float c2, const IirLds &L,
+                                           const float *__restrict__ Apow, float4 (*xw)[3], int t, int lane) {
+  constexpr int SW = S < 64 ? S : 64;
+  constexpr int NW = S > 64 ? S / 64 : 1;
+  const int ls = t % SW;
+  const int wig = t / 64;
+  const float *sA = L.A;
+  const float *waveM = L.A + 9 * 64;
+  // causal sweep from rest
+  float4 s = f4(0.f), w = f4(0.f), d = f4(0.f);
+#pragma unroll
+  for (int i = 0; i < kC; i++) {
+    casc_step(a1, g2, c2, zv[i], s, w, d);
+    zv[i] = w;
+  }
+  float4 inc[3] = {s, w, d};
+  scan_up<SW>(inc, sA, ls, lane);
+  float4 exc[3];
+#pragma unroll
+  for (int r = 0; r < 3; r++) exc[r] = keep4(ls != 0, dpp4<kDppWaveShr1>(inc[r]));
+  if constexpr (NW > 1) {
+    if (ls == 63) {
+#pragma unroll
+      for (int r = 0; r < 3; r++) xw[wig][r] = inc[r];
+    }
+    __syncthreads();
+    float4 Kc[3] = {f4(0.f), f4(0.f), f4(0.f)};
+    for (int v = 0; v < wig; v++) {
+      float4 tk[3];
+      matvec3(waveM, Kc, tk);
+#pragma unroll
+      for (int r = 0; r < 3; r++) Kc[r] = add4(xw[v][r], tk[r]);
+    }
+    __syncthreads();
+    matvec3_acc(sA + 9 * ls, Kc, exc);
+    if (t == S - 1) matvec3_acc(waveM, Kc, inc);
+  }
+  // true causal outputs
+#pragma unroll
+  for (int i = 0; i < kC; i++) row1_acc(Apow + 9 * (i + 1), exc, zv[i]);
+  // zero extension beyond the padded end
+  float4 Eb[3] = {f4(0.f), f4(0.f), f4(0.f)};
+  if (t == S - 1) matvec3(L.Mts, inc, Eb);
+  // anticausal sweep from rest
+  s = f4(0.f);
+  w = f4(0.f);
+  d = f4(0.f);
+#pragma unroll
+  for (int i = kC - 1; i >= 0; i--) {
+    casc_step(a1, g2, c2, zv[i], s, w, d);
+    zv[i] = w;
+  }
+  float4 hd[3] = {s, w, d};
+  if (t == S - 1) matvec3_acc(sA + 9, Eb, hd);  // A^c
+  scan_down<SW>(hd, sA, ls, lane);
+  float4 ein[3];
+#pragma unroll
+  for (int r = 0; r < 3; r++) ein[r] = keep4(ls != SW - 1, dpp4<kDppWaveShl1>(hd[r]));
+  if constexpr (NW > 1) {
+    if (ls == 0) {
+#pragma unroll
+      for (int r = 0; r < 3; r++) xw[wig][r] = hd[r];
+    }
+    __syncthreads();
+    float4 Kc[3] = {f4(0.f), f4(0.f), f4(0.f)};
+    for (int v = NW - 1; v > wig; v--) {
+      float4 tk[3];
+      matvec3(waveM, Kc, tk);
+#pragma unroll
+      for (int r = 0; r < 3; r++) Kc[r] = add4(xw[v][r], tk[r]);
+    }
+    __syncthreads();
+    matvec3_acc(sA + 9 * (63 - ls), Kc, ein);
+  }
+  if (t == S - 1) {
+#pragma unroll
+    for (int r = 0; r < 3; r++) ein[r] = Eb[r];
+  }
+#pragma unroll
+  for (int i = 0; i < kC; i++) row1_acc(Apow + 9 * (kC - i), ein, zv[i]);
+}
+
+// ------------------------------------------------ vertical pass (a3, a4)
+// One workgroup per (NG consecutive positions, pair); a row group of SV
+// threads per column, thread t owning rows [t kC, t kC + kC).  The four
+// images of the pair are generated from f at those rows (eq. (f1), (f2)
+// integrands, a3), smoothed down the column and written once.  Padding
+// columns (positions past the image width) are written as zeros.
+template <typename Tin, int SV, int kC>
+__device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, float4 *__restrict__ Z, float2 *__restrict__ glut, const Blk b) {
+  constexpr int NG = kHThreads / SV;
+  constexpr int NW = SV > 64 ? SV / 64 : 1;
+  __shared__ float4 xw[NG][NW][3];
+  __shared__ IirLds L;
+  __shared__ float2 lut[PhaseLut<Tin>::kOn ? 256 : 1];
+  const int tid = threadIdx.x;
+  const int t = tid % SV;
+  const int grp = tid / SV;
+  const int kl = b.y;
+  // column blocks in XCD order: the workgroups whose columns share the lines
+  // of a Z row run on one XCD, whose L2 merges their partial-line writes
+  const int ncb = (g.Spos + NG - 1) / NG;
+  const int per = (ncb + 7) / 8;
+  const int cbx = (b.x & 7) * per + (b.x >> 3);
+  if (cbx >= ncb) return;  // the whole workgroup: past the last column block
+  const OrderEntry &e = lookup(tab, st.T_used);
+  const int k = k0 + kl;
+  if (k >= e.K) return;  // the whole workgroup: pair not kept for this image's T
+  const int32_t m = tab.pm[e.off + k];
+  const uint64_t q = e.qfix;
+  const double at = e.alpha_turn;
+  if constexpr (PhaseLut<Tin>::kOn) {
+    build_lut(lut, m, q, at, tid, kHThreads);
+    // one workgroup per pair also leaves the table for the horizontal pass
+    if (cbx == 0) glut[(size_t)kl * 256 + tid] = lut[tid];
+  }
+  load_iir_lds<kC>(L, iir, tid);
+  __syncthreads();
+  const float a1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
+  const float *Apow = iir + (kC == kCSmall ? kIirHSmall : kIirHLarge) + iir_h_apow(kC);
+  const int p = cbx * NG + grp;
+  const bool inpos = p < g.Spos;
+  const int x = inpos ? (p & (g.S - 1)) * g.cC + (p >> g.logS) : 0;
+  const bool col = inpos && x < g.W;  // a column of the image (else zeros)
+  const int y0 = t * kC;
+  const int xc = min(x, g.W - 1);
+  Tin fv[kC];
+#pragma unroll
+  for (int i = 0; i < kC; i++) fv[i] = f[(int64_t)min(y0 + i, g.H - 1) * g.pitch + xc];
+  float4 zv[kC];
+#pragma unroll
+  for (int i = 0; i < kC; i++)
+    zv[i] = (col && y0 + i < g.H) ? planes_any<Tin>(fv[i], lut, m, q, at, g.center) : f4(0.f);
+  group_blur<SV, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
+  if (!inpos) return;
+  float4 *Zk = Z + (size_t)kl * g.Hz * g.Spos;
+#pragma unroll
+  for (int i = 0; i < kC; i++)
+    if (y0 + i < g.H) Zk[z_index(g, y0 + i, p)] = zv[i];
+}
+template <typename Tin, int SV, int kC>
+__device__ __forceinline__ void iir_v_body(const IirArgs &a, const Blk b) {
+  iir_v_impl<Tin, SV, kC>((const Tin *)a.f, a.g, a.tab, a.st, a.iir, a.k0, a.Z, a.glut, b);
+}
+template <typename Tin, int SV, int kC>
+__global__ __launch_bounds__(kHThreads, kC == kCSmall ? 2 : 1) void k_iir_v(IirArgs a) {
+  iir_v_body<Tin, SV, kC>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
+}
+template <typename Tin, int SV, int kC>
+__global__ __launch_bounds__(kHThreads, kC == kCSmall ? 2 : 1) void k_iir_v_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
+                                                     int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  iir_v_body<Tin, SV, kC>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+}
+
+// ------------------------------------ horizontal pass + accumulate (a4, a5)
+// One workgroup per (image row, pair group); S threads per row group, NG =
+// 256/S groups each taking every NG-th frequency of the pair group.  Each
+// group smooths its pair's four images along the row and combines them at
+// once into the numerator and the denominator (eqs. (f1), (f2)) with the
+// phases regenerated at each pixel.
 template <typename Tin, int S, int kC>
 __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, float *__restrict__ out, const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, int kcount, const float4 *__restrict__ Z, float2 *__restrict__ PQ, int first, int last, const float2 *__restrict__ glut, const Blk b) {
 
   constexpr int NG = kHThreads / S;
-  constexpr int SW = S < 64 ? S : 64;
   constexpr int NW = S > 64 ? S / 64 : 1;
   constexpr int PAD = S * (kC + 1);  // LDS row of one group, one slot skipped per kC
   // 8-bit inputs: the cos/sin tables of the groups' current pairs, copied to
@@ -781,13 +745,16 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   __shared__ float2 spq[NG * PAD];
   __shared__ float4 xw[NG][NW][3];
   __shared__ float2 slut[kLutLds ? NG * 256 : 1];
-  const int y = b.x;
+  __shared__ IirLds L;
+  // rows in XCD order: the workgroups of consecutive rows (which share the
+  // cache lines of tiled smoothed images) run on one XCD
+  const int per = (g.H + 7) / 8;
+  const int y = (b.x & 7) * per + (b.x >> 3);
+  if (y >= g.H) return;  // the whole workgroup: past the last row
   const int pg = b.y;  // pair group: launch-local pairs [kb, kb + hkpg)
   const int tid = threadIdx.x;
   const int t = tid % S;
   const int grp = tid / S;
-  const int ls = t % SW;
-  const int wig = t / 64;
   const OrderEntry &e = lookup(tab, st.T_used);
   const int kb = pg * g.hkpg;
   const int kend = min(min(kb + g.hkpg, kcount), e.K - k0);
@@ -795,20 +762,9 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   const bool finish = last && g.hgroups == 1;
   if (niter == 0 && !first && !finish) return;  // no pairs here: partial sums unchanged
   const float a1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
-  const float *hb = iir + (kC == kCSmall ? kIirHSmall : kIirHLarge);
-  const float *Apow = hb + iir_h_apow(kC);
-  // A^{c m} for m = 0..64 and the end boundary, in LDS: the scans read them
-  // in divergent code, where constants from memory would cost a round trip
-  __shared__ float sA[65 * 9];
-  __shared__ float sMts[9];
-  for (int i = tid; i < 64 * 9; i += kHThreads) sA[i] = hb[iir_h_lane(kC) + i];
-  if (tid < 9) {
-    sA[64 * 9 + tid] = hb[iir_h_wave(kC) + tid];
-    sMts[tid] = iir[kIirMts + tid];
-  }
+  const float *Apow = iir + (kC == kCSmall ? kIirHSmall : kIirHLarge) + iir_h_apow(kC);
+  load_iir_lds<kC>(L, iir, tid);
   __syncthreads();
-  const float *waveM = sA + 9 * 64;
-  const int lane = tid & 63;
   const Tin *frow = f + (int64_t)y * g.pitch;
   const int x0 = t * kC;
   float2 *mypq = spq + grp * PAD + t * (kC + 1);
@@ -827,82 +783,12 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
         for (int i = t; i < 256; i += S) slut[grp * 256 + i] = glut[(size_t)kl * 256 + i];
       __syncthreads();
     }
-    const float4 *Zr = Z + ((size_t)(act ? kl : 0) * g.H + y) * g.Spos;
+    const float4 *Zr = Z + (size_t)(act ? kl : 0) * g.Hz * g.Spos + z_index(g, y, 0);
+    const int qs = 1 << g.zlog;  // position stride
     float4 zv[kC];
 #pragma unroll
-    for (int i = 0; i < kC; i++) zv[i] = Zr[i * S + t];
-    // causal sweep from rest
-    float4 s = f4(0.f), w = f4(0.f), d = f4(0.f);
-#pragma unroll
-    for (int i = 0; i < kC; i++) {
-      casc_step(a1, g2, c2, zv[i], s, w, d);
-      zv[i] = w;
-    }
-    float4 inc[3] = {s, w, d};
-    scan_up<SW>(inc, sA, ls, lane);
-    float4 exc[3];
-#pragma unroll
-    for (int r = 0; r < 3; r++) exc[r] = keep4(ls != 0, dpp4<kDppWaveShr1>(inc[r]));
-    if constexpr (NW > 1) {
-      if (ls == 63) {
-#pragma unroll
-        for (int r = 0; r < 3; r++) xw[grp][wig][r] = inc[r];
-      }
-      __syncthreads();
-      float4 Kc[3] = {f4(0.f), f4(0.f), f4(0.f)};
-      for (int w = 0; w < wig; w++) {
-        float4 tk[3];
-        matvec3(waveM, Kc, tk);
-#pragma unroll
-        for (int r = 0; r < 3; r++) Kc[r] = add4(xw[grp][w][r], tk[r]);
-      }
-      __syncthreads();
-      matvec3_acc(sA + 9 * ls, Kc, exc);
-      if (t == S - 1) matvec3_acc(waveM, Kc, inc);
-    }
-    // true causal outputs
-#pragma unroll
-    for (int i = 0; i < kC; i++) row1_acc(Apow + 9 * (i + 1), exc, zv[i]);
-    // zero extension beyond the padded row end
-    float4 Eb[3] = {f4(0.f), f4(0.f), f4(0.f)};
-    if (t == S - 1) matvec3(sMts, inc, Eb);
-    // anticausal sweep from rest
-    s = f4(0.f);
-    w = f4(0.f);
-    d = f4(0.f);
-#pragma unroll
-    for (int i = kC - 1; i >= 0; i--) {
-      casc_step(a1, g2, c2, zv[i], s, w, d);
-      zv[i] = w;
-    }
-    float4 hd[3] = {s, w, d};
-    if (t == S - 1) matvec3_acc(sA + 9, Eb, hd);  // A^c
-    scan_down<SW>(hd, sA, ls, lane);
-    float4 ein[3];
-#pragma unroll
-    for (int r = 0; r < 3; r++) ein[r] = keep4(ls != SW - 1, dpp4<kDppWaveShl1>(hd[r]));
-    if constexpr (NW > 1) {
-      if (ls == 0) {
-#pragma unroll
-        for (int r = 0; r < 3; r++) xw[grp][wig][r] = hd[r];
-      }
-      __syncthreads();
-      float4 Kc[3] = {f4(0.f), f4(0.f), f4(0.f)};
-      for (int w = NW - 1; w > wig; w--) {
-        float4 tk[3];
-        matvec3(waveM, Kc, tk);
-#pragma unroll
-        for (int r = 0; r < 3; r++) Kc[r] = add4(xw[grp][w][r], tk[r]);
-      }
-      __syncthreads();
-      matvec3_acc(sA + 9 * (63 - ls), Kc, ein);
-    }
-    if (t == S - 1) {
-#pragma unroll
-      for (int r = 0; r < 3; r++) ein[r] = Eb[r];
-    }
-#pragma unroll
-    for (int i = 0; i < kC; i++) row1_acc(Apow + 9 * (kC - i), ein, zv[i]);
+    for (int i = 0; i < kC; i++) zv[i] = Zr[(size_t)(i * S + t) * qs];
+    group_blur<S, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
     // eqs. (f1), (f2): weight by the phase at the output pixel
     if (act) {
       const int k = k0 + kl;
@@ -1117,19 +1003,19 @@ hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g
   }
 }
 
-// Per-image arguments of the four recursive-path kernels for pairs
-// [k0, k0+kcount) (also the per-image entries of grouped launches).
+// Per-image arguments of the two recursive-path kernels for pairs
+// [k0, k0+kcount) (also the per-image entries of grouped launches) and of the
+// sum of the pair groups.
 void iir_args(const void *f, float *out, const Geom &g, DevTables tab, DevState st, const float *iir, int k0,
-              int kcount, float4 *cb, float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, IirArgs a[4],
+              int kcount, float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, IirArgs a[2],
               FinishArgs &fa) {
-  const int nbx = (g.Spos + kVThreads - 1) / kVThreads;
-  const int nfx = (g.Spos + kFThreads - 1) / kFThreads;
-  const IirArgs base{GroupGrid{1, 1, 1}, f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, (int)first, (int)last, glut};
-  for (int i = 0; i < 4; i++) a[i] = base;
-  a[0].gg = GroupGrid{nbx, g.nc, kcount};      // summary
-  a[1].gg = GroupGrid{nfx, kcount, 1};         // carries
-  a[2].gg = GroupGrid{nbx, g.nc, kcount};      // final
-  a[3].gg = GroupGrid{g.H, g.hgroups, 1};      // horizontal + combine
+  const IirArgs base{GroupGrid{1, 1, 1}, f, out, g, tab, st, iir, k0, kcount, Z, PQ, (int)first, (int)last, glut};
+  a[0] = base;
+  a[1] = base;
+  const int ng = kHThreads / g.vS;  // columns per vertical workgroup
+  const int per = ((g.Spos + ng - 1) / ng + 7) / 8;
+  a[0].gg = GroupGrid{8 * per, kcount, 1};  // vertical (column blocks in XCD order)
+  a[1].gg = GroupGrid{8 * ((g.H + 7) / 8), g.hgroups, 1};  // horizontal + combine (rows in XCD order)
   const int64_t npx = (int64_t)g.H * g.W;
   const int nfin = (last && g.hgroups > 1) ? (int)((npx + 255) / 256) : 0;
   fa = FinishArgs{GroupGrid{nfin > 0 ? nfin : 1, 1, 1}, f, out, g, st, (const float2 *)PQ, g.hgroups, 1.0f};
@@ -1154,8 +1040,15 @@ hipError_t launch_finish(hipStream_t s, bf_dtype dt, const FinishArgs *one, cons
   return hipGetLastError();
 }
 
-// Launch of the horizontal kernel for threads-per-row S and chunk C, single
-// image (args) or grouped (arr, start, n, total).
+// Launches of the two kernels for a row group size and chunk, single image
+// (one) or grouped (arr, start, n, total).
+template <typename Tin, int S, int C>
+static void launch_v(hipStream_t s, const IirArgs *one, const IirArgs *arr, const int *start, int n, int total) {
+  if (one)
+    hipLaunchKernelGGL((k_iir_v<Tin, S, C>), dim3(one->gg.gx, one->gg.gy), dim3(kHThreads), 0, s, *one);
+  else if (total > 0)
+    hipLaunchKernelGGL((k_iir_v_grp<Tin, S, C>), dim3(total), dim3(kHThreads), 0, s, arr, start, n);
+}
 template <typename Tin, int S, int C>
 static void launch_h(hipStream_t s, const IirArgs *one, const IirArgs *arr, const int *start, int n, int total) {
   if (one)
@@ -1185,79 +1078,94 @@ static bool launch_h_any(hipStream_t s, int S, int cC, const IirArgs *one, const
   return cC == kCSmall ? launch_h_S<Tin, kCSmall>(s, S, one, arr, start, n, total)
                        : launch_h_S<Tin, kCLarge>(s, S, one, arr, start, n, total);
 }
+// Columns taller than kCSmall * kHThreads use the long chunk (then always a
+// full workgroup per column).
+template <typename Tin>
+static bool launch_v_any(hipStream_t s, int S, int cV, const IirArgs *one, const IirArgs *arr, const int *start,
+                         int n, int total) {
+  if (cV == kCLarge) {
+    if (S != kHThreads) return false;
+    launch_v<Tin, kHThreads, kCLarge>(s, one, arr, start, n, total);
+    return true;
+  }
+  switch (S) {
+    case 1: launch_v<Tin, 1, kCSmall>(s, one, arr, start, n, total); return true;
+    case 2: launch_v<Tin, 2, kCSmall>(s, one, arr, start, n, total); return true;
+    case 4: launch_v<Tin, 4, kCSmall>(s, one, arr, start, n, total); return true;
+    case 8: launch_v<Tin, 8, kCSmall>(s, one, arr, start, n, total); return true;
+    case 16: launch_v<Tin, 16, kCSmall>(s, one, arr, start, n, total); return true;
+    case 32: launch_v<Tin, 32, kCSmall>(s, one, arr, start, n, total); return true;
+    case 64: launch_v<Tin, 64, kCSmall>(s, one, arr, start, n, total); return true;
+    case 128: launch_v<Tin, 128, kCSmall>(s, one, arr, start, n, total); return true;
+    case 256: launch_v<Tin, 256, kCSmall>(s, one, arr, start, n, total); return true;
+    default: return false;
+  }
+}
+
+static bool iir_geom_ok(const Geom &g, int kcount) {
+  return g.hgroups >= 1 && g.hgroups <= 65535 && g.hkpg >= 1 && (int64_t)g.hgroups * g.hkpg >= kcount &&
+         kcount >= 1 && kcount <= 65535 && g.vS >= 1 && g.vS <= kHThreads && (int64_t)g.vS * g.vC >= g.H &&
+         (int64_t)g.S * g.cC >= g.W && g.Spos == g.S * g.cC && g.zlog >= 0 && g.zlog <= 3 && g.Hz >= g.H && g.Hz % (1 << g.zlog) == 0;
+}
 
 template <typename Tin>
 static hipError_t iir_chunk_t(hipStream_t s, const Tin *f, float *out, const Geom &g, DevTables tab,
-                              DevState st, const float *iir, int k0, int kcount, float4 *cb, float4 *Z,
-                              float2 *PQ, bool first, bool last, float2 *glut, const StageRec &rec) {
-  if (g.hgroups < 1 || g.hgroups > 65535 || g.hkpg < 1 || (int64_t)g.hgroups * g.hkpg < kcount)
-    return hipErrorInvalidValue;
-  IirArgs a[4];
+                              DevState st, const float *iir, int k0, int kcount, float4 *Z, float2 *PQ,
+                              bool first, bool last, float2 *glut, const StageRec &rec) {
+  if (!iir_geom_ok(g, kcount)) return hipErrorInvalidValue;
+  IirArgs a[2];
   FinishArgs fa;
-  iir_args(f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, first, last, glut, a, fa);
-  if (kcount > 0) {
-    rec.begin(BF_STAGE_V_SUMMARY, s);
-    hipLaunchKernelGGL(k_iir_v_summary<Tin>, dim3(a[0].gg.gx, a[0].gg.gy, a[0].gg.gz), dim3(kVThreads), 0, s, a[0]);
-    rec.end(BF_STAGE_V_SUMMARY, s);
-    rec.begin(BF_STAGE_V_CARRY, s);
-    hipLaunchKernelGGL(k_iir_v_fixup, dim3(a[1].gg.gx, a[1].gg.gy), dim3(kFThreads), 0, s, a[1]);
-    rec.end(BF_STAGE_V_CARRY, s);
-    rec.begin(BF_STAGE_V_FINAL, s);
-    hipLaunchKernelGGL(k_iir_v_final<Tin>, dim3(a[2].gg.gx, a[2].gg.gy, a[2].gg.gz), dim3(kVThreads), 0, s, a[2]);
-    rec.end(BF_STAGE_V_FINAL, s);
-  }
+  iir_args(f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut, a, fa);
+  rec.begin(BF_STAGE_V_IIR, s);
+  if (!launch_v_any<Tin>(s, g.vS, g.vC, &a[0], nullptr, nullptr, 0, 0)) return hipErrorInvalidValue;
+  rec.end(BF_STAGE_V_IIR, s);
   rec.begin(BF_STAGE_H_COMBINE, s);
-  const bool ok = launch_h_any<Tin>(s, g.S, g.cC, &a[3], nullptr, nullptr, 0, 0);
-  if (!ok) return hipErrorInvalidValue;
+  if (!launch_h_any<Tin>(s, g.S, g.cC, &a[1], nullptr, nullptr, 0, 0)) return hipErrorInvalidValue;
   if (last && g.hgroups > 1) (void)launch_finish(s, dtype_of<Tin>(), &fa, nullptr, nullptr, 0, 0);
   rec.end(BF_STAGE_H_COMBINE, s);
   return hipGetLastError();
 }
 
-// Grouped recursive-path stages over n images of one dtype, threads-per-row
-// S and chunk cC (single launch of all their pairs each).
-template <typename Tin>
-static hipError_t iir_group_t(hipStream_t s, int S, int cC, const IirGroup &ig, const StageRec &rec) {
-  rec.begin(BF_STAGE_V_SUMMARY, s);
-  if (ig.total[0] > 0)
-    hipLaunchKernelGGL(k_iir_v_summary_grp<Tin>, dim3(ig.total[0]), dim3(kVThreads), 0, s, ig.a[0], ig.start[0], ig.n);
-  rec.end(BF_STAGE_V_SUMMARY, s);
-  rec.begin(BF_STAGE_V_CARRY, s);
-  if (ig.total[1] > 0)
-    hipLaunchKernelGGL(k_iir_v_fixup_grp, dim3(ig.total[1]), dim3(kFThreads), 0, s, ig.a[1], ig.start[1], ig.n);
-  rec.end(BF_STAGE_V_CARRY, s);
-  rec.begin(BF_STAGE_V_FINAL, s);
-  if (ig.total[2] > 0)
-    hipLaunchKernelGGL(k_iir_v_final_grp<Tin>, dim3(ig.total[2]), dim3(kVThreads), 0, s, ig.a[2], ig.start[2], ig.n);
-  rec.end(BF_STAGE_V_FINAL, s);
-  rec.begin(BF_STAGE_H_COMBINE, s);
-  const bool ok = launch_h_any<Tin>(s, S, cC, nullptr, ig.a[3], ig.start[3], ig.n, ig.total[3]);
-  if (ig.ftotal > 0) (void)launch_finish(s, dtype_of<Tin>(), nullptr, ig.fa, ig.fstart, ig.n, ig.ftotal);
-  rec.end(BF_STAGE_H_COMBINE, s);
-  if (!ok) return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-hipError_t launch_iir_group(hipStream_t s, bf_dtype dt, int S, int cC, const IirGroup &ig, const StageRec &rec) {
+hipError_t launch_iir_v_group(hipStream_t s, bf_dtype dt, int SV, int cV, const IirArgs *a, const int *start,
+                              int n, int total, const StageRec &rec) {
+  rec.begin(BF_STAGE_V_IIR, s);
+  bool ok;
   switch (dt) {
-    case BF_U8: return iir_group_t<uint8_t>(s, S, cC, ig, rec);
-    case BF_U16: return iir_group_t<uint16_t>(s, S, cC, ig, rec);
-    default: return iir_group_t<float>(s, S, cC, ig, rec);
+    case BF_U8: ok = launch_v_any<uint8_t>(s, SV, cV, nullptr, a, start, n, total); break;
+    case BF_U16: ok = launch_v_any<uint16_t>(s, SV, cV, nullptr, a, start, n, total); break;
+    default: ok = launch_v_any<float>(s, SV, cV, nullptr, a, start, n, total); break;
   }
+  rec.end(BF_STAGE_V_IIR, s);
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
+}
+hipError_t launch_iir_h_group(hipStream_t s, bf_dtype dt, int S, int cC, const IirArgs *a, const int *start,
+                              int n, int total, const FinishArgs *fa, const int *fstart, int ftotal,
+                              const StageRec &rec) {
+  rec.begin(BF_STAGE_H_COMBINE, s);
+  bool ok;
+  switch (dt) {
+    case BF_U8: ok = launch_h_any<uint8_t>(s, S, cC, nullptr, a, start, n, total); break;
+    case BF_U16: ok = launch_h_any<uint16_t>(s, S, cC, nullptr, a, start, n, total); break;
+    default: ok = launch_h_any<float>(s, S, cC, nullptr, a, start, n, total); break;
+  }
+  if (ok && ftotal > 0) (void)launch_finish(s, dt, nullptr, fa, fstart, n, ftotal);
+  rec.end(BF_STAGE_H_COMBINE, s);
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
 hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *out, const Geom &g,
-                            DevTables tab, DevState st, const float *iir, int k0, int kcount, float4 *cb,
-                            float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, const StageRec &rec) {
+                            DevTables tab, DevState st, const float *iir, int k0, int kcount, float4 *Z,
+                            float2 *PQ, bool first, bool last, float2 *glut, const StageRec &rec) {
   switch (dt) {
     case BF_U8:
-      return iir_chunk_t<uint8_t>(s, (const uint8_t *)f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, first,
-                                  last, glut, rec);
+      return iir_chunk_t<uint8_t>(s, (const uint8_t *)f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last,
+                                  glut, rec);
     case BF_U16:
-      return iir_chunk_t<uint16_t>(s, (const uint16_t *)f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ,
-                                   first, last, glut, rec);
+      return iir_chunk_t<uint16_t>(s, (const uint16_t *)f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last,
+                                   glut, rec);
     default:
-      return iir_chunk_t<float>(s, (const float *)f, out, g, tab, st, iir, k0, kcount, cb, Z, PQ, first,
-                                last, glut, rec);
+      return iir_chunk_t<float>(s, (const float *)f, out, g, tab, st, iir, k0, kcount, Z, PQ, first, last, glut,
+                                rec);
   }
 }
 

@@ -168,32 +168,6 @@ struct Casc {
 };
 void put(std::vector<float> &o, int off, const M3 &m) { for (int i = 0; i < 9; i++) o[off + i] = (float)m.a[i]; }
 
-// chunk summaries for a chunk of length n: end state per unit input (3 x n),
-// anticausal head state per unit input (3 x n), A^n, and the map from the
-// causal state entering the chunk to the anticausal head it produces (3x3)
-void chunk_mats(const Casc &cs, int n, std::vector<float> &o, int offAp, int offAe, int offPhi,
-                int offCm, const M3 &A) {
-  std::vector<double> w(n);
-  for (int i = 0; i < n; i++) {
-    double st[3] = {0, 0, 0};
-    for (int t = 0; t < n; t++) { cs.step(st, t == i ? 1.0 : 0.0); w[t] = st[1]; }
-    for (int r = 0; r < 3; r++) o[offAp + r * kB + i] = (float)st[r];
-    double q[3] = {0, 0, 0};
-    for (int t = n - 1; t >= 0; t--) cs.step(q, w[t]);
-    for (int r = 0; r < 3; r++) o[offAe + r * kB + i] = (float)q[r];
-  }
-  put(o, offPhi, mpow(A, n));
-  M3 C{};
-  for (int j = 0; j < 3; j++) {
-    double st[3] = {0, 0, 0};
-    st[j] = 1.0;
-    for (int t = 0; t < n; t++) { cs.step(st, 0.0); w[t] = st[1]; }
-    double q[3] = {0, 0, 0};
-    for (int t = n - 1; t >= 0; t--) cs.step(q, w[t]);
-    for (int r = 0; r < 3; r++) C.a[r * 3 + j] = q[r];
-  }
-  put(o, offCm, C);
-}
 }  // namespace
 
 bool build_iir_consts(double sigma_s, std::vector<float> &out, std::string &err) {
@@ -224,7 +198,6 @@ bool build_iir_consts(double sigma_s, std::vector<float> &out, std::string &err)
     for (int r = 0; r < 3; r++) mts.a[r * 3 + j] = q[r];
   }
   put(out, kIirMts, mts);
-  chunk_mats(cs, kB, out, kIirApFull, kIirAeFull, kIirPhiFull, kIirCmFull, A);
   for (int c : {kCSmall, kCLarge}) {
     const int hb = c == kCSmall ? kIirHSmall : kIirHLarge;
     for (int v = 0; v <= c; v++) put(out, hb + iir_h_apow(c) + 9 * v, mpow(A, v));

@@ -559,10 +559,10 @@ static hipError_t toep_t(hipStream_t s, const Tin *f, float *out, const Geom &g,
   ToepHArgs ha;
   FinishArgs fa;
   toeplitz_args(variant, f, out, g, tab, st, tc, k0, kcount, Z, PQ, first, last, va, ha, fa);
-  rec.begin(BF_STAGE_TOEPLITZ, s);
+  rec.begin(BF_STAGE_V_TOEPLITZ, s);
   hipLaunchKernelGGL((k_toep_v<Tin, BF, SPLIT>), dim3(va.gg.gx, va.gg.gy), dim3(256),
                      toeplitz_v_lds(variant, tc.rows, tc.nks), s, va);
-  rec.end(BF_STAGE_TOEPLITZ, s);
+  rec.end(BF_STAGE_V_TOEPLITZ, s);
   rec.begin(BF_STAGE_H_COMBINE, s);
   hipLaunchKernelGGL((k_toep_h<Tin, BF, SPLIT>), dim3(ha.gg.gx, ha.gg.gy), dim3(256), toeplitz_h_lds(variant, tc.nks),
                      s, ha);
@@ -576,11 +576,11 @@ static hipError_t toep_t(hipStream_t s, const Tin *f, float *out, const Geom &g,
 // of the images that split their pairs into several groups.
 template <typename Tin, bool BF, bool SPLIT>
 static hipError_t toep_group_t(hipStream_t s, const ToepGroup &tg, const StageRec &rec) {
-  rec.begin(BF_STAGE_TOEPLITZ, s);
+  rec.begin(BF_STAGE_V_TOEPLITZ, s);
   if (tg.vtotal > 0)
     hipLaunchKernelGGL((k_toep_v_grp<Tin, BF, SPLIT>), dim3(tg.vtotal), dim3(256), tg.vlds, s, tg.va, tg.vstart,
                        tg.n);
-  rec.end(BF_STAGE_TOEPLITZ, s);
+  rec.end(BF_STAGE_V_TOEPLITZ, s);
   rec.begin(BF_STAGE_H_COMBINE, s);
   if (tg.htotal > 0)
     hipLaunchKernelGGL((k_toep_h_grp<Tin, BF, SPLIT>), dim3(tg.htotal), dim3(256), tg.hlds, s, tg.ha, tg.hstart,

@@ -29,10 +29,8 @@ int shim_iir_consts(double sigma, float *out, int n) {
 }
 int shim_layout(int c, int *o) {
   const int hb = c == bfi::kCSmall ? bfi::kIirHSmall : bfi::kIirHLarge;
-  o[0] = bfi::kIirCoef; o[1] = bfi::kIirMts; o[2] = bfi::kIirApFull; o[3] = bfi::kIirAeFull;
-  o[4] = bfi::kIirPhiFull; o[5] = bfi::kIirCmFull; o[6] = hb + bfi::iir_h_apow(c); o[7] = bfi::kIirSize;
-  o[8] = bfi::kB; o[9] = c; o[10] = hb + bfi::iir_h_lane(c); o[11] = hb + bfi::iir_h_scan(c);
-  o[12] = hb + bfi::iir_h_wave(c);
+  o[0] = bfi::kIirCoef; o[1] = bfi::kIirMts; o[2] = hb + bfi::iir_h_apow(c); o[3] = bfi::kIirSize;
+  o[4] = c; o[5] = hb + bfi::iir_h_lane(c); o[6] = hb + bfi::iir_h_scan(c); o[7] = hb + bfi::iir_h_wave(c);
   return 0;
 }
 }
