@@ -239,9 +239,8 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   g.logS = logS;
   g.cC = cC;
   g.Spos = S * cC;
-  // vertical pass: one row group per column, kCSmall rows per thread (the long
-  // chunk only for columns taller than a workgroup of short ones)
-  g.vC = g.H > kCSmall * kHThreads ? kCLarge : kCSmall;
+  // vertical pass: one row group per column, kCLarge rows per thread
+  g.vC = kCLarge;
   g.vS = 1;
   while (g.vS * g.vC < g.H) g.vS <<= 1;
   // a vertical workgroup covers 256 / vS columns: below 8 (one 128-byte line

@@ -96,10 +96,15 @@ __device__ __forceinline__ int group_find(const int *__restrict__ start, int n, 
     if (start[mid] <= bid) lo = mid;
     else hi = mid - 1;
   }
-  return lo;
+  // the same for every lane of the workgroup: say so, so that the image's
+  // arguments are read with scalar loads into scalar registers
+  return __builtin_amdgcn_readfirstlane(lo);
 }
 __device__ __forceinline__ Blk group_blk(const GroupGrid &gg, int local) {
-  return Blk{local % gg.gx, (local / gg.gx) % gg.gy, local / (gg.gx * gg.gy)};
+  // the division runs on the vector unit; its results are the same in every
+  // lane, and saying so keeps what derives from them in scalar registers
+  return Blk{__builtin_amdgcn_readfirstlane(local % gg.gx), __builtin_amdgcn_readfirstlane((local / gg.gx) % gg.gy),
+             __builtin_amdgcn_readfirstlane(local / (gg.gx * gg.gy))};
 }
 
 // Offset of element (y, p) of one pair's smoothed images (recursive path).

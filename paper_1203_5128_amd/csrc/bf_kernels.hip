@@ -37,15 +37,28 @@ __device__ __forceinline__ void matvec3(const float *__restrict__ M, const float
     r[i] = a;
   }
 }
-// v += M u
-__device__ __forceinline__ void matvec3_acc(const float *__restrict__ M, const float4 u[3], float4 v[3]) {
+// M u for M a power of the cascade's zero-input state matrix
+// A, whose first row is (m00, 0, 0): the first-order section does not see the
+// second-order state (the tables hold those zeros exactly).
+__device__ __forceinline__ void apow_acc(const float *__restrict__ M, const float4 u[3], float4 v[3]) {
+  v[0] = fma4(M[0], u[0], v[0]);
 #pragma unroll
-  for (int i = 0; i < 3; i++) {
+  for (int i = 1; i < 3; i++) {
     v[i] = fma4(M[3 * i + 0], u[0], v[i]);
     v[i] = fma4(M[3 * i + 1], u[1], v[i]);
     v[i] = fma4(M[3 * i + 2], u[2], v[i]);
   }
 }
+__device__ __forceinline__ void apow_mul(const float *__restrict__ M, const float4 u[3], float4 r[3]) {
+  r[0] = make_float4(M[0] * u[0].x, M[0] * u[0].y, M[0] * u[0].z, M[0] * u[0].w);
+#pragma unroll
+  for (int i = 1; i < 3; i++) {
+    float4 a = make_float4(M[3 * i] * u[0].x, M[3 * i] * u[0].y, M[3 * i] * u[0].z, M[3 * i] * u[0].w);
+    a = fma4(M[3 * i + 1], u[1], a);
+    r[i] = fma4(M[3 * i + 2], u[2], a);
+  }
+}
+
 // One step of the recursive Gaussian cascade on the state (s, w, d):
 // first-order section s = a1 s + x (a1 = 1 - g1; the input gain g1 is left
 // out, a constant factor per pass common to all smoothed images, which
@@ -485,14 +498,14 @@ __device__ __forceinline__ void up_step(float4 v[3], const float *__restrict__ M
   float4 o[3];
 #pragma unroll
   for (int r = 0; r < 3; r++) o[r] = keep4(SW >= 16 || ls >= D, dpp4<kDppRowShr + D>(v[r]));
-  matvec3_acc(M, o, v);
+  apow_acc(M, o, v);
 }
 template <int D, int SW>
 __device__ __forceinline__ void down_step(float4 v[3], const float *__restrict__ M, int ls) {
   float4 o[3];
 #pragma unroll
   for (int r = 0; r < 3; r++) o[r] = keep4(SW >= 16 || ls + D < SW, dpp4<kDppRowShl + D>(v[r]));
-  matvec3_acc(M, o, v);
+  apow_acc(M, o, v);
 }
 template <int SW>
 __device__ __forceinline__ void scan_up(float4 v[3], const float *__restrict__ sA, int ls, int lane) {
@@ -505,13 +518,13 @@ __device__ __forceinline__ void scan_up(float4 v[3], const float *__restrict__ s
     float4 o[3];
 #pragma unroll
     for (int r = 0; r < 3; r++) o[r] = dpp4<kDppRowBcast15, 0xA, false>(v[r]);
-    matvec3_acc(sA + 9 * (j + 1), o, v);
+    apow_acc(sA + 9 * (j + 1), o, v);
   }
   if constexpr (SW == 64) {  // rows 2 and 3 take the total of lanes 0..31
     float4 o[3];
 #pragma unroll
     for (int r = 0; r < 3; r++) o[r] = dpp4<kDppRowBcast31, 0xC, false>(v[r]);
-    matvec3_acc(sA + 9 * max(lane - 31, 0), o, v);
+    apow_acc(sA + 9 * max(lane - 31, 0), o, v);
   }
 }
 template <int SW>
@@ -529,7 +542,7 @@ __device__ __forceinline__ void scan_down(float4 v[3], const float *__restrict__
     for (int r = 0; r < 3; r++)
       o[r] = keep4(even, make_float4(__shfl(v[r].x, src, 64), __shfl(v[r].y, src, 64), __shfl(v[r].z, src, 64),
                                      __shfl(v[r].w, src, 64)));
-    matvec3_acc(sA + 9 * (16 - j), o, v);
+    apow_acc(sA + 9 * (16 - j), o, v);
   }
   if constexpr (SW == 64) {  // rows 0 and 1 take the total of lanes 32..63
     const bool lo = lane < 32;
@@ -538,11 +551,16 @@ __device__ __forceinline__ void scan_down(float4 v[3], const float *__restrict__
     for (int r = 0; r < 3; r++)
       o[r] = keep4(lo, make_float4(lane_value(v[r].x, 32), lane_value(v[r].y, 32), lane_value(v[r].z, 32),
                                    lane_value(v[r].w, 32)));
-    matvec3_acc(sA + 9 * max(32 - lane, 0), o, v);
+    apow_acc(sA + 9 * max(32 - lane, 0), o, v);
   }
 }
 // z += row 1 of M times u (the w-component response to the state u)
-__device__ __forceinline__ void row1_acc(const float *__restrict__ M, const float4 u[3], float4 &z) {
+// Read-only constants of a launch, addressed as constant memory: loads with
+// a uniform address become scalar loads whatever the pointer's origin.
+typedef const __attribute__((address_space(4))) float *cfloat_p;
+__device__ __forceinline__ cfloat_p as_const(const float *p) { return (cfloat_p)p; }
+
+__device__ __forceinline__ void row1_acc(cfloat_p M, const float4 u[3], float4 &z) {
   z = fma4(M[3], u[0], z);
   z = fma4(M[4], u[1], z);
   z = fma4(M[5], u[2], z);
@@ -555,13 +573,34 @@ struct IirLds {
   float A[65 * 9];
   float Mts[9];
 };
+// Fetched into registers first and written to LDS later, so that loads
+// issued in between (memory counters complete in order) need not be waited
+// for before the tables are stored.
+struct IirLdsRegs {
+  float a[3], w, m;
+};
 template <int kC>
-__device__ __forceinline__ void load_iir_lds(IirLds &L, const float *__restrict__ iir, int tid) {
+__device__ __forceinline__ IirLdsRegs fetch_iir_lds(const float *__restrict__ iir, int tid) {
   const float *hb = iir + (kC == kCSmall ? kIirHSmall : kIirHLarge);
-  for (int i = tid; i < 64 * 9; i += kHThreads) L.A[i] = hb[iir_h_lane(kC) + i];
+  IirLdsRegs r;
+#pragma unroll
+  for (int j = 0; j < 3; j++) {
+    const int i = tid + j * kHThreads;
+    r.a[j] = i < 64 * 9 ? hb[iir_h_lane(kC) + i] : 0.f;
+  }
+  r.w = tid < 9 ? hb[iir_h_wave(kC) + tid] : 0.f;
+  r.m = tid < 9 ? iir[kIirMts + tid] : 0.f;
+  return r;
+}
+__device__ __forceinline__ void store_iir_lds(IirLds &L, const IirLdsRegs &r, int tid) {
+#pragma unroll
+  for (int j = 0; j < 3; j++) {
+    const int i = tid + j * kHThreads;
+    if (i < 64 * 9) L.A[i] = r.a[j];
+  }
   if (tid < 9) {
-    L.A[64 * 9 + tid] = hb[iir_h_wave(kC) + tid];
-    L.Mts[tid] = iir[kIirMts + tid];
+    L.A[64 * 9 + tid] = r.w;
+    L.Mts[tid] = r.m;
   }
 }
 
@@ -571,7 +610,7 @@ __device__ __forceinline__ void load_iir_lds(IirLds &L, const float *__restrict_
 // (it holds barriers when S > 64).
 template <int S, int kC>
 __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, float c2, const IirLds &L,
-                                           const float *__restrict__ Apow, float4 (*xw)[3], int t, int lane) {
+                                           cfloat_p Apow, float4 (*xw)[3], int t, int lane) {
   constexpr int SW = S < 64 ? S : 64;
   constexpr int NW = S > 64 ? S / 64 : 1;
   const int ls = t % SW;
@@ -599,13 +638,13 @@ __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, fl
     float4 Kc[3] = {f4(0.f), f4(0.f), f4(0.f)};
     for (int v = 0; v < wig; v++) {
       float4 tk[3];
-      matvec3(waveM, Kc, tk);
+      apow_mul(waveM, Kc, tk);
 #pragma unroll
       for (int r = 0; r < 3; r++) Kc[r] = add4(xw[v][r], tk[r]);
     }
     __syncthreads();
-    matvec3_acc(sA + 9 * ls, Kc, exc);
-    if (t == S - 1) matvec3_acc(waveM, Kc, inc);
+    apow_acc(sA + 9 * ls, Kc, exc);
+    if (t == S - 1) apow_acc(waveM, Kc, inc);
   }
   // true causal outputs
 #pragma unroll
@@ -623,7 +662,7 @@ __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, fl
     zv[i] = w;
   }
   float4 hd[3] = {s, w, d};
-  if (t == S - 1) matvec3_acc(sA + 9, Eb, hd);  // A^c
+  if (t == S - 1) apow_acc(sA + 9, Eb, hd);  // A^c
   scan_down<SW>(hd, sA, ls, lane);
   float4 ein[3];
 #pragma unroll
@@ -637,12 +676,12 @@ __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, fl
     float4 Kc[3] = {f4(0.f), f4(0.f), f4(0.f)};
     for (int v = NW - 1; v > wig; v--) {
       float4 tk[3];
-      matvec3(waveM, Kc, tk);
+      apow_mul(waveM, Kc, tk);
 #pragma unroll
       for (int r = 0; r < 3; r++) Kc[r] = add4(xw[v][r], tk[r]);
     }
     __syncthreads();
-    matvec3_acc(sA + 9 * (63 - ls), Kc, ein);
+    apow_acc(sA + 9 * (63 - ls), Kc, ein);
   }
   if (t == S - 1) {
 #pragma unroll
@@ -664,7 +703,9 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
   constexpr int NW = SV > 64 ? SV / 64 : 1;
   __shared__ float4 xw[NG][NW][3];
   __shared__ IirLds L;
-  __shared__ float2 lut[PhaseLut<Tin>::kOn ? 256 : 1];
+  // 8-bit inputs: cos/sin per intensity, and a zero entry for the samples
+  // outside the image
+  __shared__ float2 lut[PhaseLut<Tin>::kOn ? 257 : 1];
   const int tid = threadIdx.x;
   const int t = tid % SV;
   const int grp = tid / SV;
@@ -675,34 +716,52 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
   const int per = (ncb + 7) / 8;
   const int cbx = (b.x & 7) * per + (b.x >> 3);
   if (cbx >= ncb) return;  // the whole workgroup: past the last column block
-  const OrderEntry &e = lookup(tab, st.T_used);
+  const UEntry e = uniform_entry(tab, st.T_used);
   const int k = k0 + kl;
   if (k >= e.K) return;  // the whole workgroup: pair not kept for this image's T
-  const int32_t m = tab.pm[e.off + k];
-  const uint64_t q = e.qfix;
-  const double at = e.alpha_turn;
-  if constexpr (PhaseLut<Tin>::kOn) {
-    build_lut(lut, m, q, at, tid, kHThreads);
-    // one workgroup per pair also leaves the table for the horizontal pass
-    if (cbx == 0) glut[(size_t)kl * 256 + tid] = lut[tid];
-  }
-  load_iir_lds<kC>(L, iir, tid);
-  __syncthreads();
-  const float a1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
-  const float *Apow = iir + (kC == kCSmall ? kIirHSmall : kIirHLarge) + iir_h_apow(kC);
   const int p = cbx * NG + grp;
   const bool inpos = p < g.Spos;
   const int x = inpos ? (p & (g.S - 1)) * g.cC + (p >> g.logS) : 0;
   const bool col = inpos && x < g.W;  // a column of the image (else zeros)
   const int y0 = t * kC;
   const int xc = min(x, g.W - 1);
+  const int32_t m = uni(tab.pm[e.off + k]);
+  const IirLdsRegs tr = fetch_iir_lds<kC>(iir, tid);
+  // 8-bit samples are requested now, their latency overlapping the table
+  // set-up below (the other types compute their phases per sample, and
+  // there the early loads only add register pressure)
   Tin fv[kC];
+  if constexpr (PhaseLut<Tin>::kOn) {
 #pragma unroll
-  for (int i = 0; i < kC; i++) fv[i] = f[(int64_t)min(y0 + i, g.H - 1) * g.pitch + xc];
+    for (int i = 0; i < kC; i++) fv[i] = f[(int64_t)min(y0 + i, g.H - 1) * g.pitch + xc];
+  }
+  const Freq fq = make_freq(m, e.qfix, e.alpha_turn);
+  if constexpr (PhaseLut<Tin>::kOn) {
+    build_lut(lut, m, e.qfix, e.alpha_turn, tid, kHThreads);
+    if (tid == 0) lut[256] = make_float2(0.f, 0.f);
+    // one workgroup per pair also leaves the table for the horizontal pass
+    if (cbx == 0) glut[(size_t)kl * 256 + tid] = lut[tid];
+  }
+  store_iir_lds(L, tr, tid);
+  __syncthreads();
+  const float a1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
+  cfloat_p Apow = as_const(iir + (kC == kCSmall ? kIirHSmall : kIirHLarge) + iir_h_apow(kC));
+  if constexpr (!PhaseLut<Tin>::kOn) {
+#pragma unroll
+    for (int i = 0; i < kC; i++) fv[i] = f[(int64_t)min(y0 + i, g.H - 1) * g.pitch + xc];
+  }
   float4 zv[kC];
 #pragma unroll
-  for (int i = 0; i < kC; i++)
-    zv[i] = (col && y0 + i < g.H) ? planes_any<Tin>(fv[i], lut, m, q, at, g.center) : f4(0.f);
+  for (int i = 0; i < kC; i++) {
+    const bool in = col && y0 + i < g.H;
+    if constexpr (PhaseLut<Tin>::kOn) {
+      const float2 cs = lut[in ? (int)fv[i] : 256];
+      const float d = fval(fv[i]) - g.center;
+      zv[i] = make_float4(d * cs.x, d * cs.y, cs.x, cs.y);
+    } else {
+      zv[i] = in ? planes<Tin>(fv[i], fq, g.center) : f4(0.f);
+    }
+  }
   group_blur<SV, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
   if (!inpos) return;
   float4 *Zk = Z + (size_t)kl * g.Hz * g.Spos;
@@ -710,19 +769,26 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
   for (int i = 0; i < kC; i++)
     if (y0 + i < g.H) Zk[z_index(g, y0 + i, p)] = zv[i];
 }
+// The bodies copy the small argument structs into locals: read through a
+// reference into memory they could alias the kernel's stores, and the
+// compiler would keep their fields in vector registers.
 template <typename Tin, int SV, int kC>
 __device__ __forceinline__ void iir_v_body(const IirArgs &a, const Blk b) {
-  iir_v_impl<Tin, SV, kC>((const Tin *)a.f, a.g, a.tab, a.st, a.iir, a.k0, a.Z, a.glut, b);
+  const Geom g = a.g;
+  const DevTables tab = a.tab;
+  const DevState st = a.st;
+  iir_v_impl<Tin, SV, kC>((const Tin *)a.f, g, tab, st, a.iir, a.k0, a.Z, a.glut, b);
 }
 template <typename Tin, int SV, int kC>
-__global__ __launch_bounds__(kHThreads, kC == kCSmall ? 2 : 1) void k_iir_v(IirArgs a) {
+__global__ __launch_bounds__(kHThreads, 2) void k_iir_v(IirArgs a) {
   iir_v_body<Tin, SV, kC>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
 }
 template <typename Tin, int SV, int kC>
-__global__ __launch_bounds__(kHThreads, kC == kCSmall ? 2 : 1) void k_iir_v_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
+__global__ __launch_bounds__(kHThreads, 2) void k_iir_v_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
                                                      int n) {
   const int i = group_find(start, n, blockIdx.x);
-  iir_v_body<Tin, SV, kC>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+  const IirArgs ai = a[i];
+  iir_v_body<Tin, SV, kC>(ai, group_blk(ai.gg, blockIdx.x - start[i]));
 }
 
 // ------------------------------------ horizontal pass + accumulate (a4, a5)
@@ -755,24 +821,35 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   const int tid = threadIdx.x;
   const int t = tid % S;
   const int grp = tid / S;
-  const OrderEntry &e = lookup(tab, st.T_used);
+  const UEntry e = uniform_entry(tab, st.T_used);
   const int kb = pg * g.hkpg;
   const int kend = min(min(kb + g.hkpg, kcount), e.K - k0);
   const int niter = kend > kb ? (kend - kb + NG - 1) / NG : 0;
   const bool finish = last && g.hgroups == 1;
   if (niter == 0 && !first && !finish) return;  // no pairs here: partial sums unchanged
   const float a1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
-  const float *Apow = iir + (kC == kCSmall ? kIirHSmall : kIirHLarge) + iir_h_apow(kC);
-  load_iir_lds<kC>(L, iir, tid);
-  __syncthreads();
+  cfloat_p Apow = as_const(iir + (kC == kCSmall ? kIirHSmall : kIirHLarge) + iir_h_apow(kC));
   const Tin *frow = f + (int64_t)y * g.pitch;
   const int x0 = t * kC;
-  float2 *mypq = spq + grp * PAD + t * (kC + 1);
-#pragma unroll
-  for (int i = 0; i < kC; i++) mypq[i] = make_float2(0.f, 0.f);
+  const int qs = 1 << g.zlog;  // position stride of the smoothed images
+  const IirLdsRegs tr = fetch_iir_lds<kC>(iir, tid);
+  // the row's samples and the first pair's smoothed images are requested
+  // before the table set-up, so that their latency overlaps it
   Tin fv[kC];
 #pragma unroll
   for (int i = 0; i < kC; i++) fv[i] = frow[min(x0 + i, g.W - 1)];
+  float4 zv[kC];
+  {
+    const int kl = kb + grp;
+    const float4 *Zr = Z + (size_t)(kl < kend ? kl : 0) * g.Hz * g.Spos + z_index(g, y, 0);
+#pragma unroll
+    for (int i = 0; i < kC; i++) zv[i] = Zr[(size_t)(i * S + t) * qs];
+  }
+  store_iir_lds(L, tr, tid);
+  __syncthreads();
+  float2 *mypq = spq + grp * PAD + t * (kC + 1);
+#pragma unroll
+  for (int i = 0; i < kC; i++) mypq[i] = make_float2(0.f, 0.f);
 
   for (int it = 0; it < niter; it++) {
     const int kl = kb + it * NG + grp;
@@ -783,11 +860,11 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
         for (int i = t; i < 256; i += S) slut[grp * 256 + i] = glut[(size_t)kl * 256 + i];
       __syncthreads();
     }
-    const float4 *Zr = Z + (size_t)(act ? kl : 0) * g.Hz * g.Spos + z_index(g, y, 0);
-    const int qs = 1 << g.zlog;  // position stride
-    float4 zv[kC];
+    if (it > 0) {
+      const float4 *Zr = Z + (size_t)(act ? kl : 0) * g.Hz * g.Spos + z_index(g, y, 0);
 #pragma unroll
-    for (int i = 0; i < kC; i++) zv[i] = Zr[(size_t)(i * S + t) * qs];
+      for (int i = 0; i < kC; i++) zv[i] = Zr[(size_t)(i * S + t) * qs];
+    }
     group_blur<S, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
     // eqs. (f1), (f2): weight by the phase at the output pixel
     if (act) {
@@ -857,7 +934,10 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
 }
 template <typename Tin, int S, int kC>
 __device__ __forceinline__ void iir_h_accum_body(const IirArgs &a, const Blk b) {
-  iir_h_accum_impl<Tin, S, kC>((const Tin *)a.f, a.out, a.g, a.tab, a.st, a.iir, a.k0, a.kcount, a.Z, a.PQ, a.first, a.last, a.glut, b);
+  const Geom g = a.g;
+  const DevTables tab = a.tab;
+  const DevState st = a.st;
+  iir_h_accum_impl<Tin, S, kC>((const Tin *)a.f, a.out, g, tab, st, a.iir, a.k0, a.kcount, a.Z, a.PQ, a.first, a.last, a.glut, b);
 }
 
 template <typename Tin, int S, int kC>
@@ -868,7 +948,8 @@ template <typename Tin, int S, int kC>
 __global__ __launch_bounds__(kHThreads, kC == kCSmall ? 2 : 1) void k_iir_h_accum_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
                                                      int n) {
   const int i = group_find(start, n, blockIdx.x);
-  iir_h_accum_body<Tin, S, kC>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+  const IirArgs ai = a[i];
+  iir_h_accum_body<Tin, S, kC>(ai, group_blk(ai.gg, blockIdx.x - start[i]));
 }
 
 // ------------------------------------------------ sum of the pair groups (a5)
@@ -1078,26 +1159,22 @@ static bool launch_h_any(hipStream_t s, int S, int cC, const IirArgs *one, const
   return cC == kCSmall ? launch_h_S<Tin, kCSmall>(s, S, one, arr, start, n, total)
                        : launch_h_S<Tin, kCLarge>(s, S, one, arr, start, n, total);
 }
-// Columns taller than kCSmall * kHThreads use the long chunk (then always a
-// full workgroup per column).
+// The vertical pass always runs kCLarge rows per thread (half the scan work
+// per pixel of the short chunk).
 template <typename Tin>
 static bool launch_v_any(hipStream_t s, int S, int cV, const IirArgs *one, const IirArgs *arr, const int *start,
                          int n, int total) {
-  if (cV == kCLarge) {
-    if (S != kHThreads) return false;
-    launch_v<Tin, kHThreads, kCLarge>(s, one, arr, start, n, total);
-    return true;
-  }
+  if (cV != kCLarge) return false;
   switch (S) {
-    case 1: launch_v<Tin, 1, kCSmall>(s, one, arr, start, n, total); return true;
-    case 2: launch_v<Tin, 2, kCSmall>(s, one, arr, start, n, total); return true;
-    case 4: launch_v<Tin, 4, kCSmall>(s, one, arr, start, n, total); return true;
-    case 8: launch_v<Tin, 8, kCSmall>(s, one, arr, start, n, total); return true;
-    case 16: launch_v<Tin, 16, kCSmall>(s, one, arr, start, n, total); return true;
-    case 32: launch_v<Tin, 32, kCSmall>(s, one, arr, start, n, total); return true;
-    case 64: launch_v<Tin, 64, kCSmall>(s, one, arr, start, n, total); return true;
-    case 128: launch_v<Tin, 128, kCSmall>(s, one, arr, start, n, total); return true;
-    case 256: launch_v<Tin, 256, kCSmall>(s, one, arr, start, n, total); return true;
+    case 1: launch_v<Tin, 1, kCLarge>(s, one, arr, start, n, total); return true;
+    case 2: launch_v<Tin, 2, kCLarge>(s, one, arr, start, n, total); return true;
+    case 4: launch_v<Tin, 4, kCLarge>(s, one, arr, start, n, total); return true;
+    case 8: launch_v<Tin, 8, kCLarge>(s, one, arr, start, n, total); return true;
+    case 16: launch_v<Tin, 16, kCLarge>(s, one, arr, start, n, total); return true;
+    case 32: launch_v<Tin, 32, kCLarge>(s, one, arr, start, n, total); return true;
+    case 64: launch_v<Tin, 64, kCLarge>(s, one, arr, start, n, total); return true;
+    case 128: launch_v<Tin, 128, kCLarge>(s, one, arr, start, n, total); return true;
+    case 256: launch_v<Tin, 256, kCLarge>(s, one, arr, start, n, total); return true;
     default: return false;
   }
 }

@@ -23,6 +23,30 @@ __device__ __forceinline__ const OrderEntry &lookup(const DevTables &tab, const 
   return tab.ent[tab.idx_of_T[T]];
 }
 
+// The order entry of the device's T in registers that are the same in every
+// lane.  T and the tables are the same for the whole launch; read through
+// pointers that come from memory (grouped launches) the compiler would
+// otherwise treat them as per-lane values.
+struct UEntry {
+  int32_t K, off;
+  uint64_t qfix;
+  double alpha_turn;
+};
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ uint64_t uni(uint64_t v) {
+  return ((uint64_t)(uint32_t)uni((int32_t)(v >> 32)) << 32) | (uint32_t)uni((int32_t)(uint32_t)v);
+}
+__device__ __forceinline__ UEntry uniform_entry(const DevTables &tab, const int32_t *Tu) {
+  const OrderEntry &e = lookup(tab, Tu);
+  UEntry u;
+  u.K = uni(e.K);
+  u.off = uni(e.off);
+  u.qfix = uni(e.qfix);
+  u.alpha_turn = __longlong_as_double((long long)uni((uint64_t)__double_as_longlong(e.alpha_turn)));
+  return u;
+}
+
 // ------------------------------------------------------- phase generation
 // Turn (fraction of 2 pi) of the angle m * alpha * v, as an unsigned 32-bit
 // fixed-point number.  For integer v the turn is reduced exactly modulo 1 in
