@@ -274,6 +274,15 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   ip.KC = (int)std::min<size_t>(std::min<size_t>(kc, (size_t)ip.tab.K_max), 65535);
   g.hgroups = 1;
   g.hkpg = ip.KC;
+  {
+    // vertical pass: pairs per workgroup for about one round of workgroups
+    const int ncb = (g.Spos + kHThreads / g.vS - 1) / (kHThreads / g.vS);
+    const int gx = 8 * ((ncb + 7) / 8);
+    int target = kVWorkgroups;
+    if (const char *w = std::getenv("BF_V_WG")) target = std::max(1, std::atoi(w));
+    const int groups = std::max(1, std::min(ip.KC, (target + gx - 1) / gx));
+    g.vppw = (ip.KC + groups - 1) / groups;
+  }
   if (!is_toeplitz(variant)) {
     // horizontal pass: split the pairs of a launch over enough rows of
     // workgroups to fill the GPU, each group a whole number of the NG pairs a

@@ -42,6 +42,7 @@ struct Geom {
   int cC;             // pixels per thread in the horizontal pass (kCSmall or kCLarge)
   int Spos;           // S * cC positions per padded row
   int vS, vC;         // vertical pass: threads per column (power of two), rows per thread
+  int vppw;           // vertical pass: pairs per workgroup (one after another)
   // smoothed images of the recursive path, stored in tiles of zth = 2^zlog
   // rows: element (y, p) at ((y >> zlog) Spos + p) zth + (y mod zth), Hz rows
   // per pair (H rounded up to zth).  zth = 8 / (columns per vertical

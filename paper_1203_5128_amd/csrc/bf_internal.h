@@ -22,6 +22,10 @@ constexpr int kHThreads = 256;
 // Short images split their pairs into groups to get there; taller ones keep
 // one group (the partial sums and their reduction cost more than they gain).
 constexpr int kHWorkgroups = 512;
+// Workgroups the vertical pass aims for: one round of resident workgroups
+// (two per CU); each takes several pairs of its columns one after another,
+// so that its set-up (constants, input samples) is paid once.
+constexpr int kVWorkgroups = 512;
 // Largest supported width and height of the recursive path: one row (column)
 // group of kHThreads threads.
 constexpr int kMaxWidth = kCLarge * kHThreads;

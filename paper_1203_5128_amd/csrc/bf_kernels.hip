@@ -559,6 +559,16 @@ __device__ __forceinline__ void scan_down(float4 v[3], const float *__restrict__
 // a uniform address become scalar loads whatever the pointer's origin.
 typedef const __attribute__((address_space(4))) float *cfloat_p;
 __device__ __forceinline__ cfloat_p as_const(const float *p) { return (cfloat_p)p; }
+// r = M u for M a power of A read from constant memory (first row (m00, 0, 0))
+__device__ __forceinline__ void apow_mul_c(cfloat_p M, const float4 u[3], float4 r[3]) {
+  r[0] = make_float4(M[0] * u[0].x, M[0] * u[0].y, M[0] * u[0].z, M[0] * u[0].w);
+#pragma unroll
+  for (int i = 1; i < 3; i++) {
+    float4 a = make_float4(M[3 * i] * u[0].x, M[3 * i] * u[0].y, M[3 * i] * u[0].z, M[3 * i] * u[0].w);
+    a = fma4(M[3 * i + 1], u[1], a);
+    r[i] = fma4(M[3 * i + 2], u[2], a);
+  }
+}
 
 __device__ __forceinline__ void row1_acc(cfloat_p M, const float4 u[3], float4 &z) {
   z = fma4(M[3], u[0], z);
@@ -646,9 +656,23 @@ __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, fl
     apow_acc(sA + 9 * ls, Kc, exc);
     if (t == S - 1) apow_acc(waveM, Kc, inc);
   }
-  // true causal outputs
+  // true causal outputs.  In blocks of 16 samples: block b takes the carry
+  // A^(16 b) exc, so that only the w rows of A^1..A^16 and A^16 itself are
+  // needed (they stay in scalar registers)
+  {
+    float4 cb[3] = {exc[0], exc[1], exc[2]};
 #pragma unroll
-  for (int i = 0; i < kC; i++) row1_acc(Apow + 9 * (i + 1), exc, zv[i]);
+    for (int b0 = 0; b0 < kC; b0 += 16) {
+      if (b0 > 0) {
+        float4 nb[3];
+        apow_mul_c(Apow + 9 * 16, cb, nb);
+#pragma unroll
+        for (int r = 0; r < 3; r++) cb[r] = nb[r];
+      }
+#pragma unroll
+      for (int j = 0; j < (kC < 16 ? kC : 16); j++) row1_acc(Apow + 9 * (j + 1), cb, zv[b0 + j]);
+    }
+  }
   // zero extension beyond the padded end
   float4 Eb[3] = {f4(0.f), f4(0.f), f4(0.f)};
   if (t == S - 1) matvec3(L.Mts, inc, Eb);
@@ -687,8 +711,22 @@ __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, fl
 #pragma unroll
     for (int r = 0; r < 3; r++) ein[r] = Eb[r];
   }
+  // the anticausal corrections in the same blocks of 16, from the end
+  {
+    float4 cb[3] = {ein[0], ein[1], ein[2]};
 #pragma unroll
-  for (int i = 0; i < kC; i++) row1_acc(Apow + 9 * (kC - i), ein, zv[i]);
+    for (int b1 = kC; b1 > 0; b1 -= 16) {
+      if (b1 < kC) {
+        float4 nb[3];
+        apow_mul_c(Apow + 9 * 16, cb, nb);
+#pragma unroll
+        for (int r = 0; r < 3; r++) cb[r] = nb[r];
+      }
+      constexpr int n = kC < 16 ? kC : 16;
+#pragma unroll
+      for (int j = 0; j < n; j++) row1_acc(Apow + 9 * (n - j), cb, zv[b1 - n + j]);
+    }
+  }
 }
 
 // ------------------------------------------------ vertical pass (a3, a4)
@@ -698,18 +736,21 @@ __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, fl
 // integrands, a3), smoothed down the column and written once.  Padding
 // columns (positions past the image width) are written as zeros.
 template <typename Tin, int SV, int kC>
-__device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, float4 *__restrict__ Z, float2 *__restrict__ glut, const Blk b) {
+__device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, int kcount, float4 *__restrict__ Z, float2 *__restrict__ glut, const Blk b) {
   constexpr int NG = kHThreads / SV;
   constexpr int NW = SV > 64 ? SV / 64 : 1;
+  constexpr bool kLut = PhaseLut<Tin>::kOn;
   __shared__ float4 xw[NG][NW][3];
   __shared__ IirLds L;
-  // 8-bit inputs: cos/sin per intensity, and a zero entry for the samples
-  // outside the image
-  __shared__ float2 lut[PhaseLut<Tin>::kOn ? 257 : 1];
+  // 8-bit inputs: cos/sin per intensity and a zero entry for the samples
+  // outside the image, double-buffered over the workgroup's pairs
+  __shared__ float2 lut[kLut ? 2 * 257 : 1];
+  // each thread's samples, kept for the workgroup's later pairs
+  constexpr int kQ = kC * (int)sizeof(Tin) / 16;  // 16-byte words per thread
+  __shared__ uint4 fs[kHThreads * kQ];
   const int tid = threadIdx.x;
   const int t = tid % SV;
   const int grp = tid / SV;
-  const int kl = b.y;
   // column blocks in XCD order: the workgroups whose columns share the lines
   // of a Z row run on one XCD, whose L2 merges their partial-line writes
   const int ncb = (g.Spos + NG - 1) / NG;
@@ -717,57 +758,76 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
   const int cbx = (b.x & 7) * per + (b.x >> 3);
   if (cbx >= ncb) return;  // the whole workgroup: past the last column block
   const UEntry e = uniform_entry(tab, st.T_used);
-  const int k = k0 + kl;
-  if (k >= e.K) return;  // the whole workgroup: pair not kept for this image's T
+  // this workgroup's pairs: launch-local [kb, kend)
+  const int kb = b.y * g.vppw;
+  const int kend = min(min(kb + g.vppw, kcount), e.K - k0);
+  if (kb >= kend) return;  // the whole workgroup: no pair kept for this image's T
   const int p = cbx * NG + grp;
   const bool inpos = p < g.Spos;
   const int x = inpos ? (p & (g.S - 1)) * g.cC + (p >> g.logS) : 0;
   const bool col = inpos && x < g.W;  // a column of the image (else zeros)
   const int y0 = t * kC;
   const int xc = min(x, g.W - 1);
-  const int32_t m = uni(tab.pm[e.off + k]);
+  int32_t m = const_load(tab.pm + e.off + k0 + kb);
   const IirLdsRegs tr = fetch_iir_lds<kC>(iir, tid);
-  // 8-bit samples are requested now, their latency overlapping the table
-  // set-up below (the other types compute their phases per sample, and
-  // there the early loads only add register pressure)
-  Tin fv[kC];
-  if constexpr (PhaseLut<Tin>::kOn) {
+  // this thread's samples, requested before the table set-up and kept in its
+  // own LDS slot for all the workgroup's pairs
+  {
+    union { Tin v[kC]; uint4 q[kQ]; } u;
 #pragma unroll
-    for (int i = 0; i < kC; i++) fv[i] = f[(int64_t)min(y0 + i, g.H - 1) * g.pitch + xc];
+    for (int i = 0; i < kC; i++) u.v[i] = f[(int64_t)min(y0 + i, g.H - 1) * g.pitch + xc];
+    store_iir_lds(L, tr, tid);
+#pragma unroll
+    for (int j = 0; j < kQ; j++) fs[tid * kQ + j] = u.q[j];
   }
-  const Freq fq = make_freq(m, e.qfix, e.alpha_turn);
-  if constexpr (PhaseLut<Tin>::kOn) {
-    build_lut(lut, m, e.qfix, e.alpha_turn, tid, kHThreads);
-    if (tid == 0) lut[256] = make_float2(0.f, 0.f);
-    // one workgroup per pair also leaves the table for the horizontal pass
-    if (cbx == 0) glut[(size_t)kl * 256 + tid] = lut[tid];
-  }
-  store_iir_lds(L, tr, tid);
-  __syncthreads();
   const float a1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
   cfloat_p Apow = as_const(iir + (kC == kCSmall ? kIirHSmall : kIirHLarge) + iir_h_apow(kC));
-  if constexpr (!PhaseLut<Tin>::kOn) {
+  for (int kl = kb; kl < kend; kl++) {
+    const int it = kl - kb;
+    float2 *lt = lut + (it & 1) * 257;
+    if constexpr (kLut) {
+      // the other buffer was last read before the previous pair's barrier
+      build_lut(lt, m, e.qfix, e.alpha_turn, tid, kHThreads);
+      if (tid == 0) lt[256] = make_float2(0.f, 0.f);
+      // one workgroup per pair also leaves the table for the horizontal pass
+      if (cbx == 0) glut[(size_t)kl * 256 + tid] = lt[tid];
+      __syncthreads();
+    } else if (it == 0) {
+      __syncthreads();  // the filter constants
+    }
+    const Freq fq = make_freq(m, e.qfix, e.alpha_turn);
+    if (kl + 1 < kend) m = const_load(tab.pm + e.off + k0 + kl + 1);
+    Tin fv[kC];
+    {
+      union { Tin v[kC]; uint4 q[kQ]; } u;
 #pragma unroll
-    for (int i = 0; i < kC; i++) fv[i] = f[(int64_t)min(y0 + i, g.H - 1) * g.pitch + xc];
-  }
-  float4 zv[kC];
+      for (int j = 0; j < kQ; j++) u.q[j] = fs[tid * kQ + j];
 #pragma unroll
-  for (int i = 0; i < kC; i++) {
-    const bool in = col && y0 + i < g.H;
-    if constexpr (PhaseLut<Tin>::kOn) {
-      const float2 cs = lut[in ? (int)fv[i] : 256];
-      const float d = fval(fv[i]) - g.center;
-      zv[i] = make_float4(d * cs.x, d * cs.y, cs.x, cs.y);
-    } else {
-      zv[i] = in ? planes<Tin>(fv[i], fq, g.center) : f4(0.f);
+      for (int i = 0; i < kC; i++) fv[i] = u.v[i];
+    }
+    float4 zv[kC];
+#pragma unroll
+    for (int i = 0; i < kC; i++) {
+      const bool in = col && y0 + i < g.H;
+      if constexpr (kLut) {
+        const float2 cs = lt[in ? (int)fv[i] : 256];
+        const float d = fval(fv[i]) - g.center;
+        zv[i] = make_float4(d * cs.x, d * cs.y, cs.x, cs.y);
+      } else {
+        zv[i] = in ? planes<Tin>(fv[i], fq, g.center) : f4(0.f);
+      }
+    }
+    group_blur<SV, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
+    if (inpos) {
+      // y0 is a multiple of the tile height: row y0 + i sits at the thread's
+      // first row plus an offset that is the same in every lane
+      float4 *Zt = Z + (size_t)kl * g.Hz * g.Spos + z_index(g, y0, p);
+      const int zm = (1 << g.zlog) - 1;
+#pragma unroll
+      for (int i = 0; i < kC; i++)
+        if (y0 + i < g.H) Zt[(size_t)(i >> g.zlog) * (g.Spos << g.zlog) + (i & zm)] = zv[i];
     }
   }
-  group_blur<SV, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
-  if (!inpos) return;
-  float4 *Zk = Z + (size_t)kl * g.Hz * g.Spos;
-#pragma unroll
-  for (int i = 0; i < kC; i++)
-    if (y0 + i < g.H) Zk[z_index(g, y0 + i, p)] = zv[i];
 }
 // The bodies copy the small argument structs into locals: read through a
 // reference into memory they could alias the kernel's stores, and the
@@ -777,7 +837,7 @@ __device__ __forceinline__ void iir_v_body(const IirArgs &a, const Blk b) {
   const Geom g = a.g;
   const DevTables tab = a.tab;
   const DevState st = a.st;
-  iir_v_impl<Tin, SV, kC>((const Tin *)a.f, g, tab, st, a.iir, a.k0, a.Z, a.glut, b);
+  iir_v_impl<Tin, SV, kC>((const Tin *)a.f, g, tab, st, a.iir, a.k0, a.kcount, a.Z, a.glut, b);
 }
 template <typename Tin, int SV, int kC>
 __global__ __launch_bounds__(kHThreads, 2) void k_iir_v(IirArgs a) {
@@ -1095,7 +1155,7 @@ void iir_args(const void *f, float *out, const Geom &g, DevTables tab, DevState 
   a[1] = base;
   const int ng = kHThreads / g.vS;  // columns per vertical workgroup
   const int per = ((g.Spos + ng - 1) / ng + 7) / 8;
-  a[0].gg = GroupGrid{8 * per, kcount, 1};  // vertical (column blocks in XCD order)
+  a[0].gg = GroupGrid{8 * per, (kcount + g.vppw - 1) / g.vppw, 1};  // vertical (column blocks in XCD order)
   a[1].gg = GroupGrid{8 * ((g.H + 7) / 8), g.hgroups, 1};  // horizontal + combine (rows in XCD order)
   const int64_t npx = (int64_t)g.H * g.W;
   const int nfin = (last && g.hgroups > 1) ? (int)((npx + 255) / 256) : 0;
@@ -1180,7 +1240,7 @@ static bool launch_v_any(hipStream_t s, int S, int cV, const IirArgs *one, const
 }
 
 static bool iir_geom_ok(const Geom &g, int kcount) {
-  return g.hgroups >= 1 && g.hgroups <= 65535 && g.hkpg >= 1 && (int64_t)g.hgroups * g.hkpg >= kcount &&
+  return g.hgroups >= 1 && g.hgroups <= 65535 && g.vppw >= 1 && g.hkpg >= 1 && (int64_t)g.hgroups * g.hkpg >= kcount &&
          kcount >= 1 && kcount <= 65535 && g.vS >= 1 && g.vS <= kHThreads && (int64_t)g.vS * g.vC >= g.H &&
          (int64_t)g.S * g.cC >= g.W && g.Spos == g.S * g.cC && g.zlog >= 0 && g.zlog <= 3 && g.Hz >= g.H && g.Hz % (1 << g.zlog) == 0;
 }

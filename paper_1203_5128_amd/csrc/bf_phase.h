@@ -37,13 +37,21 @@ __device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_
 __device__ __forceinline__ uint64_t uni(uint64_t v) {
   return ((uint64_t)(uint32_t)uni((int32_t)(v >> 32)) << 32) | (uint32_t)uni((int32_t)(uint32_t)v);
 }
+// Tables and T are not written while a blur kernel runs, so they may be read
+// through the constant address space: scalar loads, no per-lane wait.
+template <typename T>
+__device__ __forceinline__ T const_load(const T *p) {
+  return *(const __attribute__((address_space(4))) T *)p;
+}
 __device__ __forceinline__ UEntry uniform_entry(const DevTables &tab, const int32_t *Tu) {
-  const OrderEntry &e = lookup(tab, Tu);
+  int T = const_load(Tu);
+  T = T < 0 ? 0 : (T > tab.T_cap ? tab.T_cap : T);
+  const OrderEntry *e = tab.ent + const_load(tab.idx_of_T + T);
   UEntry u;
-  u.K = uni(e.K);
-  u.off = uni(e.off);
-  u.qfix = uni(e.qfix);
-  u.alpha_turn = __longlong_as_double((long long)uni((uint64_t)__double_as_longlong(e.alpha_turn)));
+  u.K = const_load(&e->K);
+  u.off = const_load(&e->off);
+  u.qfix = const_load(&e->qfix);
+  u.alpha_turn = const_load(&e->alpha_turn);
   return u;
 }
 
