@@ -29,12 +29,14 @@
  *    other ranges sigma_r is rescaled by 255/range before the comparison.
  *  - For non-integer T (float images) the order uses ceil(T).
  *  - Where the denominator (f2) is not positive the output is the input pixel.
- *  - The paper does not name its O(1) spatial smoother.  Two operators are
- *    provided, both separable and zero-extended outside the image:
+ *  - The paper does not name its O(1) spatial smoother.  Three operators are
+ *    provided, all separable and zero-extended outside the image:
  *      FIR: taps exp(-j^2 / (2 sigma_s^2)) for |j| <= R;
  *      IIR: the recursive Gaussian of Young and van Vliet (Signal Processing
  *           44, 1995), causal pass then anticausal pass, applied to the
- *           zero-extended signal.
+ *           zero-extended signal;
+ *      BOX: the constant spatial filter of Section 4 (the comparison with
+ *           integral histograms), unit taps for |j| <= R, R its radius.
  */
 #include <math.h>
 #include <stdint.h>
@@ -204,6 +206,20 @@ static void fir_1d(const double *in, long n, double sigma, long R, double *out)
     }
 }
 
+/* BOX: out[i] = sum_{|j|<=R, 0<=i+j<n} in[i+j] */
+static void box_1d(const double *in, long n, long R, double *out)
+{
+    for (long i = 0; i < n; i++) {
+        double acc = 0.0;
+        for (long j = -R; j <= R; j++) {
+            long k = i + j;
+            if (k < 0 || k >= n) continue;
+            acc += in[k];
+        }
+        out[i] = acc;
+    }
+}
+
 /* Young & van Vliet (1995) coefficients, valid for sigma >= 0.5. */
 void orc_yvv_coefs(double sigma, double *coef /* [4]: B, b1/b0, b2/b0, b3/b0 */)
 {
@@ -250,12 +266,14 @@ static void iir_1d(const double *in, long n, const double *cf, long pad, double 
 
 #define ORC_OP_FIR 0
 #define ORC_OP_IIR 1
+#define ORC_OP_BOX 2
 
 /* 1-D operator along a strided line (used for the tests of the operators). */
 int orc_blur_1d(const double *in, long n, int op, double sigma, long R, double *out)
 {
     if (n < 1 || sigma <= 0.0) return ORC_ERR_ARG;
     if (op == ORC_OP_FIR) { fir_1d(in, n, sigma, R, out); return ORC_OK; }
+    if (op == ORC_OP_BOX) { box_1d(in, n, R, out); return ORC_OK; }
     if (op != ORC_OP_IIR || sigma < 0.5) return ORC_ERR_ARG;
     double cf[4];
     orc_yvv_coefs(sigma, cf);
@@ -273,7 +291,7 @@ int orc_blur_2d(double *img, long H, long W, int op, double sigma, long R)
 {
     if (H < 1 || W < 1 || sigma <= 0.0) return ORC_ERR_ARG;
     if (op == ORC_OP_IIR && sigma < 0.5) return ORC_ERR_ARG;
-    if (op != ORC_OP_FIR && op != ORC_OP_IIR) return ORC_ERR_ARG;
+    if (op != ORC_OP_FIR && op != ORC_OP_IIR && op != ORC_OP_BOX) return ORC_ERR_ARG;
     double cf[4] = {0, 0, 0, 0};
     long pad = 0;
     if (op == ORC_OP_IIR) { orc_yvv_coefs(sigma, cf); pad = yvv_pad(sigma); }
@@ -291,6 +309,7 @@ int orc_blur_2d(double *img, long H, long W, int op, double sigma, long R)
             for (long y = 0; y < H; y++) {
                 double *row = img + y * W;
                 if (op == ORC_OP_FIR) fir_1d(row, W, sigma, R, res);
+                else if (op == ORC_OP_BOX) box_1d(row, W, R, res);
                 else iir_1d(row, W, cf, pad, bw, by, res);
                 memcpy(row, res, sizeof(double) * W);
             }
@@ -298,6 +317,7 @@ int orc_blur_2d(double *img, long H, long W, int op, double sigma, long R)
             for (long x = 0; x < W; x++) {
                 for (long y = 0; y < H; y++) line[y] = img[y * W + x];
                 if (op == ORC_OP_FIR) fir_1d(line, H, sigma, R, res);
+                else if (op == ORC_OP_BOX) box_1d(line, H, R, res);
                 else iir_1d(line, H, cf, pad, bw, by, res);
                 for (long y = 0; y < H; y++) img[y * W + x] = res[y];
             }
@@ -394,16 +414,19 @@ int orc_algorithm2(const double *f, long H, long W, int op, double sigma_s, long
 }
 
 /* Direct evaluation of eq. (BF) at chosen pixels with the truncated range
- * kernel phi_eps and the FIR spatial kernel on the clipped square window:
+ * kernel phi_eps and the FIR (or BOX) spatial kernel on the clipped square
+ * window:
  *   out(x) = sum_y w(y) phi_eps(f(x-y) - f(x)) f(x-y) / sum_y w(y) phi_eps(...)
  * Used for sampled parity at sizes where the full expansion is too slow. */
-int orc_direct_fir_at(const double *f, long H, long W, double sigma_s, long R, int N, int M,
-                      double sigma_r, const long *ys, const long *xs, long npts, double *out)
+int orc_direct_at(const double *f, long H, long W, int op, double sigma_s, long R, int N, int M,
+                  double sigma_r, const long *ys, const long *xs, long npts, double *out)
 {
     if (H < 1 || W < 1 || R < 0 || N < 1 || M < 0 || 2 * M > N) return ORC_ERR_ARG;
+    if (op != ORC_OP_FIR && op != ORC_OP_BOX) return ORC_ERR_ARG;
     double *w1 = (double *)malloc(sizeof(double) * (2 * R + 1));
     if (!w1) return ORC_ERR_MEM;
-    for (long j = -R; j <= R; j++) w1[j + R] = exp(-(double)(j * j) / (2.0 * sigma_s * sigma_s));
+    for (long j = -R; j <= R; j++)
+        w1[j + R] = op == ORC_OP_BOX ? 1.0 : exp(-(double)(j * j) / (2.0 * sigma_s * sigma_s));
 #pragma omp parallel for schedule(dynamic)
     for (long t = 0; t < npts; t++) {
         long y0 = ys[t], x0 = xs[t];
@@ -424,4 +447,10 @@ int orc_direct_fir_at(const double *f, long H, long W, double sigma_s, long R, i
     }
     free(w1);
     return ORC_OK;
+}
+
+int orc_direct_fir_at(const double *f, long H, long W, double sigma_s, long R, int N, int M,
+                      double sigma_r, const long *ys, const long *xs, long npts, double *out)
+{
+    return orc_direct_at(f, H, W, ORC_OP_FIR, sigma_s, R, N, M, sigma_r, ys, xs, npts, out);
 }

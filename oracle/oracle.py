@@ -30,7 +30,8 @@ _LIB = os.path.join(_LIB_DIR, "liboracle.so")
 
 OP_FIR = 0
 OP_IIR = 1
-_OPS = {"fir": OP_FIR, "iir": OP_IIR, OP_FIR: OP_FIR, OP_IIR: OP_IIR}
+OP_BOX = 2
+_OPS = {"fir": OP_FIR, "iir": OP_IIR, "box": OP_BOX, OP_FIR: OP_FIR, OP_IIR: OP_IIR, OP_BOX: OP_BOX}
 
 _lib = None
 
@@ -77,6 +78,7 @@ def lib():
         L.orc_shiftable_bf.argtypes = [P, Lg, Lg, I, D, Lg, I, I, D, P, P, P, P]
         L.orc_algorithm2.argtypes = [P, Lg, Lg, I, D, Lg, D, D, D, I, D, P, P, P, P, P]
         L.orc_direct_fir_at.argtypes = [P, Lg, Lg, D, Lg, I, I, D, P, P, Lg, P]
+        L.orc_direct_at.argtypes = [P, Lg, Lg, I, D, Lg, I, I, D, P, P, Lg, P]
         _lib = L
     return _lib
 
@@ -263,6 +265,19 @@ def direct_fir_at(f, sigma_s: float, R: int, N: int, M: int, sigma_r: float, ys,
     out = np.empty(ys.size)
     _check(lib().orc_direct_fir_at(_ptr(f), H, W, float(sigma_s), int(R), int(N), int(M),
                                    float(sigma_r), _ptr(ys), _ptr(xs), ys.size, _ptr(out)))
+    return out
+
+
+def direct_box_at(f, R: int, N: int, M: int, sigma_r: float, ys, xs):
+    """Eq. (BF) evaluated directly at the given pixels with the constant
+    spatial filter of radius R (Section 4) and phi_eps."""
+    f = _f64(f)
+    H, W = f.shape
+    ys = np.ascontiguousarray(np.asarray(ys, dtype=np.int64))
+    xs = np.ascontiguousarray(np.asarray(xs, dtype=np.int64))
+    out = np.empty(ys.size)
+    _check(lib().orc_direct_at(_ptr(f), H, W, OP_BOX, 1.0, int(R), int(N), int(M), float(sigma_r),
+                               _ptr(ys), _ptr(xs), ys.size, _ptr(out)))
     return out
 
 

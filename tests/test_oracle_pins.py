@@ -222,8 +222,30 @@ def test_iir_impulse_response_is_gaussian(sigma, tol):
     assert 0.95 * sigma ** 2 < var < 1.6 * sigma ** 2
 
 
+@pytest.mark.parametrize("n,R", [(1, 0), (1, 3), (9, 2), (40, 5), (300, 20), (17, 40)])
+def test_box_operator_pins(n, R):
+    """The constant spatial filter of radius R (Section 4): the count of the
+    clipped window on a constant line, the difference of cumulative sums,
+    scipy's uniform filter times the window size, and the banded all-ones
+    matrix."""
+    from scipy.ndimage import uniform_filter1d
+    i = np.arange(n)
+    cnt = np.minimum(i + R, n - 1) - np.maximum(i - R, 0) + 1
+    assert np.array_equal(o.blur_1d(np.ones(n), "box", 1.0, R), cnt.astype(float))
+    rng = np.random.default_rng(n * 7 + R)
+    x = rng.normal(size=n)
+    c = np.concatenate([[0.0], np.cumsum(x)])
+    ref = c[np.minimum(i + R, n - 1) + 1] - c[np.maximum(i - R, 0)]
+    assert np.allclose(o.blur_1d(x, "box", 1.0, R), ref, rtol=0, atol=1e-11)
+    if 2 * R + 1 <= n:
+        uf = uniform_filter1d(x, 2 * R + 1, mode="constant", cval=0.0) * (2 * R + 1)
+        assert np.allclose(o.blur_1d(x, "box", 1.0, R), uf, rtol=0, atol=1e-11)
+    S = o.operator_matrix(n, "box", 1.0, R)
+    assert np.array_equal(S, (np.abs(i[:, None] - i[None, :]) <= R).astype(float))
+
+
 def test_operators_are_symmetric_matrices():
-    for op, s, R in (("fir", 2.0, 6), ("iir", 2.0, 0), ("iir", 5.0, 0)):
+    for op, s, R in (("fir", 2.0, 6), ("iir", 2.0, 0), ("iir", 5.0, 0), ("box", 1.0, 3)):
         S = o.operator_matrix(23, op, s, R)
         assert np.allclose(S, S.T, atol=1e-13)
 
@@ -234,7 +256,7 @@ TINY = [(1, 1, "mixed"), (1, 7, "mixed"), (7, 1, "mixed"), (7, 5, "noise"), (12,
 
 
 @pytest.mark.parametrize("H,W,kind", TINY)
-@pytest.mark.parametrize("op", ["fir", "iir"])
+@pytest.mark.parametrize("op", ["fir", "iir", "box"])
 def test_shiftable_equals_direct(H, W, kind, op):
     """The expansion of eqs. (f1)/(f2) reproduces eq. (BF) with the same
     truncated range kernel and the same spatial operator."""
@@ -251,7 +273,7 @@ def test_shiftable_equals_direct(H, W, kind, op):
     assert np.allclose(out, ref, rtol=1e-9, atol=1e-9 * 255)
 
 
-@pytest.mark.parametrize("op", ["fir", "iir"])
+@pytest.mark.parametrize("op", ["fir", "iir", "box"])
 def test_constant_image_unchanged(op):
     for v in (0.0, 17.0, 255.0):
         f = np.full((20, 17), v)
@@ -260,7 +282,7 @@ def test_constant_image_unchanged(op):
         assert np.allclose(r["out"], v, atol=1e-9)
 
 
-@pytest.mark.parametrize("op", ["fir", "iir"])
+@pytest.mark.parametrize("op", ["fir", "iir", "box"])
 def test_affine_and_reflection_invariance(op):
     f = gen_random(7, 24, 20, "u8").astype(float)
     ss, R, sr, eps = 2.0, 6, 15.0, 1e-3
@@ -277,12 +299,25 @@ def test_affine_and_reflection_invariance(op):
     assert np.allclose(ref["out"], 255.0 - base["out"], atol=1e-8 * 255)
 
 
-@pytest.mark.parametrize("op", ["fir", "iir"])
+@pytest.mark.parametrize("op", ["fir", "iir", "box"])
 def test_transpose_commutes(op):
     f = gen_random(9, 19, 26, "u8").astype(float)
     a = o.algorithm2(f, op, 2.5, 8, 20.0, 1e-3, 255.0, True)
     b = o.algorithm2(f.T.copy(), op, 2.5, 8, 20.0, 1e-3, 255.0, True)
     assert np.allclose(a["out"].T, b["out"], atol=1e-9)
+
+
+def test_box_direct_matches_expansion():
+    """Eq. (BF) evaluated directly with the box filter at sampled pixels equals
+    the expansion (Algorithm 2 with the box operator), at the paper's box
+    setting (radius 20, sigma_r = 5, eps = 0.01) on a synthetic image."""
+    f = gen_random(21, 90, 110, "u8").astype(float)
+    r = o.algorithm2(f, "box", 1.0, 20, 5.0, 1e-2, 255.0, True)
+    rng = np.random.default_rng(5)
+    ys = np.concatenate([rng.integers(0, 90, 60), [0, 89, 0, 89]])
+    xs = np.concatenate([rng.integers(0, 110, 60), [0, 109, 109, 0]])
+    d = o.direct_box_at(f, 20, r["N"], r["M"], 5.0, ys, xs)
+    assert np.allclose(r["out"][ys, xs], d, rtol=0, atol=1e-9 * 255)
 
 
 def test_error_to_gaussian_bf_shrinks():
