@@ -9,9 +9,11 @@ the host cores as the CPU baseline.
 
 Besides this plain FP32 line (`value`), the same JSON line carries the mixed
 path on the same workload (split-FP16 Toeplitz blur, its error against the
-oracle with the FIR operator) and the batched path (64 images of uneven
-sizes with per-image sigma_s, sigma_r, autotuned, one grouped graph launch per
-step, its error at sampled pixels against eq. (BF) evaluated directly).
+oracle with the FIR operator), the batched path (64 images of uneven sizes
+with per-image sigma_s, sigma_r, one grouped graph launch per step, its error
+at sampled pixels against eq. (BF) evaluated directly, and the same images
+filtered one by one for comparison), and the constant (box) spatial filter of
+Section 4 (radius 20, sigma_r 5, eps 0.01) on the same image.
 
 Prints one JSON line.  Only one GPU is supported: --gpus above 1 exits.
 """
@@ -63,7 +65,7 @@ def measured_traffic(kernel: str):
     return rec["traffic_bytes"] if sha.startswith(rec["source_sha256_prefix"]) else None
 
 
-def cpu_baseline(img, c, mixed=None, batch=None, budget_s=25.0):
+def cpu_baseline(img, c, mixed=None, batch=None, box=None, budget_s=25.0):
     """The CPU leg: the FP64 oracle timed on the main workload (Algorithm 2
     with the recursive operator, all host threads).  Its outputs, and the
     oracle values it computes afterwards (untimed) for the mixed line (whole
@@ -96,6 +98,13 @@ def cpu_baseline(img, c, mixed=None, batch=None, budget_s=25.0):
             else:
                 vals.append(oracle.direct_fir_at(g, ss, R, rep["N"], rep["M"], sr, ys, xs))
         refs["batch"] = vals
+    if box is not None:  # eq. (BF) directly with the box filter at the sampled pixels
+        ys, xs = box
+        R, sr, eps = BOX["radius"], BOX["sigma_r"], BOX["eps"]
+        T = oracle.range_T(f, R)
+        N = oracle.order(T, sr)
+        M = oracle.trunc_rule(N, sr, eps)
+        refs["box"] = dict(T=T, N=N, M=M, vals=oracle.direct_box_at(f, R, N, M, sr, ys, xs))
     return refs, base
 
 
@@ -127,6 +136,55 @@ def mixed_line(img, c, x, steps, warmup):
                 ms_per_step=round(sec * 1e3, 5), dtype="f16 hi+lo operands, f32 accumulation",
                 N=rep["N"], M=rep["M"])
     return line, out.cpu().numpy().astype(np.float64)
+
+
+BOX = dict(radius=20, sigma_r=5.0, eps=1e-2)  # the paper's box setting (Section 4)
+
+
+def box_line(img, x, steps, warmup):
+    """The constant (box) spatial filter of radius 20 with sigma_r = 5 and
+    eps = 0.01 on the same image (split-FP16 Toeplitz kernels, unit taps);
+    returns the line and the output at sampled pixels for the error check."""
+    import torch
+    from paper_1203_5128_amd import Plan, make_params
+    H, W = img.shape
+    out = torch.empty((H, W), dtype=torch.float32, device=x.device)
+    plan = Plan.create(make_params(H, W, "u8", float(BOX["radius"]), BOX["sigma_r"], BOX["eps"], BOX["radius"],
+                                   "local", blur="toeplitz_f16x2", spatial="box"))
+    _, rep = plan.filter(x, out, report=True)
+    sec = time_steps(lambda: plan.filter(x, out, report=False), steps, warmup)
+    plan.close()
+    line = dict(spatial="box", blur="toeplitz_f16x2", radius=BOX["radius"], sigma_r=BOX["sigma_r"],
+                eps=BOX["eps"], value=round(H * W / sec / 1e6, 3), unit="megapixels/sec",
+                ms_per_step=round(sec * 1e3, 5), T=rep["T"], N=rep["N"], M=rep["M"], pairs=rep["pairs"])
+    rng = np.random.default_rng(9)
+    ys = np.concatenate([rng.integers(0, H, 150), [0, H - 1, 0, H - 1]])
+    xs = np.concatenate([rng.integers(0, W, 150), [0, W - 1, W - 1, 0]])
+    return line, (ys, xs, out.cpu().numpy()[ys, xs].astype(np.float64))
+
+
+def sequential_batch(steps, warmup):
+    """The 64 images of the batch workload filtered one after another, each
+    by its own single-image plan (recursive blur): the reference for what the
+    grouped batch launch gains."""
+    import torch
+    from bfsynth import batch_images
+    from paper_1203_5128_amd import Plan, make_params
+    items = batch_images()
+    xs = [torch.from_numpy(im).to("cuda:0") for im, _, _ in items]
+    outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in xs]
+    plans = [Plan.create(make_params(im.shape[0], im.shape[1], "u8", sigma_s=ss, sigma_r=sr, eps=1e-3,
+                                     blur="iir_f32")) for im, ss, sr in items]
+
+    def step():
+        for pl, x, o in zip(plans, xs, outs):
+            pl.filter(x, o, report=False)
+    sec = time_steps(step, steps, warmup)
+    for pl in plans:
+        pl.close()
+    px = sum(im.size for im, _, _ in items)
+    return dict(blur="iir_f32", images=len(items), value=round(px / sec / 1e6, 3), unit="megapixels/sec",
+                ms_per_step=round(sec * 1e3, 5)), [o.cpu() for o in outs]
 
 
 def batched_line(blur, steps, warmup):
@@ -172,8 +230,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="plain FP32 line only (no mixed/batched lines)")
-    ap.add_argument("--lines", default="mixed,batch",
-                    help="extra lines besides the plain one: any of mixed, batch (empty: none)")
+    ap.add_argument("--lines", default="mixed,batch,box",
+                    help="extra lines besides the plain one: any of mixed, batch, box (empty: none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB mebibytes (a kernel of known "
                          "traffic against which the HBM byte counters are scaled)")
@@ -273,10 +331,18 @@ def main():
             batches["mixed"][0]["value"] / batches["plain"][0]["value"], 3)
         result["batched"]["speedup_auto_vs_plain"] = round(
             batches["auto"][0]["value"] / batches["plain"][0]["value"], 3)
+        seq, seq_outs = sequential_batch(max(2, bsteps // 4), 1)
+        result["batched"]["sequential"] = seq
+        result["batched"]["speedup_batched_vs_sequential"] = round(batches["plain"][0]["value"] / seq["value"], 3)
+    box = None
+    if "box" in lines:
+        box, box_out = box_line(img, x, args.steps, args.warmup)
+        result["box"] = box
     # accuracy of the timed outputs against the FP64 oracle (the CPU leg)
     if not args.no_cpu_baseline:
         samples = [smp for v in batches.values() for smp in v[1]]
-        refs, cpu = cpu_baseline(img, c, mixed=mixed, batch=[(it, r, p) for it, r, p, _ in samples] or None)
+        refs, cpu = cpu_baseline(img, c, mixed=mixed, batch=[(it, r, p) for it, r, p, _ in samples] or None,
+                                 box=(box_out[0], box_out[1]) if box is not None else None)
         ref = refs["iir"]
         err = np.abs(got - ref["out"])
         result["max_err"] = float(err.max())
@@ -294,6 +360,11 @@ def main():
                 worst = max(errs[i0:i0 + len(smp)])
                 i0 += len(smp)
                 line.update(sampled_max_err=worst, err_ok=bool(worst <= 2e-3))
+        if box is not None:
+            rb = refs["box"]
+            e3 = np.abs(box_out[2] - rb["vals"])
+            box.update(sampled_max_err=float(e3.max()),
+                       err_ok=bool(e3.max() <= 2e-3 and (rb["T"], rb["N"], rb["M"]) == (box["T"], box["N"], box["M"])))
     print(json.dumps(result), flush=True)
 
 

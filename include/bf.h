@@ -68,6 +68,15 @@ typedef enum {
   BF_BLUR_TOEPLITZ_BF16X2 = 5  /* same FIR, BF16 hi+lo split operands, FP32 accumulation  */
 } bf_blur;
 
+/* Spatial kernel of eq. (BF) (the filter smoothed by step 3). */
+typedef enum {
+  BF_SPATIAL_GAUSSIAN = 0, /* Gaussian of sigma_s (the recursive or the FIR form above)  */
+  BF_SPATIAL_BOX = 1       /* constant filter over the (2R+1)^2 square (Section 4, the
+                              comparison with integral histograms); R = radius, or
+                              round(sigma_s) when radius is 0.  Toeplitz variants only
+                              (unit taps); BF_BLUR_AUTO takes BF_BLUR_TOEPLITZ_F16X2. */
+} bf_spatial;
+
 typedef struct {
   int32_t height, width;   /* >= 1                                                   */
   int64_t in_pitch;        /* elements between input rows; 0 => width               */
@@ -83,6 +92,7 @@ typedef struct {
                               and f32, 65535 for u16.  Sets the T table size and
                               the sigma_r bands (given in 8-bit units) of step 4. */
   bf_blur blur;
+  bf_spatial spatial;
 } bf_params;
 
 /* Per-image result summary (filled only when requested; requesting it makes
@@ -107,7 +117,8 @@ typedef struct bf_plan_s *bf_plan_t;
  * allocated on the current device.  No image data is read.
  * Errors: BF_ERR_INVALID_ARG (bad params, n_images < 1, NULL pointers),
  * BF_ERR_UNSUPPORTED (order beyond the build limits; width or height above
- * 8192 for the recursive blur; radius above 120 for the Toeplitz blur),
+ * 8192 for the recursive blur; radius above 120 for the Toeplitz blur; the
+ * box spatial filter with the recursive blur),
  * BF_ERR_OUT_OF_MEMORY, BF_ERR_DEVICE.  On error *out is set to NULL. */
 bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out);
 

@@ -48,7 +48,7 @@ class bf_params(ctypes.Structure):
                 ("sigma_r", ctypes.c_double), ("eps", ctypes.c_double),
                 ("radius", ctypes.c_int32), ("t_mode", ctypes.c_int),
                 ("t_value", ctypes.c_double), ("value_range", ctypes.c_double),
-                ("blur", ctypes.c_int)]
+                ("blur", ctypes.c_int), ("spatial", ctypes.c_int)]
 
 
 class bf_report(ctypes.Structure):
@@ -117,8 +117,12 @@ def _check(status: int):
         raise BFError(status, bf_last_error_detail())
 
 
+SPATIALS = {"gaussian": 0, "box": 1}
+
+
 def make_params(H, W, dtype="u8", sigma_s=3.0, sigma_r=30.0, eps=1e-3, radius=0, t_mode="local",
-                t_value=0.0, value_range=0.0, blur="iir_f32", in_pitch=0, out_pitch=0) -> bf_params:
+                t_value=0.0, value_range=0.0, blur="iir_f32", in_pitch=0, out_pitch=0,
+                spatial="gaussian") -> bf_params:
     p = bf_params()
     p.height, p.width = int(H), int(W)
     p.in_pitch, p.out_pitch = int(in_pitch), int(out_pitch)
@@ -128,6 +132,7 @@ def make_params(H, W, dtype="u8", sigma_s=3.0, sigma_r=30.0, eps=1e-3, radius=0,
     p.t_mode = {"global": BF_T_GLOBAL, "local": BF_T_LOCAL}[t_mode] if isinstance(t_mode, str) else int(t_mode)
     p.t_value, p.value_range = float(t_value), float(value_range)
     p.blur = BLURS[blur] if isinstance(blur, str) else int(blur)
+    p.spatial = SPATIALS[spatial] if isinstance(spatial, str) else int(spatial)
     return p
 
 

@@ -170,7 +170,20 @@ bf_status check_params(const bf_params &p) {
   if (p.value_range < 0.0 || !std::isfinite(p.value_range))
     return fail(BF_ERR_INVALID_ARG, "value_range must be >= 0");
   if (p.blur < BF_BLUR_AUTO || p.blur > BF_BLUR_TOEPLITZ_BF16X2) return fail(BF_ERR_INVALID_ARG, "unknown blur");
+  if (p.spatial != BF_SPATIAL_GAUSSIAN && p.spatial != BF_SPATIAL_BOX)
+    return fail(BF_ERR_INVALID_ARG, "unknown spatial kernel");
+  if (p.spatial == BF_SPATIAL_BOX && p.blur == BF_BLUR_IIR_F32)
+    return fail(BF_ERR_UNSUPPORTED, "the box spatial filter runs on the Toeplitz blur variants");
   return BF_OK;
+}
+
+// Window radius R: the given radius, else ceil(3 sigma_s) for the Gaussian
+// (Section 2) and round(sigma_s) for the box filter (whose sigma_s is its
+// radius in Section 4).
+int window_radius(const bf_params &p) {
+  if (p.radius > 0) return p.radius;
+  if (p.spatial == BF_SPATIAL_BOX) return std::max(1, (int)std::lround(p.sigma_s));
+  return (int)std::ceil(3.0 * p.sigma_s);
 }
 
 bf_status upload(void **dst, const void *src, size_t bytes) {
@@ -196,7 +209,8 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   ip.range = p.value_range > 0.0 ? p.value_range : full;
   if (p.dtype == BF_U8 && ip.range > 255.0) return fail(BF_ERR_INVALID_ARG, "value_range above 255 for u8");
   if (p.dtype == BF_U16 && ip.range > 65535.0) return fail(BF_ERR_INVALID_ARG, "value_range above 65535 for u16");
-  ip.R = p.radius > 0 ? p.radius : (int)std::ceil(3.0 * p.sigma_s);
+  const bool box = p.spatial == BF_SPATIAL_BOX;
+  ip.R = window_radius(p);
   if (ip.R > 1024) return fail(BF_ERR_UNSUPPORTED, "radius above 1024");
   double Tg = p.t_value > 0.0 ? p.t_value : ip.range;
   double cap = std::ceil(ip.range);
@@ -205,8 +219,11 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   ip.T_cap = (int32_t)cap;
   ip.T_global = (int32_t)std::ceil(Tg);
   ip.T_global_raw = Tg;
-  int variant = kn.variant ? kn.variant : (p.blur == BF_BLUR_AUTO ? BF_BLUR_IIR_F32 : p.blur);
+  int variant = kn.variant ? kn.variant
+                           : (p.blur != BF_BLUR_AUTO ? p.blur : (box ? BF_BLUR_TOEPLITZ_F16X2 : BF_BLUR_IIR_F32));
   ip.variant = variant;
+  if (box && !is_toeplitz(variant))
+    return fail(BF_ERR_UNSUPPORTED, "the box spatial filter runs on the Toeplitz blur variants");
   if (!is_toeplitz(variant) && (p.width > kMaxWidth || p.height > kMaxWidth))
     return fail(BF_ERR_UNSUPPORTED, "width or height above 8192 for the recursive blur");
   if (is_toeplitz(variant) && !toeplitz_shape(variant, ip.R, p.height, kn.lds_kb, ip.tc))
@@ -216,7 +233,8 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   std::vector<float> iir, taps;
   if (is_toeplitz(variant)) {
     std::vector<double> t;
-    build_fir_taps(p.sigma_s, ip.R, t);
+    if (box) t.assign(2 * ip.R + 1, 1.0);  // the constant filter: unit taps
+    else build_fir_taps(p.sigma_s, ip.R, t);
     taps.assign(t.begin(), t.end());
   } else if (!build_iir_consts(p.sigma_s, iir, err)) {
     return fail(BF_ERR_INVALID_ARG, err);
@@ -996,8 +1014,9 @@ std::string tune_key(const bf_params &p) {
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
     std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "%s|d%d|%dx%d|ss%.9g|sr%.9g|e%.9g|R%d|t%d|tv%.9g|vr%.9g", arch, (int)p.dtype,
-                p.height, p.width, p.sigma_s, p.sigma_r, p.eps, p.radius, (int)p.t_mode, p.t_value, p.value_range);
+  std::snprintf(buf, sizeof(buf), "%s|d%d|%dx%d|ss%.9g|sr%.9g|e%.9g|R%d|t%d|tv%.9g|vr%.9g|k%d", arch, (int)p.dtype,
+                p.height, p.width, p.sigma_s, p.sigma_r, p.eps, p.radius, (int)p.t_mode, p.t_value, p.value_range,
+                (int)p.spatial);
   return buf;
 }
 
@@ -1077,8 +1096,8 @@ bf_status autotune(const bf_params &p, Knobs &best) {
     }
   }
   std::vector<Knobs> cand;
-  const int R = p.radius > 0 ? p.radius : (int)std::ceil(3.0 * p.sigma_s);
-  if (p.width <= kMaxWidth && p.sigma_s >= 0.5) {
+  const int R = window_radius(p);
+  if (p.width <= kMaxWidth && p.height <= kMaxWidth && p.sigma_s >= 0.5 && p.spatial != BF_SPATIAL_BOX) {
     cand.push_back(Knobs{BF_BLUR_IIR_F32, kCSmall, 0});
     if (p.width > kCSmall) cand.push_back(Knobs{BF_BLUR_IIR_F32, kCLarge, 0});
   }
@@ -1185,8 +1204,11 @@ void autotune_batch(const bf_params *params, int n, std::vector<Knobs> &kn) {
     bool differs = false, ok = true;
     for (int i = 0; i < n; i++) {
       if (params[i].blur != BF_BLUR_AUTO || kn[i].variant == v) continue;
-      const int R = params[i].radius > 0 ? params[i].radius : (int)std::ceil(3.0 * params[i].sigma_s);
-      const bool fits = v == BF_BLUR_TOEPLITZ_F16X2 ? R <= 120 : (params[i].width <= kMaxWidth && params[i].sigma_s >= 0.5);
+      const int R = window_radius(params[i]);
+      const bool fits = v == BF_BLUR_TOEPLITZ_F16X2
+                            ? R <= 120
+                            : (params[i].width <= kMaxWidth && params[i].height <= kMaxWidth &&
+                               params[i].sigma_s >= 0.5 && params[i].spatial != BF_SPATIAL_BOX);
       if (!fits) {
         ok = false;
         break;

@@ -34,7 +34,7 @@ def test_status_strings():
 
 BAD = [dict(H=0), dict(W=0), dict(sigma_s=0.0), dict(sigma_s=-1.0), dict(sigma_r=0.0), dict(eps=0.0),
        dict(eps=1.0), dict(radius=-1), dict(t_value=-5.0), dict(value_range=-1.0), dict(dtype=7),
-       dict(blur=9), dict(t_mode=3), dict(in_pitch=3), dict(out_pitch=5)]
+       dict(blur=9), dict(t_mode=3), dict(in_pitch=3), dict(out_pitch=5), dict(spatial=7)]
 
 
 @pytest.mark.parametrize("bad", BAD)
@@ -71,3 +71,13 @@ def test_toeplitz_radius_limits_rejected_without_device(blur, R, ok):
     st = bf.lib().bf_plan(ctypes.byref(p), 1, ctypes.byref(h))
     assert st == bf.BF_ERR_UNSUPPORTED and h.value is None
     assert "radius" in bf.bf_last_error_detail()
+
+
+def test_box_spatial_filter_needs_a_toeplitz_variant():
+    """The constant (box) spatial filter runs on the Toeplitz kernels with unit
+    taps; asking for it with the recursive Gaussian is refused up front."""
+    p = bf.make_params(16, 16, "u8", sigma_s=3.0, sigma_r=20.0, radius=3, blur="iir_f32", spatial="box")
+    h = ctypes.c_void_p(123)
+    st = bf.lib().bf_plan(ctypes.byref(p), 1, ctypes.byref(h))
+    assert st == bf.BF_ERR_UNSUPPORTED and h.value is None
+    assert "box" in bf.bf_last_error_detail()
