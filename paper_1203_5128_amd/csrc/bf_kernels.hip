@@ -740,13 +740,19 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
   constexpr int NG = kHThreads / SV;
   constexpr int NW = SV > 64 ? SV / 64 : 1;
   constexpr bool kLut = PhaseLut<Tin>::kOn;
+  // tile height of the smoothed images (2^ZL rows: NG 2^ZL >= 8, the host's
+  // zlog for this column group size)
+  constexpr int ZL = NG >= 8 ? 0 : (NG == 4 ? 1 : (NG == 2 ? 2 : 3));
   __shared__ float4 xw[NG][NW][3];
   __shared__ IirLds L;
   // 8-bit inputs: cos/sin per intensity and a zero entry for the samples
   // outside the image, double-buffered over the workgroup's pairs
   __shared__ float2 lut[kLut ? 2 * 257 : 1];
-  // each thread's samples, kept for the workgroup's later pairs
-  constexpr int kQ = kC * (int)sizeof(Tin) / 16;  // 16-byte words per thread
+  // each thread's samples, kept for the workgroup's later pairs; 8-bit
+  // inputs keep the table index instead (256, the zero entry, for samples
+  // outside the image), so that no per-sample predicate stays live
+  typedef typename std::conditional<kLut, uint16_t, Tin>::type Ts;
+  constexpr int kQ = kC * (int)sizeof(Ts) / 16;  // 16-byte words per thread
   __shared__ uint4 fs[kHThreads * kQ];
   const int tid = threadIdx.x;
   const int t = tid % SV;
@@ -773,10 +779,16 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
   // this thread's samples, requested before the table set-up and kept in its
   // own LDS slot for all the workgroup's pairs
   {
-    union { Tin v[kC]; uint4 q[kQ]; } u;
+    Tin fl[kC];
 #pragma unroll
-    for (int i = 0; i < kC; i++) u.v[i] = f[(int64_t)min(y0 + i, g.H - 1) * g.pitch + xc];
+    for (int i = 0; i < kC; i++) fl[i] = f[(int64_t)min(y0 + i, g.H - 1) * g.pitch + xc];
     store_iir_lds(L, tr, tid);
+    union { Ts v[kC]; uint4 q[kQ]; } u;
+#pragma unroll
+    for (int i = 0; i < kC; i++) {
+      if constexpr (kLut) u.v[i] = (col && y0 + i < g.H) ? (Ts)fl[i] : (Ts)256;
+      else u.v[i] = fl[i];
+    }
 #pragma unroll
     for (int j = 0; j < kQ; j++) fs[tid * kQ + j] = u.q[j];
   }
@@ -797,9 +809,9 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
     }
     const Freq fq = make_freq(m, e.qfix, e.alpha_turn);
     if (kl + 1 < kend) m = const_load(tab.pm + e.off + k0 + kl + 1);
-    Tin fv[kC];
+    Ts fv[kC];
     {
-      union { Tin v[kC]; uint4 q[kQ]; } u;
+      union { Ts v[kC]; uint4 q[kQ]; } u;
 #pragma unroll
       for (int j = 0; j < kQ; j++) u.q[j] = fs[tid * kQ + j];
 #pragma unroll
@@ -808,24 +820,39 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
     float4 zv[kC];
 #pragma unroll
     for (int i = 0; i < kC; i++) {
-      const bool in = col && y0 + i < g.H;
       if constexpr (kLut) {
-        const float2 cs = lt[in ? (int)fv[i] : 256];
-        const float d = fval(fv[i]) - g.center;
+        // index 256 reads (0, 0): all four images vanish whatever d is
+        const float2 cs = lt[fv[i]];
+        const float d = (float)fv[i] - g.center;
         zv[i] = make_float4(d * cs.x, d * cs.y, cs.x, cs.y);
       } else {
-        zv[i] = in ? planes<Tin>(fv[i], fq, g.center) : f4(0.f);
+        zv[i] = (col && y0 + i < g.H) ? planes<Tin>(fv[i], fq, g.center) : f4(0.f);
       }
     }
     group_blur<SV, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
     if (inpos) {
       // y0 is a multiple of the tile height: row y0 + i sits at the thread's
       // first row plus an offset that is the same in every lane
-      float4 *Zt = Z + (size_t)kl * g.Hz * g.Spos + z_index(g, y0, p);
-      const int zm = (1 << g.zlog) - 1;
+      // rows y0 .. y0+kC-1 by tiles of 2^ZL rows: consecutive elements
+      // inside a tile, one pointer step of Spos 2^ZL elements between tiles
+      float4 *q = Z + (size_t)kl * g.Hz * g.Spos + z_index(g, y0, p);
+      const size_t step = (size_t)g.Spos << ZL;
+      if (y0 + kC <= g.H) {  // the whole chunk inside the image: no per-row test
 #pragma unroll
-      for (int i = 0; i < kC; i++)
-        if (y0 + i < g.H) Zt[(size_t)(i >> g.zlog) * (g.Spos << g.zlog) + (i & zm)] = zv[i];
+        for (int b = 0; b < (kC >> ZL); b++) {
+#pragma unroll
+          for (int r = 0; r < (1 << ZL); r++) q[r] = zv[(b << ZL) + r];
+          q += step;
+        }
+      } else {
+#pragma unroll
+        for (int b = 0; b < (kC >> ZL); b++) {
+#pragma unroll
+          for (int r = 0; r < (1 << ZL); r++)
+            if (y0 + (b << ZL) + r < g.H) q[r] = zv[(b << ZL) + r];
+          q += step;
+        }
+      }
     }
   }
 }
@@ -901,9 +928,9 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   float4 zv[kC];
   {
     const int kl = kb + grp;
-    const float4 *Zr = Z + (size_t)(kl < kend ? kl : 0) * g.Hz * g.Spos + z_index(g, y, 0);
+    const float4 *q = Z + (size_t)(kl < kend ? kl : 0) * g.Hz * g.Spos + z_index(g, y, t);
 #pragma unroll
-    for (int i = 0; i < kC; i++) zv[i] = Zr[(size_t)(i * S + t) * qs];
+    for (int i = 0; i < kC; i++, q += (size_t)S * qs) zv[i] = *q;
   }
   store_iir_lds(L, tr, tid);
   __syncthreads();
@@ -921,9 +948,9 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
       __syncthreads();
     }
     if (it > 0) {
-      const float4 *Zr = Z + (size_t)(act ? kl : 0) * g.Hz * g.Spos + z_index(g, y, 0);
+      const float4 *q = Z + (size_t)(act ? kl : 0) * g.Hz * g.Spos + z_index(g, y, t);
 #pragma unroll
-      for (int i = 0; i < kC; i++) zv[i] = Zr[(size_t)(i * S + t) * qs];
+      for (int i = 0; i < kC; i++, q += (size_t)S * qs) zv[i] = *q;
     }
     group_blur<S, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
     // eqs. (f1), (f2): weight by the phase at the output pixel
@@ -1242,7 +1269,8 @@ static bool launch_v_any(hipStream_t s, int S, int cV, const IirArgs *one, const
 static bool iir_geom_ok(const Geom &g, int kcount) {
   return g.hgroups >= 1 && g.hgroups <= 65535 && g.vppw >= 1 && g.hkpg >= 1 && (int64_t)g.hgroups * g.hkpg >= kcount &&
          kcount >= 1 && kcount <= 65535 && g.vS >= 1 && g.vS <= kHThreads && (int64_t)g.vS * g.vC >= g.H &&
-         (int64_t)g.S * g.cC >= g.W && g.Spos == g.S * g.cC && g.zlog >= 0 && g.zlog <= 3 && g.Hz >= g.H && g.Hz % (1 << g.zlog) == 0;
+         (int64_t)g.S * g.cC >= g.W && g.Spos == g.S * g.cC && g.zlog >= 0 && g.zlog <= 3 && g.Hz >= g.H && g.Hz % (1 << g.zlog) == 0 &&
+         ((kHThreads / g.vS) << g.zlog) >= 8 && (g.zlog == 0 || ((kHThreads / g.vS) << g.zlog) == 8);
 }
 
 template <typename Tin>
