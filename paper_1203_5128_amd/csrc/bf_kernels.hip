@@ -809,6 +809,11 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
     }
     const Freq fq = make_freq(m, e.qfix, e.alpha_turn);
     if (kl + 1 < kend) m = const_load(tab.pm + e.off + k0 + kl + 1);
+    // samples of this thread inside the image: the tests below stay inside
+    // the loop (the empty asm hides that nv does not change; hoisted, they
+    // would hold 32 lane masks in scalar registers)
+    int nv = col ? min(max(g.H - y0, 0), kC) : 0;
+    if constexpr (!kLut) asm volatile("" : "+v"(nv));
     Ts fv[kC];
     {
       union { Ts v[kC]; uint4 q[kQ]; } u;
@@ -826,7 +831,7 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
         const float d = (float)fv[i] - g.center;
         zv[i] = make_float4(d * cs.x, d * cs.y, cs.x, cs.y);
       } else {
-        zv[i] = (col && y0 + i < g.H) ? planes<Tin>(fv[i], fq, g.center) : f4(0.f);
+        zv[i] = i < nv ? planes<Tin>(fv[i], fq, g.center) : f4(0.f);
       }
     }
     group_blur<SV, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
@@ -961,10 +966,13 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
       const uint64_t q = e.qfix;
       const double at = e.alpha_turn;
       const float2 *lk = glut + (size_t)kl * 256;
+      // columns of this thread inside the image, kept in the loop (hoisted,
+      // the kC tests would hold lane masks in scalar registers)
+      int nx = min(max(g.W - x0, 0), kC);
+      asm volatile("" : "+v"(nx));
 #pragma unroll
       for (int i = 0; i < kC; i++) {
-        const int x = x0 + i;
-        if (x < g.W) {
+        if (i < nx) {
           float c, sn;
           if constexpr (PhaseLut<Tin>::kOn) {
             const float2 cs = kLutLds ? slut[grp * 256 + (int)fv[i]] : lk[(int)fv[i]];
