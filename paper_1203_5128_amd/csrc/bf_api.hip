@@ -142,6 +142,13 @@ DevState state_of(const ImagePlan &ip) {
   st.q_nonpos = (unsigned long long *)(b + 16);
   return st;
 }
+// d_state: the published state (24 bytes), then the range accumulators
+// (top slot at 32, kRangeSubs slots from 48).
+constexpr size_t kStateBytes = 48 + kRangeSubs * sizeof(RangeAccSlot);
+RangeAcc acc_of(const ImagePlan &ip) {
+  char *b = (char *)ip.d_state;
+  return RangeAcc{(RangeAccSlot *)(b + 32), (RangeAccSlot *)(b + 48)};
+}
 
 DevTables tables_of(const ImagePlan &ip) {
   DevTables t;
@@ -279,8 +286,11 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   if ((st = upload((void **)&ip.d_iir, iir.data(), iir.size() * 4))) return st;
   if ((st = upload((void **)&ip.d_taps, taps.data(), taps.size() * 4))) return st;
   ip.tc.taps = ip.d_taps;
-  hipError_t e = hipMalloc(&ip.d_state, 64);
-  if (e != hipSuccess) return dev_fail(e, "hipMalloc(state)");
+  {
+    // the range accumulator and counter must start at zero
+    const std::vector<unsigned char> zero(kStateBytes, 0);
+    if ((st = upload(&ip.d_state, zero.data(), zero.size()))) return st;
+  }
   // pairs per launch: bounded by a workspace budget for the smoothed images
   size_t per_pair = (size_t)g.Hz * g.Spos * sizeof(float4);
   if (is_toeplitz(variant)) per_pair = (size_t)4 * g.H * g.zpitch * (is_split(variant) ? 4 : 2);
@@ -422,9 +432,7 @@ bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out
   DevTables tab = tables_of(ip);
   hipError_t e;
   if (ip.p.t_mode == BF_T_LOCAL) {
-    e = launch_reset(s, st, 0, 0.0);
-    if (e != hipSuccess) return dev_fail(e, "reset");
-    e = launch_range(s, ip.p.dtype, d_in, g, ip.R, pl->d_rowmax, st, ip.T_cap, pl->rec);
+    e = launch_range(s, ip.p.dtype, d_in, g, ip.R, pl->d_rowmax, st, acc_of(ip), ip.T_cap, pl->rec);
     if (e != hipSuccess) return dev_fail(e, "dynamic range");
   } else {
     e = launch_reset(s, st, ip.T_global, ip.T_global_raw);
@@ -475,7 +483,8 @@ std::vector<int> starts_of(const std::vector<int> &blocks) {
 // The grouped launches of a batch: offsets of their argument arrays in the
 // packed buffer, block totals and LDS sizes.
 struct GLaunch {
-  int kind;  // 0 reset, 1 range, 2 Toeplitz stages, 3 recursive vertical, 4 recursive horizontal
+  int kind;  // 0 reset, 1 range, 2 Toeplitz stages, 3 recursive vertical, 4 recursive horizontal,
+            // 5 one-launch range
   bf_dtype dt;
   int variant;
   bool seq;
@@ -503,16 +512,43 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
     for (int i : gidx) {
       const ImagePlan &ip = pl->im[i];
       const bool loc = ip.p.t_mode == BF_T_LOCAL;
+      if (loc && range_tile_ok(ip.R)) continue;  // the tile kernel resets its own state
       ra.push_back(ResetArgs{GroupGrid{1, 1, 1}, state_of(ip), loc ? 0 : ip.T_global, loc ? 0.0 : ip.T_global_raw});
       blocks.push_back(1);
     }
-    const std::vector<int> st = starts_of(blocks);
+    if (!ra.empty()) {
+      const std::vector<int> st = starts_of(blocks);
+      GLaunch L{};
+      L.kind = 0;
+      L.cnt = (int)ra.size();
+      L.o[0] = bp.pack.add(ra);
+      L.o[1] = bp.pack.add(st);
+      L.t[0] = st.back();
+      bp.launches.push_back(L);
+    }
+  }
+  for (bf_dtype dt : {BF_U8, BF_U16, BF_F32}) {
+    std::vector<RangeTileArgs> ta;
+    std::vector<int> tb;
+    size_t lds = 0;
+    for (int i : gidx) {
+      const ImagePlan &ip = pl->im[i];
+      if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || !range_tile_ok(ip.R)) continue;
+      const GroupGrid gt = range_tile_grid(ip.g);
+      ta.push_back(RangeTileArgs{gt, d_in[i], ip.g.pitch, ip.g.H, ip.g.W, ip.R, state_of(ip), acc_of(ip), ip.T_cap});
+      tb.push_back(gt.gx * gt.gy);
+      lds = std::max(lds, range_tile_lds(ip.R));
+    }
+    if (ta.empty()) continue;
+    const std::vector<int> ts = starts_of(tb);
     GLaunch L{};
-    L.kind = 0;
-    L.cnt = (int)ra.size();
-    L.o[0] = bp.pack.add(ra);
-    L.o[1] = bp.pack.add(st);
-    L.t[0] = st.back();
+    L.kind = 5;
+    L.dt = dt;
+    L.cnt = (int)ta.size();
+    L.o[0] = bp.pack.add(ta);
+    L.o[1] = bp.pack.add(ts);
+    L.t[0] = ts.back();
+    L.lds[0] = lds;
     bp.launches.push_back(L);
   }
   for (bf_dtype dt : {BF_U8, BF_U16, BF_F32})
@@ -522,7 +558,8 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
       std::vector<int> rb, cb;
       for (int i : gidx) {
         const ImagePlan &ip = pl->im[i];
-        if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || range_col_seq(ip.R) != seq) continue;
+        if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || range_tile_ok(ip.R) || range_col_seq(ip.R) != seq)
+          continue;
         void *rm = (char *)pl->d_bws + pl->rowmax_off[i];
         const GroupGrid gr = range_row_grid(ip.g), gc = range_col_grid(ip.g, ip.R);
         ra.push_back(RowmaxArgs{gr, d_in[i], ip.g.pitch, ip.g.H, ip.g.W, ip.R, rm, state_of(ip)});
@@ -641,6 +678,11 @@ bf_status enqueue_batch(bf_plan_s *pl, int n, const void *const *d_in, float *co
     hipError_t e;
     if (L.kind == 0) {
       e = launch_reset_group(s, (const ResetArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]), L.t[0], L.cnt);
+    } else if (L.kind == 5) {
+      pl->rec.begin(BF_STAGE_RANGE, s);
+      e = launch_range_tile_group(s, L.dt, (const RangeTileArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]),
+                                  L.t[0], L.cnt, L.lds[0]);
+      pl->rec.end(BF_STAGE_RANGE, s);
     } else if (L.kind == 1) {
       pl->rec.begin(BF_STAGE_RANGE, s);
       e = launch_range_group(s, L.dt, L.seq, (const RowmaxArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]),
@@ -979,8 +1021,7 @@ bf_status bf_dynamic_range(bf_plan_t pl, const void *d_in, void *hip_stream, dou
   hipStream_t s = (hipStream_t)hip_stream;
   ImagePlan &ip = pl->im[0];
   DevState st = state_of(ip);
-  hipError_t e = launch_reset(s, st, 0, 0.0);
-  if (e == hipSuccess) e = launch_range(s, ip.p.dtype, d_in, ip.g, ip.R, pl->d_rowmax, st, ip.T_cap, pl->rec);
+  hipError_t e = launch_range(s, ip.p.dtype, d_in, ip.g, ip.R, pl->d_rowmax, st, acc_of(ip), ip.T_cap, pl->rec);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return dev_fail(e, "dynamic range");
   unsigned long long traw;

@@ -137,6 +137,29 @@ struct ColmaxArgs {
   DevState st;
   int32_t T_cap;
 };
+// Per-image accumulators of the one-launch range stage: a running maximum
+// (double bit pattern), the OR of the flags and the count of arrivals; a top
+// slot and kRangeSubs sub-slots.  All zero between calls (the last arrival
+// at each slot clears it).
+constexpr int kRangeSubs = 32;
+struct RangeAccSlot {
+  unsigned long long T;
+  int32_t flags;
+  uint32_t count;
+};
+struct RangeAcc {
+  RangeAccSlot *top;
+  RangeAccSlot *sub;  // [kRangeSubs]
+};
+struct RangeTileArgs {
+  GroupGrid gg;
+  const void *f;
+  int64_t pitch;
+  int H, W, R;
+  DevState st;
+  RangeAcc acc;
+  int32_t T_cap;
+};
 
 struct ToepVArgs {  // vertical pass: blocks (launch tile index, pair)
   GroupGrid gg;
@@ -201,13 +224,20 @@ struct StageRec {
 // ---- launch wrappers (bf_kernels.hip) ----
 hipError_t launch_fill_checker(hipStream_t s, bf_dtype dt, void *f, int H, int W, double top);
 hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw);
+// Algorithm 1 for one image, with the state reset it needs (the one-launch
+// tile kernel when range_tile_ok(R), else reset + row pass + column pass).
 hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,
-                        DevState st, int32_t T_cap, const StageRec &rec);
+                        DevState st, RangeAcc acc, int32_t T_cap, const StageRec &rec);
 // Grids of the range stage for one image and whether its column pass is the
 // sequential kind (windows taller than the LDS tile).
 GroupGrid range_row_grid(const Geom &g);
 GroupGrid range_col_grid(const Geom &g, int R);
 bool range_col_seq(int R);
+bool range_tile_ok(int R);
+GroupGrid range_tile_grid(const Geom &g);
+size_t range_tile_lds(int R);
+hipError_t launch_range_tile_group(hipStream_t s, bf_dtype dt, const RangeTileArgs *a, const int *start,
+                                   int total, int n, size_t lds);
 // Grouped launches over n images (device argument arrays and block starts).
 hipError_t launch_reset_group(hipStream_t s, const ResetArgs *a, const int *start, int total, int n);
 hipError_t launch_range_group(hipStream_t s, bf_dtype dt, bool seq, const RowmaxArgs *ra, const int *rstart,

@@ -205,7 +205,8 @@ __device__ __forceinline__ void rowmax_body(const RowmaxArgs &a, const Blk b) {
     for (int u = 0; u < 8; u++) {
       const int e = e0 + u * 64 + lane;
       const int x = xs - R + e;
-      vb[u] = (e < L && x >= 0 && x < W) ? fval(frow[x]) : -INFINITY;
+      const float raw = fval(frow[min(max(x, 0), W - 1)]);  // clamped: no branch around the load
+      vb[u] = (e < L && x >= 0 && x < W) ? raw : -INFINITY;
     }
 #pragma unroll
     for (int u = 0; u < 8; u++) {
@@ -295,7 +296,8 @@ __device__ __forceinline__ void colmax_T_body(const ColmaxArgs &a, const Blk b) 
       const int idx = base + u * 256 + tid;
       const int e = idx >> 4, c = idx & 15;
       const int y = y0 - R + e, x = x0 + c;
-      vb[u] = (idx < L * kColW && y >= 0 && y < H && x < W) ? fval(rowmax[(int64_t)y * W + x]) : -INFINITY;
+      const float raw = fval(rowmax[(int64_t)min(max(y, 0), H - 1) * W + min(x, W - 1)]);
+      vb[u] = (idx < L * kColW && y >= 0 && y < H && x < W) ? raw : -INFINITY;
     }
 #pragma unroll
     for (int u = 0; u < 4; u++) {
@@ -309,7 +311,8 @@ __device__ __forceinline__ void colmax_T_body(const ColmaxArgs &a, const Blk b) 
     for (int u = 0; u < 4; u++) {
       const int idx = u * 256 + tid;
       const int i = idx >> 4, x = x0 + (idx & 15);
-      vb[u] = (i < nb && x < W) ? fval(f[(int64_t)(y0 + i) * pitch + x]) : 0.f;
+      const float raw = fval(f[(int64_t)(y0 + min(i, nb - 1)) * pitch + min(x, W - 1)]);
+      vb[u] = (i < nb && x < W) ? raw : 0.f;
     }
 #pragma unroll
     for (int u = 0; u < 4; u++) {
@@ -406,7 +409,8 @@ __device__ __forceinline__ void colmax_T_seq_body(const ColmaxArgs &a, const Blk
 #pragma unroll
       for (int u = 0; u < 16; u++) {
         const int y = y0 - R + eb - u;
-        vb[u] = (eb - u >= 0 && y >= 0 && y < H) ? fval(rowmax[(int64_t)y * W + x]) : -INFINITY;
+        const float raw = fval(rowmax[(int64_t)min(max(y, 0), H - 1) * W + x]);
+        vb[u] = (eb - u >= 0 && y >= 0 && y < H) ? raw : -INFINITY;
       }
 #pragma unroll
       for (int u = 0; u < 16; u++) {
@@ -420,11 +424,14 @@ __device__ __forceinline__ void colmax_T_seq_body(const ColmaxArgs &a, const Blk
     float l = -INFINITY;
     ph = 0;
     for (int eb = 0; eb < L; eb += 16) {
-      float vb[16];
+      float vb[16], fv[16];
 #pragma unroll
       for (int u = 0; u < 16; u++) {
         const int y = y0 - R + eb + u;
-        vb[u] = (eb + u < L && y >= 0 && y < H) ? fval(rowmax[(int64_t)y * W + x]) : -INFINITY;
+        const float raw = fval(rowmax[(int64_t)min(max(y, 0), H - 1) * W + x]);
+        vb[u] = (eb + u < L && y >= 0 && y < H) ? raw : -INFINITY;
+        // f at output row e - 2R (clamped into the band; used only for e >= 2R)
+        fv[u] = fval(f[(int64_t)(y0 + min(max(eb + u - 2 * R, 0), nb - 1)) * pitch + x]);
       }
 #pragma unroll
       for (int u = 0; u < 16; u++) {
@@ -435,7 +442,7 @@ __device__ __forceinline__ void colmax_T_seq_body(const ColmaxArgs &a, const Blk
         if (e >= 2 * R) {
           const int i = e - 2 * R;
           const float mx = fmaxf(srb[i][lane], l);
-          const double d = (double)mx - (double)fval(f[(int64_t)(y0 + i) * pitch + x]);
+          const double d = (double)mx - (double)fv[u];
           tmax = d > tmax ? d : tmax;
         }
       }
@@ -457,6 +464,232 @@ __global__ __launch_bounds__(64) void k_colmax_T_seq_grp(const ColmaxArgs *__res
                                                          const int *__restrict__ start, int n) {
   const int i = group_find(start, n, blockIdx.x);
   colmax_T_seq_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+}
+
+// ------------------------ Algorithm 1 in one launch, for 16 <= R <= 32
+// A workgroup takes a 32 x 32 block of output pixels.  The block and its
+// R-pixel halo are staged in LDS (out-of-image samples -inf).  With a window
+// 2R+1 >= 32 the MAX-FILTER of the Appendix over a line of 32 + 2R samples x
+// has, for output j in [0, 32), the window [j, j+2R] = [j, 30] u [31, 2R] u
+// [2R+1, 2R+j]: a suffix maximum over the first 31 samples, one maximum
+// common to the whole line, and a prefix maximum over the last 31 samples
+// (van Herk's forward and backward running maxima with the segment boundary
+// placed at the line's 31st sample).  A half-wave takes one line, lane j
+// holding the three pieces for output j, and forms each with DPP scans.  The
+// row pass filters every staged row into the row maxima; the column pass
+// filters every output column of those, and T = max (out - f) (Prop. 2.1)
+// over the block is merged in two levels: into one of kRangeSubs
+// sub-accumulators (block index mod kRangeSubs), whose last arrival merges
+// it into the top accumulator, whose last arrival publishes T, the flags and
+// a zero non-positive-denominator count and clears both levels for the next
+// call.  So no reset launch precedes it, and no address takes more than a
+// few dozen atomics.
+constexpr int kTileW = 32;
+constexpr int kTileH = 32;
+constexpr int kTileMinR = 16;
+constexpr int kTileMaxR = 32;
+constexpr int kTileRS = kTileW + 2 * kTileMaxR;  // staged row stride (= 32 mod 64 banks)
+constexpr int kTileMS = kTileW + 1;              // row-maxima and centre strides
+constexpr int kStageMax = ((kTileH + 2 * kTileMaxR) * (kTileW + 2 * kTileMaxR) + 255) / 256;
+
+// LDS floats: staged block (L x kTileRS), row maxima (L x kTileMS), the raw
+// centre samples (kTileH x kTileMS).
+__host__ __device__ constexpr int tile_lds_floats(int R) {
+  return (kTileH + 2 * R) * (kTileRS + kTileMS) + kTileH * kTileMS;
+}
+
+template <typename Tin>
+__device__ __forceinline__ float tile_clean(float v) {
+  if constexpr (std::is_same<Tin, float>::value) return isfinite(v) ? v : -INFINITY;
+  return v;
+}
+
+// Max scans over each 32-lane half of the wave (lanes 0-31 and 32-63 hold
+// independent lines).  Lanes without a source keep -inf.
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ float dpp_keep(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, RM, 0xF, false));
+}
+__device__ __forceinline__ float half_prefix_max(float v) {
+  v = fmaxf(v, dpp_keep<0x111>(-INFINITY, v));        // row_shr:1
+  v = fmaxf(v, dpp_keep<0x112>(-INFINITY, v));        // row_shr:2
+  v = fmaxf(v, dpp_keep<0x114>(-INFINITY, v));        // row_shr:4
+  v = fmaxf(v, dpp_keep<0x118>(-INFINITY, v));        // row_shr:8
+  return fmaxf(v, dpp_keep<0x142, 0xA>(-INFINITY, v));  // row_bcast:15 into rows 1 and 3
+}
+__device__ __forceinline__ float half_suffix_max(float v) {
+  v = fmaxf(v, dpp_keep<0x101>(-INFINITY, v));  // row_shl:1
+  v = fmaxf(v, dpp_keep<0x102>(-INFINITY, v));  // row_shl:2
+  v = fmaxf(v, dpp_keep<0x104>(-INFINITY, v));  // row_shl:4
+  v = fmaxf(v, dpp_keep<0x108>(-INFINITY, v));  // row_shl:8
+  const float t = __shfl(v, (int)((threadIdx.x & 32) | 16));  // head of the half's upper row
+  return (threadIdx.x & 16) ? v : fmaxf(v, t);
+}
+__device__ __forceinline__ float half_max(float v) {
+  v = fmaxf(v, dpp_keep<0x128>(v, v));  // row_ror:8
+  v = fmaxf(v, dpp_keep<0x124>(v, v));  // row_ror:4
+  v = fmaxf(v, dpp_keep<0x122>(v, v));  // row_ror:2
+  v = fmaxf(v, dpp_keep<0x121>(v, v));  // row_ror:1
+  return fmaxf(v, __shfl_xor(v, 16));
+}
+
+// Merge the candidate t and flags fl into accumulator slot c; true for the
+// n-th (last) arrival, which then holds the merged values and has cleared
+// the slot.  Each step waits for the previous atomic's return value, so an
+// arrival's maximum and flags are performed before its count increment, and
+// the last arrival reads the slot (by exchange) only after its own increment
+// returned: every merged value is seen without L2 writeback fences.
+__device__ __forceinline__ bool acc_merge(RangeAccSlot *c, unsigned long long &t, int32_t &fl, uint32_t n) {
+  const unsigned long long om = atomicMax(&c->T, t);
+  const int32_t of = atomicOr(&c->flags, fl);
+  uint32_t one = 1u;
+  asm volatile("" : "+v"(one) : "v"(om), "v"(of));
+  const uint32_t done = atomicAdd(&c->count, one);
+  if (done != n - 1) return false;
+  unsigned long long z = 0ull;
+  int32_t zf = 0;
+  asm volatile("" : "+v"(z), "+v"(zf) : "v"(done));
+  t = atomicExch(&c->T, z);
+  fl = atomicExch(&c->flags, zf);
+  atomicExch(&c->count, 0u);
+  return true;
+}
+
+template <typename Tin>
+__device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Blk b) {
+  extern __shared__ float tlds[];
+  __shared__ double wmax[4];
+  const Tin *__restrict__ f = (const Tin *)a.f;
+  const int64_t pitch = a.pitch;
+  const int H = a.H, W = a.W, R = a.R;
+  const int L = kTileH + 2 * R;   // staged rows
+  const int Lc = kTileW + 2 * R;  // staged columns
+  const int nc = 2 * R - 30;      // samples [31, 2R] common to every window of a line
+  float *reg = tlds;
+  float *rm = reg + L * kTileRS;
+  float *fc = rm + L * kTileMS;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, j = lane & 31, half = lane >> 5;
+  const int x0 = b.x * kTileW, y0 = b.y * kTileH;
+
+  // stage: the block's samples in row-major order, kStageMax per thread; every
+  // lane loads from a clamped in-image address (no branch around the load, so
+  // all loads stay in flight) and masks afterwards
+  bool bad = false;
+  {
+    const int q = 256 / Lc, r = 256 - q * Lc;
+    float v[kStageMax];
+    int e = tid / Lc, c = tid - (tid / Lc) * Lc;
+#pragma unroll
+    for (int k = 0; k < kStageMax; k++) {
+      const int y = y0 - R + e, x = x0 - R + c;
+      const bool in = e < L && y >= 0 && y < H && x >= 0 && x < W;
+      const float raw = fval(f[(int64_t)min(max(y, 0), H - 1) * pitch + min(max(x, 0), W - 1)]);
+      v[k] = in ? raw : -INFINITY;
+      if (in && !isfinite(raw)) bad = true;
+      c += r;
+      e += q;
+      if (c >= Lc) { c -= Lc; e++; }
+    }
+    e = tid / Lc;
+    c = tid - e * Lc;
+#pragma unroll
+    for (int k = 0; k < kStageMax; k++) {
+      if (e < L) reg[e * kTileRS + c] = v[k];
+      const int ce = e - R, cc = c - R;
+      if (ce >= 0 && ce < kTileH && cc >= 0 && cc < kTileW) fc[ce * kTileMS + cc] = v[k];
+      c += r;
+      e += q;
+      if (c >= Lc) { c -= Lc; e++; }
+    }
+  }
+  bad = __syncthreads_or(bad) != 0;
+
+  // row pass: staged row e = 2 it + half, four row pairs per wave in flight
+  constexpr int U = 4;
+  for (int it0 = wv; 2 * it0 < L; it0 += 4 * U) {
+    float av[U], bv[U], cv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const float *xr = reg + min(2 * (it0 + 4 * u) + half, L - 1) * kTileRS;
+      av[u] = tile_clean<Tin>(xr[j]);
+      bv[u] = tile_clean<Tin>(xr[2 * R + j]);
+      cv[u] = j < nc ? tile_clean<Tin>(xr[31 + j]) : -INFINITY;
+      if (nc > 32) {
+        const float c2 = tile_clean<Tin>(xr[63 + j]);
+        if (j < nc - 32) cv[u] = fmaxf(cv[u], c2);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int e = 2 * (it0 + 4 * u) + half;
+      const float S = half_suffix_max(j < 31 ? av[u] : -INFINITY);
+      const float P = half_prefix_max(j >= 1 ? bv[u] : -INFINITY);
+      const float C = half_max(cv[u]);
+      if (e < L) rm[e * kTileMS + j] = fmaxf(fmaxf(S, P), C);
+    }
+  }
+  __syncthreads();
+
+  // column pass: output column cc = 2 it + half, it = wv + 4 u (all 16 pairs)
+  double tmax = 0.0;
+  {
+    float av[4], bv[4], cv[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const float *col = rm + 2 * (wv + 4 * u) + half;
+      av[u] = col[j * kTileMS];
+      bv[u] = col[(2 * R + j) * kTileMS];
+      cv[u] = j < nc ? col[(31 + j) * kTileMS] : -INFINITY;
+      if (nc > 32) {
+        const float c2 = col[(63 + j) * kTileMS];
+        if (j < nc - 32) cv[u] = fmaxf(cv[u], c2);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int cc = 2 * (wv + 4 * u) + half;
+      const float S = half_suffix_max(j < 31 ? av[u] : -INFINITY);
+      const float P = half_prefix_max(j >= 1 ? bv[u] : -INFINITY);
+      const float C = half_max(cv[u]);
+      const double d = (double)fmaxf(fmaxf(S, P), C) - (double)fc[j * kTileMS + cc];
+      tmax = (y0 + j < H && x0 + cc < W && d > tmax) ? d : tmax;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(tmax, off, 64);
+    tmax = o > tmax ? o : tmax;
+  }
+  if (lane == 0) wmax[wv] = tmax;
+  __syncthreads();
+
+  if (tid == 0) {
+    tmax = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    const int nb = a.gg.gx * a.gg.gy, bl = b.y * a.gg.gx + b.x;
+    const int sub = bl % kRangeSubs, nsub = min(nb, kRangeSubs);
+    unsigned long long t = (unsigned long long)__double_as_longlong(tmax);
+    int32_t fl = bad ? 1 : 0;
+    if (acc_merge(a.acc.sub + sub, t, fl, (uint32_t)((nb - sub + kRangeSubs - 1) / kRangeSubs)) &&
+        acc_merge(a.acc.top, t, fl, (uint32_t)nsub)) {
+      const double tc = ceil(__longlong_as_double((long long)t));
+      const int32_t ti = tc > 2147483647.0 ? 2147483647 : (int32_t)tc;
+      const DevState st = a.st;
+      *st.T_raw = t;
+      *st.T_used = ti;
+      *st.flags = fl | (ti > a.T_cap ? 2 : 0);
+      *st.q_nonpos = 0ull;
+    }
+  }
+}
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_range_tile(RangeTileArgs a) {
+  range_tile_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
+}
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_range_tile_grp(const RangeTileArgs *__restrict__ a,
+                                                        const int *__restrict__ start, int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  range_tile_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
 }
 
 // --------------------------------------------- blocked recursive Gaussian
@@ -1128,9 +1361,23 @@ GroupGrid range_col_grid(const Geom &g, int R) {
 }
 bool range_col_seq(int R) { return R > kColMaxR; }
 
+bool range_tile_ok(int R) { return R >= kTileMinR && R <= kTileMaxR; }
+GroupGrid range_tile_grid(const Geom &g) { return GroupGrid{(g.W + kTileW - 1) / kTileW, (g.H + kTileH - 1) / kTileH, 1}; }
+size_t range_tile_lds(int R) { return (size_t)tile_lds_floats(R) * sizeof(float); }
+
 template <typename Tin>
 static hipError_t range_t(hipStream_t s, const Tin *f, const Geom &g, int R, Tin *rowmax, DevState st,
-                          int32_t T_cap, const StageRec &rec) {
+                          RangeAcc acc, int32_t T_cap, const StageRec &rec) {
+  if (range_tile_ok(R)) {
+    rec.begin(BF_STAGE_RANGE, s);
+    const GroupGrid gt = range_tile_grid(g);
+    RangeTileArgs ta{gt, f, g.pitch, g.H, g.W, R, st, acc, T_cap};
+    hipLaunchKernelGGL(k_range_tile<Tin>, dim3(gt.gx, gt.gy), dim3(256), range_tile_lds(R), s, ta);
+    rec.end(BF_STAGE_RANGE, s);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_reset(s, st, 0, 0.0);
+  if (e != hipSuccess) return e;
   rec.begin(BF_STAGE_RANGE, s);
   const GroupGrid gr = range_row_grid(g), gc = range_col_grid(g, R);
   RowmaxArgs ra{gr, f, g.pitch, g.H, g.W, R, rowmax, st};
@@ -1164,18 +1411,33 @@ hipError_t launch_range_group(hipStream_t s, bf_dtype dt, bool seq, const Rowmax
     default: return range_group_t<float>(s, seq, ra, rstart, rtotal, ca, cstart, ctotal, n);
   }
 }
+template <typename Tin>
+static hipError_t range_tile_group_t(hipStream_t s, const RangeTileArgs *a, const int *start, int total, int n,
+                                     size_t lds) {
+  if (total > 0) hipLaunchKernelGGL(k_range_tile_grp<Tin>, dim3(total), dim3(256), lds, s, a, start, n);
+  return hipGetLastError();
+}
+hipError_t launch_range_tile_group(hipStream_t s, bf_dtype dt, const RangeTileArgs *a, const int *start,
+                                   int total, int n, size_t lds) {
+  switch (dt) {
+    case BF_U8: return range_tile_group_t<uint8_t>(s, a, start, total, n, lds);
+    case BF_U16: return range_tile_group_t<uint16_t>(s, a, start, total, n, lds);
+    default: return range_tile_group_t<float>(s, a, start, total, n, lds);
+  }
+}
 hipError_t launch_reset_group(hipStream_t s, const ResetArgs *a, const int *start, int total, int n) {
   if (total > 0) hipLaunchKernelGGL(k_reset_grp, dim3(total), dim3(64), 0, s, a, start, n);
   return hipGetLastError();
 }
 
 hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,
-                        DevState st, int32_t T_cap, const StageRec &rec) {
+                        DevState st, RangeAcc acc, int32_t T_cap, const StageRec &rec) {
   if (R > kMaxR) return hipErrorInvalidValue;
   switch (dt) {
-    case BF_U8: return range_t<uint8_t>(s, (const uint8_t *)f, g, R, (uint8_t *)rowmax, st, T_cap, rec);
-    case BF_U16: return range_t<uint16_t>(s, (const uint16_t *)f, g, R, (uint16_t *)rowmax, st, T_cap, rec);
-    default: return range_t<float>(s, (const float *)f, g, R, (float *)rowmax, st, T_cap, rec);
+    case BF_U8: return range_t<uint8_t>(s, (const uint8_t *)f, g, R, (uint8_t *)rowmax, st, acc, T_cap, rec);
+    case BF_U16:
+      return range_t<uint16_t>(s, (const uint16_t *)f, g, R, (uint16_t *)rowmax, st, acc, T_cap, rec);
+    default: return range_t<float>(s, (const float *)f, g, R, (float *)rowmax, st, acc, T_cap, rec);
   }
 }
 

@@ -59,7 +59,7 @@ def compare(img, dtype, sigma_s, sigma_r, eps, radius=0, t_mode="local", t_value
 
 # ------------------------------------------------------------ Algorithm 1
 @pytest.mark.parametrize("shape", [(1, 1), (1, 70), (70, 1), (33, 65), (129, 300), (300, 129)])
-@pytest.mark.parametrize("R", [0, 1, 4, 30, 48, 49, 200])
+@pytest.mark.parametrize("R", [0, 1, 4, 15, 16, 30, 31, 32, 33, 48, 49, 200])
 @pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
 def test_dynamic_range_exact(shape, R, dtype):
     torch = _torch()
@@ -72,6 +72,49 @@ def test_dynamic_range_exact(shape, R, dtype):
     plan.close()
     Rr = R if R > 0 else 6
     assert T == o.range_T(img.astype(np.float64), Rr)
+
+
+@pytest.mark.parametrize("R", [3, 16, 30, 32, 33, 40])
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_dynamic_range_repeated_calls(R, dtype):
+    """Every call on one plan starts from a clean range state: images whose T
+    falls from call to call each get their own T (the one-launch tile kernel
+    clears its accumulator and workgroup counter as it publishes T), and the
+    filter's report agrees."""
+    torch = _torch()
+    from paper_1203_5128_amd import Plan, make_params
+    H, W = 150, 170
+    plan = Plan.create(make_params(H, W, dtype, sigma_s=2.0, sigma_r=20.0, radius=R, t_mode="local"))
+    for seed, scale in [(11, 1.0), (12, 0.3), (13, 0.6), (14, 0.05), (15, 0.0)]:
+        img = np.floor(gen_random(seed, H, W, "u8").astype(np.float64) * scale)
+        img = img.astype(np.uint8 if dtype == "u8" else np.float32)
+        t = torch.from_numpy(img).to("cuda")
+        T = plan.dynamic_range(t)
+        assert T == o.range_T(img.astype(np.float64), R), (seed, scale)
+        _, rep = plan.filter(t)
+        _, rep2 = plan.filter(t)
+        assert rep["T"] == T and rep["flags"] == 0
+        assert rep2["T"] == T and rep2["q_nonpos"] == rep["q_nonpos"]
+    plan.close()
+
+
+def test_dynamic_range_non_finite_values():
+    """Float input with +inf, -inf and NaN: the report flags it on both range
+    paths, and the next call on a clean image reports no flag."""
+    torch = _torch()
+    from paper_1203_5128_amd import BFError, Plan, make_params
+    for R in (5, 20, 40):
+        plan = Plan.create(make_params(70, 90, "f32", sigma_s=2.0, sigma_r=20.0, radius=R))
+        for bad in (np.inf, -np.inf, np.nan):
+            img = gen_random(83, 70, 90, "f32")
+            img[33, 61] = bad
+            with pytest.raises(BFError) as ei:
+                plan.filter(torch.from_numpy(img).to("cuda"))
+            assert ei.value.status == 5
+            clean = gen_random(84, 70, 90, "f32")
+            _, rep = plan.filter(torch.from_numpy(clean).to("cuda"))
+            assert rep["flags"] == 0 and rep["T"] == o.range_T(clean.astype(np.float64), R)
+        plan.close()
 
 
 # ------------------------------------------------------- small parity sweep
