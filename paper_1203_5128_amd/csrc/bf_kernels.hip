@@ -467,70 +467,95 @@ __global__ __launch_bounds__(64) void k_colmax_T_seq_grp(const ColmaxArgs *__res
 }
 
 // ------------------------ Algorithm 1 in one launch, for 16 <= R <= 32
-// A workgroup takes a 32 x 32 block of output pixels.  The block and its
-// R-pixel halo are staged in LDS (out-of-image samples -inf).  With a window
+// A workgroup (8 waves) takes a 32 x 32 block of output pixels.  The block
+// and its R-pixel halo are staged in LDS, one staged row per wave step with
+// the lanes along the row (out-of-image samples -inf).  With a window
 // 2R+1 >= 32 the MAX-FILTER of the Appendix over a line of 32 + 2R samples x
 // has, for output j in [0, 32), the window [j, j+2R] = [j, 30] u [31, 2R] u
 // [2R+1, 2R+j]: a suffix maximum over the first 31 samples, one maximum
 // common to the whole line, and a prefix maximum over the last 31 samples
 // (van Herk's forward and backward running maxima with the segment boundary
 // placed at the line's 31st sample).  A half-wave takes one line, lane j
-// holding the three pieces for output j, and forms each with DPP scans.  The
-// row pass filters every staged row into the row maxima; the column pass
-// filters every output column of those, and T = max (out - f) (Prop. 2.1)
-// over the block is merged in two levels: into one of kRangeSubs
-// sub-accumulators (block index mod kRangeSubs), whose last arrival merges
-// it into the top accumulator, whose last arrival publishes T, the flags and
-// a zero non-positive-denominator count and clears both levels for the next
-// call.  So no reset launch precedes it, and no address takes more than a
-// few dozen atomics.
+// holding output j; the common maximum enters the suffix scan as lane 31's
+// sample.  Samples x[31] and x[2R] lie in every window of the line, so lanes
+// whose piece is empty read one of them instead of a masked value.  The
+// scans run on integer keys that order like the samples (float bit patterns,
+// sign-folded for float input), so each step is one DPP max.  The row pass
+// filters every staged row into the row maxima; the column pass filters
+// every output column of those, and T = max (out - f) (Prop. 2.1) over the
+// block is merged in two levels: into one of kRangeSubs sub-accumulators
+// (block index mod kRangeSubs), whose last arrival merges it into the top
+// accumulator, whose last arrival publishes T, the flags and a zero
+// non-positive-denominator count and clears both levels for the next call.
+// So no reset launch precedes it, and no address takes more than a few dozen
+// atomics.
 constexpr int kTileW = 32;
 constexpr int kTileH = 32;
 constexpr int kTileMinR = 16;
 constexpr int kTileMaxR = 32;
+constexpr int kTileThreads = 512;
+constexpr int kTileWaves = kTileThreads / 64;
 constexpr int kTileRS = kTileW + 2 * kTileMaxR;  // staged row stride (= 32 mod 64 banks)
 constexpr int kTileMS = kTileW + 1;              // row-maxima and centre strides
-constexpr int kStageMax = ((kTileH + 2 * kTileMaxR) * (kTileW + 2 * kTileMaxR) + 255) / 256;
 
-// LDS floats: staged block (L x kTileRS), row maxima (L x kTileMS), the raw
-// centre samples (kTileH x kTileMS).
+// LDS words: staged keys (L x kTileRS), row-maxima keys (L x kTileMS), the
+// raw centre samples (kTileH x kTileMS).
 __host__ __device__ constexpr int tile_lds_floats(int R) {
   return (kTileH + 2 * R) * (kTileRS + kTileMS) + kTileH * kTileMS;
 }
 
+// Order-preserving integer key of a sample (non-finite float samples count
+// as -inf); 8- and 16-bit samples are >= 0, whose bit patterns already
+// order as integers, as does -inf's below them.
 template <typename Tin>
-__device__ __forceinline__ float tile_clean(float v) {
-  if constexpr (std::is_same<Tin, float>::value) return isfinite(v) ? v : -INFINITY;
-  return v;
+__device__ __forceinline__ int tile_key(float v) {
+  if constexpr (std::is_same<Tin, float>::value) {
+    const int bits = __float_as_int(isfinite(v) ? v : -INFINITY);
+    return bits ^ ((bits >> 31) & 0x7FFFFFFF);
+  }
+  return __float_as_int(v);
+}
+template <typename Tin>
+__device__ __forceinline__ float tile_unkey(int k) {
+  if constexpr (std::is_same<Tin, float>::value) return __int_as_float(k ^ ((k >> 31) & 0x7FFFFFFF));
+  return __int_as_float(k);
 }
 
 // Max scans over each 32-lane half of the wave (lanes 0-31 and 32-63 hold
-// independent lines).  Lanes without a source keep -inf.
+// independent lines); lanes without a source take INT_MIN, max's identity.
 template <int CTRL, int RM = 0xF>
-__device__ __forceinline__ float dpp_keep(float old, float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, RM, 0xF, false));
+__device__ __forceinline__ int dpp_max(int v) {
+  return max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, CTRL, RM, 0xF, false));
 }
-__device__ __forceinline__ float half_prefix_max(float v) {
-  v = fmaxf(v, dpp_keep<0x111>(-INFINITY, v));        // row_shr:1
-  v = fmaxf(v, dpp_keep<0x112>(-INFINITY, v));        // row_shr:2
-  v = fmaxf(v, dpp_keep<0x114>(-INFINITY, v));        // row_shr:4
-  v = fmaxf(v, dpp_keep<0x118>(-INFINITY, v));        // row_shr:8
-  return fmaxf(v, dpp_keep<0x142, 0xA>(-INFINITY, v));  // row_bcast:15 into rows 1 and 3
+__device__ __forceinline__ int half_prefix_max(int v) {
+  v = dpp_max<0x111>(v);          // row_shr:1
+  v = dpp_max<0x112>(v);          // row_shr:2
+  v = dpp_max<0x114>(v);          // row_shr:4
+  v = dpp_max<0x118>(v);          // row_shr:8
+  return dpp_max<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
 }
-__device__ __forceinline__ float half_suffix_max(float v) {
-  v = fmaxf(v, dpp_keep<0x101>(-INFINITY, v));  // row_shl:1
-  v = fmaxf(v, dpp_keep<0x102>(-INFINITY, v));  // row_shl:2
-  v = fmaxf(v, dpp_keep<0x104>(-INFINITY, v));  // row_shl:4
-  v = fmaxf(v, dpp_keep<0x108>(-INFINITY, v));  // row_shl:8
-  const float t = __shfl(v, (int)((threadIdx.x & 32) | 16));  // head of the half's upper row
-  return (threadIdx.x & 16) ? v : fmaxf(v, t);
+__device__ __forceinline__ int half_suffix_max(int v) {
+  v = dpp_max<0x101>(v);  // row_shl:1
+  v = dpp_max<0x102>(v);  // row_shl:2
+  v = dpp_max<0x104>(v);  // row_shl:4
+  v = dpp_max<0x108>(v);  // row_shl:8
+  const int t16 = __builtin_amdgcn_readlane(v, 16), t48 = __builtin_amdgcn_readlane(v, 48);
+  return (threadIdx.x & 16) ? v : max(v, (threadIdx.x & 32) ? t48 : t16);
 }
-__device__ __forceinline__ float half_max(float v) {
-  v = fmaxf(v, dpp_keep<0x128>(v, v));  // row_ror:8
-  v = fmaxf(v, dpp_keep<0x124>(v, v));  // row_ror:4
-  v = fmaxf(v, dpp_keep<0x122>(v, v));  // row_ror:2
-  v = fmaxf(v, dpp_keep<0x121>(v, v));  // row_ror:1
-  return fmaxf(v, __shfl_xor(v, 16));
+// Maximum over the half, complete in its upper row (lanes 16-31, 48-63).
+__device__ __forceinline__ int half_upper_max(int v) {
+  v = dpp_max<0x128>(v);          // row_ror:8
+  v = dpp_max<0x124>(v);          // row_ror:4
+  v = dpp_max<0x122>(v);          // row_ror:2
+  v = dpp_max<0x121>(v);          // row_ror:1
+  return dpp_max<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+}
+// Window maxima of one line: lane j holds a = x[j], b = x[2R + j] and c = a
+// sample of [31, 2R]; returns the key of max x[j .. j + 2R].
+__device__ __forceinline__ int line_max(int a, int b, int c) {
+  const int C = half_upper_max(c);
+  const int S = half_suffix_max((threadIdx.x & 31) == 31 ? C : a);
+  return max(S, half_prefix_max(b));
 }
 
 // Merge the candidate t and flags fl into accumulator slot c; true for the
@@ -558,100 +583,93 @@ __device__ __forceinline__ bool acc_merge(RangeAccSlot *c, unsigned long long &t
 template <typename Tin>
 __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Blk b) {
   extern __shared__ float tlds[];
-  __shared__ double wmax[4];
+  __shared__ double wmax[kTileWaves];
   const Tin *__restrict__ f = (const Tin *)a.f;
   const int64_t pitch = a.pitch;
   const int H = a.H, W = a.W, R = a.R;
   const int L = kTileH + 2 * R;   // staged rows
   const int Lc = kTileW + 2 * R;  // staged columns
   const int nc = 2 * R - 30;      // samples [31, 2R] common to every window of a line
-  float *reg = tlds;
-  float *rm = reg + L * kTileRS;
-  float *fc = rm + L * kTileMS;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, j = lane & 31, half = lane >> 5;
+  int *reg = (int *)tlds;
+  int *rm = reg + L * kTileRS;
+  float *fc = (float *)(rm + L * kTileMS);
+  const int tid = threadIdx.x, lane = tid & 63, j = lane & 31, half = lane >> 5;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int x0 = b.x * kTileW, y0 = b.y * kTileH;
 
-  // stage: the block's samples in row-major order, kStageMax per thread; every
-  // lane loads from a clamped in-image address (no branch around the load, so
-  // all loads stay in flight) and masks afterwards
+  // stage: staged row e = wv + kTileWaves k, columns lane and lane + 64; every
+  // lane loads from a clamped in-image address (no branch around the load,
+  // so all loads stay in flight) and masks afterwards
   bool bad = false;
   {
-    const int q = 256 / Lc, r = 256 - q * Lc;
-    float v[kStageMax];
-    int e = tid / Lc, c = tid - (tid / Lc) * Lc;
+    constexpr int kRows = (kTileH + 2 * kTileMaxR) / kTileWaves;
+    float v[kRows][2];
+    const int xa = x0 - R + lane, xb = xa + 64;
+    const int xac = min(max(xa, 0), W - 1), xbc = min(max(xb, 0), W - 1);
+    const bool ina = xa >= 0 && xa < W, inb = lane + 64 < Lc && xb >= 0 && xb < W;
 #pragma unroll
-    for (int k = 0; k < kStageMax; k++) {
-      const int y = y0 - R + e, x = x0 - R + c;
-      const bool in = e < L && y >= 0 && y < H && x >= 0 && x < W;
-      const float raw = fval(f[(int64_t)min(max(y, 0), H - 1) * pitch + min(max(x, 0), W - 1)]);
-      v[k] = in ? raw : -INFINITY;
-      if (in && !isfinite(raw)) bad = true;
-      c += r;
-      e += q;
-      if (c >= Lc) { c -= Lc; e++; }
+    for (int k = 0; k < kRows; k++) {
+      const int e = wv + kTileWaves * k, y = y0 - R + e;
+      const bool rin = e < L && y >= 0 && y < H;
+      const Tin *row = f + (int64_t)min(max(y, 0), H - 1) * pitch;
+      const float ra = fval(row[xac]), rb = fval(row[xbc]);
+      v[k][0] = (rin && ina) ? ra : -INFINITY;
+      v[k][1] = (rin && inb) ? rb : -INFINITY;
+      if ((rin && ina && !isfinite(ra)) || (rin && inb && !isfinite(rb))) bad = true;
     }
-    e = tid / Lc;
-    c = tid - e * Lc;
 #pragma unroll
-    for (int k = 0; k < kStageMax; k++) {
-      if (e < L) reg[e * kTileRS + c] = v[k];
-      const int ce = e - R, cc = c - R;
-      if (ce >= 0 && ce < kTileH && cc >= 0 && cc < kTileW) fc[ce * kTileMS + cc] = v[k];
-      c += r;
-      e += q;
-      if (c >= Lc) { c -= Lc; e++; }
+    for (int k = 0; k < kRows; k++) {
+      const int e = wv + kTileWaves * k;
+      if (e < L) {
+        reg[e * kTileRS + lane] = tile_key<Tin>(v[k][0]);
+        if (lane + 64 < Lc) reg[e * kTileRS + lane + 64] = tile_key<Tin>(v[k][1]);
+        const int ce = e - R, cc = lane - R;  // centre columns [R, R + 32) lie below 64
+        if (ce >= 0 && ce < kTileH && cc >= 0 && cc < kTileW) fc[ce * kTileMS + cc] = v[k][0];
+      }
     }
   }
   bad = __syncthreads_or(bad) != 0;
 
   // row pass: staged row e = 2 it + half, four row pairs per wave in flight
+  const int n1 = nc - 1, n2 = nc - 33;
   constexpr int U = 4;
-  for (int it0 = wv; 2 * it0 < L; it0 += 4 * U) {
-    float av[U], bv[U], cv[U];
+  for (int it0 = wv; 2 * it0 < L; it0 += kTileWaves * U) {
+    int av[U], bv[U], cv[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      const float *xr = reg + min(2 * (it0 + 4 * u) + half, L - 1) * kTileRS;
-      av[u] = tile_clean<Tin>(xr[j]);
-      bv[u] = tile_clean<Tin>(xr[2 * R + j]);
-      cv[u] = j < nc ? tile_clean<Tin>(xr[31 + j]) : -INFINITY;
-      if (nc > 32) {
-        const float c2 = tile_clean<Tin>(xr[63 + j]);
-        if (j < nc - 32) cv[u] = fmaxf(cv[u], c2);
-      }
+      const int *xr = reg + min(2 * (it0 + kTileWaves * u) + half, L - 1) * kTileRS;
+      av[u] = xr[j];
+      bv[u] = xr[2 * R + j];
+      cv[u] = xr[31 + min(j, n1)];
+      if (nc > 32) cv[u] = max(cv[u], xr[63 + min(j, n2)]);
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      const int e = 2 * (it0 + 4 * u) + half;
-      const float S = half_suffix_max(j < 31 ? av[u] : -INFINITY);
-      const float P = half_prefix_max(j >= 1 ? bv[u] : -INFINITY);
-      const float C = half_max(cv[u]);
-      if (e < L) rm[e * kTileMS + j] = fmaxf(fmaxf(S, P), C);
+      const int e = 2 * (it0 + kTileWaves * u) + half;
+      const int m = line_max(av[u], bv[u], cv[u]);
+      if (e < L) rm[e * kTileMS + j] = m;
     }
   }
   __syncthreads();
 
-  // column pass: output column cc = 2 it + half, it = wv + 4 u (all 16 pairs)
+  // column pass: output column cc = 2 it + half, it = wv + kTileWaves u
   double tmax = 0.0;
   {
-    float av[4], bv[4], cv[4];
+    constexpr int UC = kTileW / 2 / kTileWaves;
+    int av[UC], bv[UC], cv[UC];
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const float *col = rm + 2 * (wv + 4 * u) + half;
+    for (int u = 0; u < UC; u++) {
+      const int *col = rm + 2 * (wv + kTileWaves * u) + half;
       av[u] = col[j * kTileMS];
       bv[u] = col[(2 * R + j) * kTileMS];
-      cv[u] = j < nc ? col[(31 + j) * kTileMS] : -INFINITY;
-      if (nc > 32) {
-        const float c2 = col[(63 + j) * kTileMS];
-        if (j < nc - 32) cv[u] = fmaxf(cv[u], c2);
-      }
+      cv[u] = col[(31 + min(j, n1)) * kTileMS];
+      if (nc > 32) cv[u] = max(cv[u], col[(63 + min(j, n2)) * kTileMS]);
     }
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const int cc = 2 * (wv + 4 * u) + half;
-      const float S = half_suffix_max(j < 31 ? av[u] : -INFINITY);
-      const float P = half_prefix_max(j >= 1 ? bv[u] : -INFINITY);
-      const float C = half_max(cv[u]);
-      const double d = (double)fmaxf(fmaxf(S, P), C) - (double)fc[j * kTileMS + cc];
+    for (int u = 0; u < UC; u++) {
+      const int cc = 2 * (wv + kTileWaves * u) + half;
+      const float m = tile_unkey<Tin>(line_max(av[u], bv[u], cv[u]));
+      const double d = (double)m - (double)fc[j * kTileMS + cc];
       tmax = (y0 + j < H && x0 + cc < W && d > tmax) ? d : tmax;
     }
   }
@@ -664,7 +682,9 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
   __syncthreads();
 
   if (tid == 0) {
-    tmax = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    tmax = wmax[0];
+#pragma unroll
+    for (int w = 1; w < kTileWaves; w++) tmax = fmax(tmax, wmax[w]);
     const int nb = a.gg.gx * a.gg.gy, bl = b.y * a.gg.gx + b.x;
     const int sub = bl % kRangeSubs, nsub = min(nb, kRangeSubs);
     unsigned long long t = (unsigned long long)__double_as_longlong(tmax);
@@ -682,11 +702,11 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
   }
 }
 template <typename Tin>
-__global__ __launch_bounds__(256) void k_range_tile(RangeTileArgs a) {
+__global__ __launch_bounds__(kTileThreads) void k_range_tile(RangeTileArgs a) {
   range_tile_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
 }
 template <typename Tin>
-__global__ __launch_bounds__(256) void k_range_tile_grp(const RangeTileArgs *__restrict__ a,
+__global__ __launch_bounds__(kTileThreads) void k_range_tile_grp(const RangeTileArgs *__restrict__ a,
                                                         const int *__restrict__ start, int n) {
   const int i = group_find(start, n, blockIdx.x);
   range_tile_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
@@ -1372,7 +1392,7 @@ static hipError_t range_t(hipStream_t s, const Tin *f, const Geom &g, int R, Tin
     rec.begin(BF_STAGE_RANGE, s);
     const GroupGrid gt = range_tile_grid(g);
     RangeTileArgs ta{gt, f, g.pitch, g.H, g.W, R, st, acc, T_cap};
-    hipLaunchKernelGGL(k_range_tile<Tin>, dim3(gt.gx, gt.gy), dim3(256), range_tile_lds(R), s, ta);
+    hipLaunchKernelGGL(k_range_tile<Tin>, dim3(gt.gx, gt.gy), dim3(kTileThreads), range_tile_lds(R), s, ta);
     rec.end(BF_STAGE_RANGE, s);
     return hipGetLastError();
   }
@@ -1414,7 +1434,7 @@ hipError_t launch_range_group(hipStream_t s, bf_dtype dt, bool seq, const Rowmax
 template <typename Tin>
 static hipError_t range_tile_group_t(hipStream_t s, const RangeTileArgs *a, const int *start, int total, int n,
                                      size_t lds) {
-  if (total > 0) hipLaunchKernelGGL(k_range_tile_grp<Tin>, dim3(total), dim3(256), lds, s, a, start, n);
+  if (total > 0) hipLaunchKernelGGL(k_range_tile_grp<Tin>, dim3(total), dim3(kTileThreads), lds, s, a, start, n);
   return hipGetLastError();
 }
 hipError_t launch_range_tile_group(hipStream_t s, bf_dtype dt, const RangeTileArgs *a, const int *start,
