@@ -1288,12 +1288,19 @@ __device__ __forceinline__ void iir_h_accum_body(const IirArgs &a, const Blk b) 
   iir_h_accum_impl<Tin, S, kC>((const Tin *)a.f, a.out, g, tab, st, a.iir, a.k0, a.kcount, a.Z, a.PQ, a.first, a.last, a.glut, b);
 }
 
+// Workgroups per CU the horizontal kernel is compiled for: with 16 samples
+// per thread, 8- and 16-bit input fits 168 VGPRs (3 waves per SIMD, the
+// recursion's dependent chains overlap better); float input would spill.
+template <typename Tin, int kC>
+constexpr int h_blocks_per_cu() {
+  return kC == kCSmall ? (std::is_same<Tin, float>::value ? 2 : 3) : 1;
+}
 template <typename Tin, int S, int kC>
-__global__ __launch_bounds__(kHThreads, kC == kCSmall ? 2 : 1) void k_iir_h_accum(IirArgs a) {
+__global__ __launch_bounds__(kHThreads, (h_blocks_per_cu<Tin, kC>())) void k_iir_h_accum(IirArgs a) {
   iir_h_accum_body<Tin, S, kC>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
 }
 template <typename Tin, int S, int kC>
-__global__ __launch_bounds__(kHThreads, kC == kCSmall ? 2 : 1) void k_iir_h_accum_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
+__global__ __launch_bounds__(kHThreads, (h_blocks_per_cu<Tin, kC>())) void k_iir_h_accum_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
                                                      int n) {
   const int i = group_find(start, n, blockIdx.x);
   const IirArgs ai = a[i];
