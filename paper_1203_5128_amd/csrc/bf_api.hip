@@ -512,7 +512,7 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
     for (int i : gidx) {
       const ImagePlan &ip = pl->im[i];
       const bool loc = ip.p.t_mode == BF_T_LOCAL;
-      if (loc && range_tile_ok(ip.R)) continue;  // the tile kernel resets its own state
+      if (loc && range_tile_ok(ip.R, ip.p.dtype)) continue;  // the tile kernel resets its own state
       ra.push_back(ResetArgs{GroupGrid{1, 1, 1}, state_of(ip), loc ? 0 : ip.T_global, loc ? 0.0 : ip.T_global_raw});
       blocks.push_back(1);
     }
@@ -527,30 +527,33 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
       bp.launches.push_back(L);
     }
   }
-  for (bf_dtype dt : {BF_U8, BF_U16, BF_F32}) {
-    std::vector<RangeTileArgs> ta;
-    std::vector<int> tb;
-    size_t lds = 0;
-    for (int i : gidx) {
-      const ImagePlan &ip = pl->im[i];
-      if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || !range_tile_ok(ip.R)) continue;
-      const GroupGrid gt = range_tile_grid(ip.g);
-      ta.push_back(RangeTileArgs{gt, d_in[i], ip.g.pitch, ip.g.H, ip.g.W, ip.R, state_of(ip), acc_of(ip), ip.T_cap});
-      tb.push_back(gt.gx * gt.gy);
-      lds = std::max(lds, range_tile_lds(ip.R));
+  for (bf_dtype dt : {BF_U8, BF_U16, BF_F32})
+    for (int kr : {32, 48}) {
+      std::vector<RangeTileArgs> ta;
+      std::vector<int> tb;
+      size_t lds = 0;
+      for (int i : gidx) {
+        const ImagePlan &ip = pl->im[i];
+        if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || !range_tile_ok(ip.R, dt) || range_tile_kr(ip.R) != kr)
+          continue;
+        const GroupGrid gt = range_tile_grid(ip.g);
+        ta.push_back(RangeTileArgs{gt, d_in[i], ip.g.pitch, ip.g.H, ip.g.W, ip.R, state_of(ip), acc_of(ip), ip.T_cap});
+        tb.push_back(gt.gx * gt.gy);
+        lds = std::max(lds, range_tile_lds(ip.R, dt));
+      }
+      if (ta.empty()) continue;
+      const std::vector<int> ts = starts_of(tb);
+      GLaunch L{};
+      L.kind = 5;
+      L.dt = dt;
+      L.S = kr;
+      L.cnt = (int)ta.size();
+      L.o[0] = bp.pack.add(ta);
+      L.o[1] = bp.pack.add(ts);
+      L.t[0] = ts.back();
+      L.lds[0] = lds;
+      bp.launches.push_back(L);
     }
-    if (ta.empty()) continue;
-    const std::vector<int> ts = starts_of(tb);
-    GLaunch L{};
-    L.kind = 5;
-    L.dt = dt;
-    L.cnt = (int)ta.size();
-    L.o[0] = bp.pack.add(ta);
-    L.o[1] = bp.pack.add(ts);
-    L.t[0] = ts.back();
-    L.lds[0] = lds;
-    bp.launches.push_back(L);
-  }
   for (bf_dtype dt : {BF_U8, BF_U16, BF_F32})
     for (bool seq : {false, true}) {
       std::vector<RowmaxArgs> ra;
@@ -558,7 +561,7 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
       std::vector<int> rb, cb;
       for (int i : gidx) {
         const ImagePlan &ip = pl->im[i];
-        if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || range_tile_ok(ip.R) || range_col_seq(ip.R) != seq)
+        if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || range_tile_ok(ip.R, dt) || range_col_seq(ip.R) != seq)
           continue;
         void *rm = (char *)pl->d_bws + pl->rowmax_off[i];
         const GroupGrid gr = range_row_grid(ip.g), gc = range_col_grid(ip.g, ip.R);
@@ -680,8 +683,8 @@ bf_status enqueue_batch(bf_plan_s *pl, int n, const void *const *d_in, float *co
       e = launch_reset_group(s, (const ResetArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]), L.t[0], L.cnt);
     } else if (L.kind == 5) {
       pl->rec.begin(BF_STAGE_RANGE, s);
-      e = launch_range_tile_group(s, L.dt, (const RangeTileArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]),
-                                  L.t[0], L.cnt, L.lds[0]);
+      e = launch_range_tile_group(s, L.dt, L.S, (const RangeTileArgs *)(d_args + L.o[0]),
+                                  (const int *)(d_args + L.o[1]), L.t[0], L.cnt, L.lds[0]);
       pl->rec.end(BF_STAGE_RANGE, s);
     } else if (L.kind == 1) {
       pl->rec.begin(BF_STAGE_RANGE, s);

@@ -225,7 +225,7 @@ struct StageRec {
 hipError_t launch_fill_checker(hipStream_t s, bf_dtype dt, void *f, int H, int W, double top);
 hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw);
 // Algorithm 1 for one image, with the state reset it needs (the one-launch
-// tile kernel when range_tile_ok(R), else reset + row pass + column pass).
+// tile kernel when range_tile_ok(R, dt), else reset + row pass + column pass).
 hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,
                         DevState st, RangeAcc acc, int32_t T_cap, const StageRec &rec);
 // Grids of the range stage for one image and whether its column pass is the
@@ -233,10 +233,11 @@ hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g
 GroupGrid range_row_grid(const Geom &g);
 GroupGrid range_col_grid(const Geom &g, int R);
 bool range_col_seq(int R);
-bool range_tile_ok(int R);
+bool range_tile_ok(int R, bf_dtype dt);
+int range_tile_kr(int R);  // staged-block size class (32 or 48) of a tile-kernel image
 GroupGrid range_tile_grid(const Geom &g);
-size_t range_tile_lds(int R);
-hipError_t launch_range_tile_group(hipStream_t s, bf_dtype dt, const RangeTileArgs *a, const int *start,
+size_t range_tile_lds(int R, bf_dtype dt);
+hipError_t launch_range_tile_group(hipStream_t s, bf_dtype dt, int kr, const RangeTileArgs *a, const int *start,
                                    int total, int n, size_t lds);
 // Grouped launches over n images (device argument arrays and block starts).
 hipError_t launch_reset_group(hipStream_t s, const ResetArgs *a, const int *start, int total, int n);

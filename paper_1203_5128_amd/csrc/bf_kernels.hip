@@ -466,59 +466,67 @@ __global__ __launch_bounds__(64) void k_colmax_T_seq_grp(const ColmaxArgs *__res
   colmax_T_seq_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
 }
 
-// ------------------------ Algorithm 1 in one launch, for 16 <= R <= 32
+// ------------------------------------------- Algorithm 1 in one launch
 // A workgroup (8 waves) takes a 32 x 32 block of output pixels.  The block
 // and its R-pixel halo are staged in LDS, one staged row per wave step with
-// the lanes along the row (out-of-image samples -inf).  With a window
-// 2R+1 >= 32 the MAX-FILTER of the Appendix over a line of 32 + 2R samples x
-// has, for output j in [0, 32), the window [j, j+2R] = [j, 30] u [31, 2R] u
-// [2R+1, 2R+j]: a suffix maximum over the first 31 samples, one maximum
-// common to the whole line, and a prefix maximum over the last 31 samples
-// (van Herk's forward and backward running maxima with the segment boundary
-// placed at the line's 31st sample).  A half-wave takes one line, lane j
-// holding output j; the common maximum enters the suffix scan as lane 31's
-// sample.  Samples x[31] and x[2R] lie in every window of the line, so lanes
-// whose piece is empty read one of them instead of a masked value.  The
-// scans run on integer keys that order like the samples (float bit patterns,
-// sign-folded for float input), so each step is one DPP max.  The row pass
-// filters every staged row into the row maxima; the column pass filters
-// every output column of those, and T = max (out - f) (Prop. 2.1) over the
-// block is merged in two levels: into one of kRangeSubs sub-accumulators
-// (block index mod kRangeSubs), whose last arrival merges it into the top
-// accumulator, whose last arrival publishes T, the flags and a zero
-// non-positive-denominator count and clears both levels for the next call.
-// So no reset launch precedes it, and no address takes more than a few dozen
-// atomics.
+// the lanes along the row.  Samples are kept as integer keys that order like
+// them: the 8- or 16-bit value itself (out-of-image samples 0: every window
+// holds its in-image centre, which is >= 0), or for float input the bit
+// pattern sign-folded (non-finite samples and out-of-image ones -inf).
+// With a window 2R+1 >= 32 the MAX-FILTER of the Appendix over a line of
+// 32 + 2R samples x has, for output j in [0, 32), the window [j, j+2R] =
+// [j, 30] u [31, 2R] u [2R+1, 2R+j]: a suffix maximum over the first 31
+// samples, one maximum common to the whole line, and a prefix maximum over
+// the last 31 samples (van Herk's forward and backward running maxima with
+// the segment boundary placed at the line's 31st sample).  A half-wave
+// takes one line, lane j holding output j; the common maximum enters the
+// suffix scan as lane 31's sample.  Samples x[31] and x[2R] lie in every
+// window of the line, so lanes whose piece is empty read one of them instead
+// of a masked value; each scan step is one DPP max.  With a narrower window
+// (R < 16) each output takes the maximum of its 2R+1 <= 31 samples directly.
+// The row pass filters every staged row into the row maxima; the column pass
+// filters every output column of those, and T = max (out - f) (Prop. 2.1)
+// over the block is merged in two levels: into one of kRangeSubs
+// sub-accumulators (block index mod kRangeSubs), whose last arrival merges
+// it into the top accumulator, whose last arrival publishes T, the flags and
+// a zero non-positive-denominator count and clears both levels for the next
+// call.  So no reset launch precedes it, and no address takes more than a
+// few dozen atomics.  KR is the largest R an instantiation stages (32, or
+// 48 for 8- and 16-bit input, whose narrow keys keep that block in LDS).
 constexpr int kTileW = 32;
 constexpr int kTileH = 32;
-constexpr int kTileMinR = 16;
-constexpr int kTileMaxR = 32;
 constexpr int kTileThreads = 512;
 constexpr int kTileWaves = kTileThreads / 64;
-constexpr int kTileRS = kTileW + 2 * kTileMaxR;  // staged row stride (= 32 mod 64 banks)
-constexpr int kTileMS = kTileW + 1;              // row-maxima and centre strides
+constexpr int kTileMS = kTileW + 1;  // row-maxima and centre strides (words)
 
-// LDS words: staged keys (L x kTileRS), row-maxima keys (L x kTileMS), the
-// raw centre samples (kTileH x kTileMS).
-__host__ __device__ constexpr int tile_lds_floats(int R) {
-  return (kTileH + 2 * R) * (kTileRS + kTileMS) + kTileH * kTileMS;
+template <typename Tin> struct TileKey { using T = int; };
+template <> struct TileKey<uint8_t> { using T = uint8_t; };
+template <> struct TileKey<uint16_t> { using T = uint16_t; };
+
+// staged row stride in keys: the two half-waves of a row pass read rows e
+// and e+1 at the same offsets, which this stride puts in disjoint banks
+template <int KR> constexpr int tile_rs() { return KR <= 32 ? 96 : 160; }
+
+// LDS bytes: staged keys (L x RS, padded to a word), row-maxima keys
+// (L x kTileMS words), raw centre samples (kTileH x kTileMS floats).
+template <typename Tin, int KR>
+__host__ __device__ constexpr size_t tile_lds_bytes(int R) {
+  return ((size_t)(kTileH + 2 * R) * tile_rs<KR>() * sizeof(typename TileKey<Tin>::T) + 3) / 4 * 4 +
+         (size_t)(kTileH + 2 * R) * kTileMS * 4 + (size_t)kTileH * kTileMS * 4;
 }
 
-// Order-preserving integer key of a sample (non-finite float samples count
-// as -inf); 8- and 16-bit samples are >= 0, whose bit patterns already
-// order as integers, as does -inf's below them.
 template <typename Tin>
 __device__ __forceinline__ int tile_key(float v) {
   if constexpr (std::is_same<Tin, float>::value) {
     const int bits = __float_as_int(isfinite(v) ? v : -INFINITY);
     return bits ^ ((bits >> 31) & 0x7FFFFFFF);
   }
-  return __float_as_int(v);
+  return (int)v;
 }
 template <typename Tin>
 __device__ __forceinline__ float tile_unkey(int k) {
   if constexpr (std::is_same<Tin, float>::value) return __int_as_float(k ^ ((k >> 31) & 0x7FFFFFFF));
-  return __int_as_float(k);
+  return (float)k;
 }
 
 // Max scans over each 32-lane half of the wave (lanes 0-31 and 32-63 hold
@@ -580,8 +588,11 @@ __device__ __forceinline__ bool acc_merge(RangeAccSlot *c, unsigned long long &t
   return true;
 }
 
-template <typename Tin>
+template <typename Tin, int KR>
 __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Blk b) {
+  using KeyT = typename TileKey<Tin>::T;
+  constexpr int RS = tile_rs<KR>();
+  constexpr bool kFloat = std::is_same<Tin, float>::value;
   extern __shared__ float tlds[];
   __shared__ double wmax[kTileWaves];
   const Tin *__restrict__ f = (const Tin *)a.f;
@@ -590,19 +601,20 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
   const int L = kTileH + 2 * R;   // staged rows
   const int Lc = kTileW + 2 * R;  // staged columns
   const int nc = 2 * R - 30;      // samples [31, 2R] common to every window of a line
-  int *reg = (int *)tlds;
-  int *rm = reg + L * kTileRS;
+  KeyT *reg = (KeyT *)tlds;
+  int *rm = (int *)tlds + ((size_t)L * RS * sizeof(KeyT) + 3) / 4;
   float *fc = (float *)(rm + L * kTileMS);
   const int tid = threadIdx.x, lane = tid & 63, j = lane & 31, half = lane >> 5;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int x0 = b.x * kTileW, y0 = b.y * kTileH;
+  const float pad = kFloat ? -INFINITY : 0.f;
 
   // stage: staged row e = wv + kTileWaves k, columns lane and lane + 64; every
   // lane loads from a clamped in-image address (no branch around the load,
   // so all loads stay in flight) and masks afterwards
   bool bad = false;
   {
-    constexpr int kRows = (kTileH + 2 * kTileMaxR) / kTileWaves;
+    constexpr int kRows = (kTileH + 2 * KR) / kTileWaves;
     float v[kRows][2];
     const int xa = x0 - R + lane, xb = xa + 64;
     const int xac = min(max(xa, 0), W - 1), xbc = min(max(xb, 0), W - 1);
@@ -613,40 +625,55 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
       const bool rin = e < L && y >= 0 && y < H;
       const Tin *row = f + (int64_t)min(max(y, 0), H - 1) * pitch;
       const float ra = fval(row[xac]), rb = fval(row[xbc]);
-      v[k][0] = (rin && ina) ? ra : -INFINITY;
-      v[k][1] = (rin && inb) ? rb : -INFINITY;
+      v[k][0] = (rin && ina) ? ra : pad;
+      v[k][1] = (rin && inb) ? rb : pad;
       if ((rin && ina && !isfinite(ra)) || (rin && inb && !isfinite(rb))) bad = true;
     }
 #pragma unroll
     for (int k = 0; k < kRows; k++) {
       const int e = wv + kTileWaves * k;
       if (e < L) {
-        reg[e * kTileRS + lane] = tile_key<Tin>(v[k][0]);
-        if (lane + 64 < Lc) reg[e * kTileRS + lane + 64] = tile_key<Tin>(v[k][1]);
-        const int ce = e - R, cc = lane - R;  // centre columns [R, R + 32) lie below 64
+        reg[e * RS + lane] = (KeyT)tile_key<Tin>(v[k][0]);
+        if (lane + 64 < Lc) reg[e * RS + lane + 64] = (KeyT)tile_key<Tin>(v[k][1]);
+        // centre columns [R, R + 32): from the first load, and past column 64
+        // (R > 32) from the second
+        const int ce = e - R, cc = lane - R, cc2 = lane + 64 - R;
         if (ce >= 0 && ce < kTileH && cc >= 0 && cc < kTileW) fc[ce * kTileMS + cc] = v[k][0];
+        if (KR > 32 && ce >= 0 && ce < kTileH && cc2 < kTileW) fc[ce * kTileMS + cc2] = v[k][1];
       }
     }
   }
   bad = __syncthreads_or(bad) != 0;
 
   // row pass: staged row e = 2 it + half, four row pairs per wave in flight
-  const int n1 = nc - 1, n2 = nc - 33;
+  const int n1 = nc - 1, n2 = nc - 33, n3 = nc - 65;
   constexpr int U = 4;
-  for (int it0 = wv; 2 * it0 < L; it0 += kTileWaves * U) {
-    int av[U], bv[U], cv[U];
+  if (R >= 16) {
+    for (int it0 = wv; 2 * it0 < L; it0 += kTileWaves * U) {
+      int av[U], bv[U], cv[U];
 #pragma unroll
-    for (int u = 0; u < U; u++) {
-      const int *xr = reg + min(2 * (it0 + kTileWaves * u) + half, L - 1) * kTileRS;
-      av[u] = xr[j];
-      bv[u] = xr[2 * R + j];
-      cv[u] = xr[31 + min(j, n1)];
-      if (nc > 32) cv[u] = max(cv[u], xr[63 + min(j, n2)]);
+      for (int u = 0; u < U; u++) {
+        const KeyT *xr = reg + min(2 * (it0 + kTileWaves * u) + half, L - 1) * RS;
+        av[u] = xr[j];
+        bv[u] = xr[2 * R + j];
+        cv[u] = xr[31 + min(j, n1)];
+        if (nc > 32) cv[u] = max(cv[u], (int)xr[63 + min(j, n2)]);
+        if (KR > 32 && nc > 64) cv[u] = max(cv[u], (int)xr[95 + min(j, n3)]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int e = 2 * (it0 + kTileWaves * u) + half;
+        const int m = line_max(av[u], bv[u], cv[u]);
+        if (e < L) rm[e * kTileMS + j] = m;
+      }
     }
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const int e = 2 * (it0 + kTileWaves * u) + half;
-      const int m = line_max(av[u], bv[u], cv[u]);
+  } else {
+    for (int it = wv; 2 * it < L; it += kTileWaves) {
+      const int e = 2 * it + half;
+      const KeyT *xr = reg + min(e, L - 1) * RS + j;
+      int m = xr[0];
+#pragma unroll 8
+      for (int k = 1; k <= 2 * R; k++) m = max(m, (int)xr[k]);
       if (e < L) rm[e * kTileMS + j] = m;
     }
   }
@@ -656,20 +683,34 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
   double tmax = 0.0;
   {
     constexpr int UC = kTileW / 2 / kTileWaves;
-    int av[UC], bv[UC], cv[UC];
+    int mv[UC];
+    if (R >= 16) {
+      int av[UC], bv[UC], cv[UC];
 #pragma unroll
-    for (int u = 0; u < UC; u++) {
-      const int *col = rm + 2 * (wv + kTileWaves * u) + half;
-      av[u] = col[j * kTileMS];
-      bv[u] = col[(2 * R + j) * kTileMS];
-      cv[u] = col[(31 + min(j, n1)) * kTileMS];
-      if (nc > 32) cv[u] = max(cv[u], col[(63 + min(j, n2)) * kTileMS]);
+      for (int u = 0; u < UC; u++) {
+        const int *col = rm + 2 * (wv + kTileWaves * u) + half;
+        av[u] = col[j * kTileMS];
+        bv[u] = col[(2 * R + j) * kTileMS];
+        cv[u] = col[(31 + min(j, n1)) * kTileMS];
+        if (nc > 32) cv[u] = max(cv[u], col[(63 + min(j, n2)) * kTileMS]);
+        if (KR > 32 && nc > 64) cv[u] = max(cv[u], col[(95 + min(j, n3)) * kTileMS]);
+      }
+#pragma unroll
+      for (int u = 0; u < UC; u++) mv[u] = line_max(av[u], bv[u], cv[u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < UC; u++) {
+        const int *col = rm + 2 * (wv + kTileWaves * u) + half + j * kTileMS;
+        int m = col[0];
+#pragma unroll 8
+        for (int k = 1; k <= 2 * R; k++) m = max(m, col[k * kTileMS]);
+        mv[u] = m;
+      }
     }
 #pragma unroll
     for (int u = 0; u < UC; u++) {
       const int cc = 2 * (wv + kTileWaves * u) + half;
-      const float m = tile_unkey<Tin>(line_max(av[u], bv[u], cv[u]));
-      const double d = (double)m - (double)fc[j * kTileMS + cc];
+      const double d = (double)tile_unkey<Tin>(mv[u]) - (double)fc[j * kTileMS + cc];
       tmax = (y0 + j < H && x0 + cc < W && d > tmax) ? d : tmax;
     }
   }
@@ -701,15 +742,15 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
     }
   }
 }
-template <typename Tin>
+template <typename Tin, int KR>
 __global__ __launch_bounds__(kTileThreads) void k_range_tile(RangeTileArgs a) {
-  range_tile_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
+  range_tile_body<Tin, KR>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
 }
-template <typename Tin>
+template <typename Tin, int KR>
 __global__ __launch_bounds__(kTileThreads) void k_range_tile_grp(const RangeTileArgs *__restrict__ a,
-                                                        const int *__restrict__ start, int n) {
+                                                                 const int *__restrict__ start, int n) {
   const int i = group_find(start, n, blockIdx.x);
-  range_tile_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+  range_tile_body<Tin, KR>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
 }
 
 // --------------------------------------------- blocked recursive Gaussian
@@ -1388,18 +1429,36 @@ GroupGrid range_col_grid(const Geom &g, int R) {
 }
 bool range_col_seq(int R) { return R > kColMaxR; }
 
-bool range_tile_ok(int R) { return R >= kTileMinR && R <= kTileMaxR; }
+// The one-launch range kernel stages blocks up to R = 32 for every dtype and
+// up to R = 48 for 8- and 16-bit input (narrow keys); larger R use the two
+// passes.
+bool range_tile_ok(int R, bf_dtype dt) { return R >= 1 && (R <= 32 || (R <= 48 && dt != BF_F32)); }
+int range_tile_kr(int R) { return R <= 32 ? 32 : 48; }
 GroupGrid range_tile_grid(const Geom &g) { return GroupGrid{(g.W + kTileW - 1) / kTileW, (g.H + kTileH - 1) / kTileH, 1}; }
-size_t range_tile_lds(int R) { return (size_t)tile_lds_floats(R) * sizeof(float); }
+template <typename Tin>
+static size_t tile_lds_t(int R) {
+  return range_tile_kr(R) == 32 ? tile_lds_bytes<Tin, 32>(R) : tile_lds_bytes<Tin, 48>(R);
+}
+size_t range_tile_lds(int R, bf_dtype dt) {
+  switch (dt) {
+    case BF_U8: return tile_lds_t<uint8_t>(R);
+    case BF_U16: return tile_lds_t<uint16_t>(R);
+    default: return tile_lds_t<float>(R);
+  }
+}
 
 template <typename Tin>
 static hipError_t range_t(hipStream_t s, const Tin *f, const Geom &g, int R, Tin *rowmax, DevState st,
                           RangeAcc acc, int32_t T_cap, const StageRec &rec) {
-  if (range_tile_ok(R)) {
+  if (range_tile_ok(R, dtype_of<Tin>())) {
     rec.begin(BF_STAGE_RANGE, s);
     const GroupGrid gt = range_tile_grid(g);
     RangeTileArgs ta{gt, f, g.pitch, g.H, g.W, R, st, acc, T_cap};
-    hipLaunchKernelGGL(k_range_tile<Tin>, dim3(gt.gx, gt.gy), dim3(kTileThreads), range_tile_lds(R), s, ta);
+    const size_t lds = range_tile_lds(R, dtype_of<Tin>());
+    if (range_tile_kr(R) == 32)
+      hipLaunchKernelGGL((k_range_tile<Tin, 32>), dim3(gt.gx, gt.gy), dim3(kTileThreads), lds, s, ta);
+    else if constexpr (!std::is_same<Tin, float>::value)
+      hipLaunchKernelGGL((k_range_tile<Tin, 48>), dim3(gt.gx, gt.gy), dim3(kTileThreads), lds, s, ta);
     rec.end(BF_STAGE_RANGE, s);
     return hipGetLastError();
   }
@@ -1439,17 +1498,24 @@ hipError_t launch_range_group(hipStream_t s, bf_dtype dt, bool seq, const Rowmax
   }
 }
 template <typename Tin>
-static hipError_t range_tile_group_t(hipStream_t s, const RangeTileArgs *a, const int *start, int total, int n,
-                                     size_t lds) {
-  if (total > 0) hipLaunchKernelGGL(k_range_tile_grp<Tin>, dim3(total), dim3(kTileThreads), lds, s, a, start, n);
+static hipError_t range_tile_group_t(hipStream_t s, int kr, const RangeTileArgs *a, const int *start, int total,
+                                     int n, size_t lds) {
+  if (total > 0) {
+    if (kr == 32)
+      hipLaunchKernelGGL((k_range_tile_grp<Tin, 32>), dim3(total), dim3(kTileThreads), lds, s, a, start, n);
+    else if constexpr (!std::is_same<Tin, float>::value)
+      hipLaunchKernelGGL((k_range_tile_grp<Tin, 48>), dim3(total), dim3(kTileThreads), lds, s, a, start, n);
+    else
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
-hipError_t launch_range_tile_group(hipStream_t s, bf_dtype dt, const RangeTileArgs *a, const int *start,
+hipError_t launch_range_tile_group(hipStream_t s, bf_dtype dt, int kr, const RangeTileArgs *a, const int *start,
                                    int total, int n, size_t lds) {
   switch (dt) {
-    case BF_U8: return range_tile_group_t<uint8_t>(s, a, start, total, n, lds);
-    case BF_U16: return range_tile_group_t<uint16_t>(s, a, start, total, n, lds);
-    default: return range_tile_group_t<float>(s, a, start, total, n, lds);
+    case BF_U8: return range_tile_group_t<uint8_t>(s, kr, a, start, total, n, lds);
+    case BF_U16: return range_tile_group_t<uint16_t>(s, kr, a, start, total, n, lds);
+    default: return range_tile_group_t<float>(s, kr, a, start, total, n, lds);
   }
 }
 hipError_t launch_reset_group(hipStream_t s, const ResetArgs *a, const int *start, int total, int n) {

@@ -59,7 +59,7 @@ def compare(img, dtype, sigma_s, sigma_r, eps, radius=0, t_mode="local", t_value
 
 # ------------------------------------------------------------ Algorithm 1
 @pytest.mark.parametrize("shape", [(1, 1), (1, 70), (70, 1), (33, 65), (129, 300), (300, 129)])
-@pytest.mark.parametrize("R", [0, 1, 4, 15, 16, 30, 31, 32, 33, 48, 49, 200])
+@pytest.mark.parametrize("R", [0, 1, 2, 4, 15, 16, 30, 31, 32, 33, 40, 47, 48, 49, 200])
 @pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
 def test_dynamic_range_exact(shape, R, dtype):
     torch = _torch()
