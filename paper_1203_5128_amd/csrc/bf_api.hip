@@ -268,10 +268,11 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   g.vC = kCLarge;
   g.vS = 1;
   while (g.vS * g.vC < g.H) g.vS <<= 1;
-  // a vertical workgroup covers 256 / vS columns: below 8 (one 128-byte line
-  // of a row) the smoothed images are stored in tiles of 8 vS / 256 rows
+  // a vertical workgroup covers 256 / vS columns; the smoothed images are
+  // stored in tiles whose row in a workgroup's columns holds
+  // z_tile_words(vS) elements
   g.zlog = 0;
-  while ((kHThreads / g.vS) << g.zlog < 8) g.zlog++;
+  while ((kHThreads / g.vS) << g.zlog < z_tile_words(g.vS)) g.zlog++;
   g.Hz = (g.H + (1 << g.zlog) - 1) >> g.zlog << g.zlog;
   g.center = (float)(0.5 * ip.range);
   if (!(g.center > 0.f)) return fail(BF_ERR_INVALID_ARG, "value_range too small");

@@ -45,9 +45,15 @@ struct Geom {
   int vppw;           // vertical pass: pairs per workgroup (one after another)
   // smoothed images of the recursive path, stored in tiles of zth = 2^zlog
   // rows: element (y, p) at ((y >> zlog) Spos + p) zth + (y mod zth), Hz rows
-  // per pair (H rounded up to zth).  zth = 8 / (columns per vertical
-  // workgroup), at least 1 (row-major): each vertical workgroup then writes
-  // whole 128-byte lines.
+  // per pair (H rounded up to zth).  zth (columns per vertical workgroup)
+  // = z_tile_words(vS), zth at least 1 (row-major): 16 elements (256 bytes)
+  // for workgroups of 4 and 8 columns, so that each writes 256 contiguous
+  // bytes per tile while the horizontal workgroups of neighbouring rows
+  // share each line; 8 (one line) for the 1- and 2-column workgroups of
+  // images taller than 2048, whose horizontal workgroups hold one row.
+  // (Taller tiles make the vertical writes longer but leave each horizontal
+  // workgroup a smaller share of the lines it reads; shorter ones scatter
+  // the vertical writes.)
   int Hz, zlog;
   // horizontal pass: the pairs of a launch are split into hgroups groups of
   // hkpg pairs, each a row of workgroups with its own partial sums
@@ -109,6 +115,7 @@ __device__ __forceinline__ Blk group_blk(const GroupGrid &gg, int local) {
 }
 
 // Offset of element (y, p) of one pair's smoothed images (recursive path).
+__host__ __device__ constexpr int z_tile_words(int vS) { return vS >= 128 ? 8 : 16; }
 __host__ __device__ inline size_t z_index(const Geom &g, int y, int p) {
   return (((size_t)(y >> g.zlog) * g.Spos + p) << g.zlog) + (y & ((1 << g.zlog) - 1));
 }

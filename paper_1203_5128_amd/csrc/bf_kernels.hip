@@ -1034,9 +1034,9 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
   constexpr int NG = kHThreads / SV;
   constexpr int NW = SV > 64 ? SV / 64 : 1;
   constexpr bool kLut = PhaseLut<Tin>::kOn;
-  // tile height of the smoothed images (2^ZL rows: NG 2^ZL >= 8, the host's
-  // zlog for this column group size)
-  constexpr int ZL = NG >= 8 ? 0 : (NG == 4 ? 1 : (NG == 2 ? 2 : 3));
+  // tile height of the smoothed images (2^ZL rows, the host's zlog for this
+  // column group size)
+  constexpr int ZL = NG >= 16 ? 0 : (NG == 8 ? 1 : (NG == 1 ? 3 : 2));
   __shared__ float4 xw[NG][NW][3];
   __shared__ IirLds L;
   // 8-bit inputs: cos/sin per intensity and a zero entry for the samples
@@ -1633,7 +1633,7 @@ static bool iir_geom_ok(const Geom &g, int kcount) {
   return g.hgroups >= 1 && g.hgroups <= 65535 && g.vppw >= 1 && g.hkpg >= 1 && (int64_t)g.hgroups * g.hkpg >= kcount &&
          kcount >= 1 && kcount <= 65535 && g.vS >= 1 && g.vS <= kHThreads && (int64_t)g.vS * g.vC >= g.H &&
          (int64_t)g.S * g.cC >= g.W && g.Spos == g.S * g.cC && g.zlog >= 0 && g.zlog <= 3 && g.Hz >= g.H && g.Hz % (1 << g.zlog) == 0 &&
-         ((kHThreads / g.vS) << g.zlog) >= 8 && (g.zlog == 0 || ((kHThreads / g.vS) << g.zlog) == 8);
+         ((kHThreads / g.vS) << g.zlog) >= z_tile_words(g.vS) && (g.zlog == 0 || ((kHThreads / g.vS) << g.zlog) == z_tile_words(g.vS));
 }
 
 template <typename Tin>
