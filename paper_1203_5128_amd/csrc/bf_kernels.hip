@@ -507,11 +507,21 @@ template <> struct TileKey<uint16_t> { using T = uint16_t; };
 // and e+1 at the same offsets, which this stride puts in disjoint banks
 template <int KR> constexpr int tile_rs() { return KR <= 32 ? 96 : 160; }
 
-// LDS bytes: staged keys (L x RS, padded to a word), row-maxima keys
-// (L x kTileMS words), raw centre samples (kTileH x kTileMS floats).
+// Float input with 32 < R <= 48: four-byte keys of the whole staged block
+// would take ~100 KB of LDS, so the row pass reads its samples from global
+// memory instead (coalesced 128-byte pieces, mostly cache hits) and only the
+// row maxima and the centre samples live in LDS.
+template <typename Tin, int KR>
+__host__ __device__ constexpr bool tile_global_rows() { return std::is_same<Tin, float>::value && KR > 32; }
+
+// LDS bytes: staged keys (L x RS, padded to a word; none when the row pass
+// reads global memory), row-maxima keys (L x kTileMS words), raw centre
+// samples (kTileH x kTileMS floats).
 template <typename Tin, int KR>
 __host__ __device__ constexpr size_t tile_lds_bytes(int R) {
-  return ((size_t)(kTileH + 2 * R) * tile_rs<KR>() * sizeof(typename TileKey<Tin>::T) + 3) / 4 * 4 +
+  return (tile_global_rows<Tin, KR>()
+              ? 0
+              : ((size_t)(kTileH + 2 * R) * tile_rs<KR>() * sizeof(typename TileKey<Tin>::T) + 3) / 4 * 4) +
          (size_t)(kTileH + 2 * R) * kTileMS * 4 + (size_t)kTileH * kTileMS * 4;
 }
 
@@ -601,8 +611,9 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
   const int L = kTileH + 2 * R;   // staged rows
   const int Lc = kTileW + 2 * R;  // staged columns
   const int nc = 2 * R - 30;      // samples [31, 2R] common to every window of a line
+  constexpr bool kGlob = tile_global_rows<Tin, KR>();
   KeyT *reg = (KeyT *)tlds;
-  int *rm = (int *)tlds + ((size_t)L * RS * sizeof(KeyT) + 3) / 4;
+  int *rm = (int *)tlds + (kGlob ? 0 : ((size_t)L * RS * sizeof(KeyT) + 3) / 4);
   float *fc = (float *)(rm + L * kTileMS);
   const int tid = threadIdx.x, lane = tid & 63, j = lane & 31, half = lane >> 5;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -613,7 +624,17 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
   // lane loads from a clamped in-image address (no branch around the load,
   // so all loads stay in flight) and masks afterwards
   bool bad = false;
-  {
+  if constexpr (kGlob) {
+    // only the centre samples: rows tid / 32 and tid / 32 + 16, column tid % 32
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      const int ce = (tid >> 5) + 16 * h, cc = tid & 31, y = y0 + ce, x = x0 + cc;
+      const bool in = y < H && x < W;
+      const float v = fval(f[(int64_t)min(y, H - 1) * pitch + min(x, W - 1)]);
+      fc[ce * kTileMS + cc] = v;
+      if (in && !isfinite(v)) bad = true;
+    }
+  } else {
     constexpr int kRows = (kTileH + 2 * KR) / kTileWaves;
     float v[kRows][2];
     const int xa = x0 - R + lane, xb = xa + 64;
@@ -648,7 +669,34 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
   // row pass: staged row e = 2 it + half, four row pairs per wave in flight
   const int n1 = nc - 1, n2 = nc - 33, n3 = nc - 65;
   constexpr int U = 4;
-  if (R >= 16) {
+  if constexpr (kGlob) {
+    // R > 32 here, so the common piece takes two or three loads
+    for (int it0 = wv; 2 * it0 < L; it0 += kTileWaves * U) {
+      int av[U], bv[U], cv[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int y = y0 - R + 2 * (it0 + kTileWaves * u) + half;
+        const bool rin = y >= 0 && y < H;
+        const float *row = (const float *)f + (int64_t)min(max(y, 0), H - 1) * pitch;
+        // key of staged column s: clamped load, -inf outside the image
+        const auto key_at = [&](int s) {
+          const int x = x0 - R + s;
+          const float v = row[min(max(x, 0), W - 1)];
+          return tile_key<Tin>((rin && x >= 0 && x < W) ? v : -INFINITY);
+        };
+        av[u] = key_at(j);
+        bv[u] = key_at(2 * R + j);
+        cv[u] = max(key_at(31 + min(j, n1)), key_at(63 + min(j, n2)));
+        if (nc > 64) cv[u] = max(cv[u], key_at(95 + min(j, n3)));
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int e = 2 * (it0 + kTileWaves * u) + half;
+        const int m = line_max(av[u], bv[u], cv[u]);
+        if (e < L) rm[e * kTileMS + j] = m;
+      }
+    }
+  } else if (R >= 16) {
     for (int it0 = wv; 2 * it0 < L; it0 += kTileWaves * U) {
       int av[U], bv[U], cv[U];
 #pragma unroll
@@ -1429,10 +1477,12 @@ GroupGrid range_col_grid(const Geom &g, int R) {
 }
 bool range_col_seq(int R) { return R > kColMaxR; }
 
-// The one-launch range kernel stages blocks up to R = 32 for every dtype and
-// up to R = 48 for 8- and 16-bit input (narrow keys); larger R use the two
-// passes.
-bool range_tile_ok(int R, bf_dtype dt) { return R >= 1 && (R <= 32 || (R <= 48 && dt != BF_F32)); }
+// The one-launch range kernel covers R <= 48 (for float input with R > 32
+// its row pass reads global memory); larger R use the two passes.
+bool range_tile_ok(int R, bf_dtype dt) {
+  (void)dt;
+  return R >= 1 && R <= 48;
+}
 int range_tile_kr(int R) { return R <= 32 ? 32 : 48; }
 GroupGrid range_tile_grid(const Geom &g) { return GroupGrid{(g.W + kTileW - 1) / kTileW, (g.H + kTileH - 1) / kTileH, 1}; }
 template <typename Tin>
@@ -1457,7 +1507,7 @@ static hipError_t range_t(hipStream_t s, const Tin *f, const Geom &g, int R, Tin
     const size_t lds = range_tile_lds(R, dtype_of<Tin>());
     if (range_tile_kr(R) == 32)
       hipLaunchKernelGGL((k_range_tile<Tin, 32>), dim3(gt.gx, gt.gy), dim3(kTileThreads), lds, s, ta);
-    else if constexpr (!std::is_same<Tin, float>::value)
+    else
       hipLaunchKernelGGL((k_range_tile<Tin, 48>), dim3(gt.gx, gt.gy), dim3(kTileThreads), lds, s, ta);
     rec.end(BF_STAGE_RANGE, s);
     return hipGetLastError();
@@ -1503,10 +1553,8 @@ static hipError_t range_tile_group_t(hipStream_t s, int kr, const RangeTileArgs 
   if (total > 0) {
     if (kr == 32)
       hipLaunchKernelGGL((k_range_tile_grp<Tin, 32>), dim3(total), dim3(kTileThreads), lds, s, a, start, n);
-    else if constexpr (!std::is_same<Tin, float>::value)
-      hipLaunchKernelGGL((k_range_tile_grp<Tin, 48>), dim3(total), dim3(kTileThreads), lds, s, a, start, n);
     else
-      return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_range_tile_grp<Tin, 48>), dim3(total), dim3(kTileThreads), lds, s, a, start, n);
   }
   return hipGetLastError();
 }
