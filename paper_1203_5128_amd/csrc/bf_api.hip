@@ -488,7 +488,6 @@ struct GLaunch {
             // 5 one-launch range
   bf_dtype dt;
   int variant;
-  bool seq;
   int S, cC;
   int cnt;
   size_t o[10];
@@ -555,37 +554,34 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
       L.lds[0] = lds;
       bp.launches.push_back(L);
     }
-  for (bf_dtype dt : {BF_U8, BF_U16, BF_F32})
-    for (bool seq : {false, true}) {
-      std::vector<RowmaxArgs> ra;
-      std::vector<ColmaxArgs> ca;
-      std::vector<int> rb, cb;
-      for (int i : gidx) {
-        const ImagePlan &ip = pl->im[i];
-        if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || range_tile_ok(ip.R, dt) || range_col_seq(ip.R) != seq)
-          continue;
-        void *rm = (char *)pl->d_bws + pl->rowmax_off[i];
-        const GroupGrid gr = range_row_grid(ip.g), gc = range_col_grid(ip.g, ip.R);
-        ra.push_back(RowmaxArgs{gr, d_in[i], ip.g.pitch, ip.g.H, ip.g.W, ip.R, rm, state_of(ip)});
-        ca.push_back(ColmaxArgs{gc, d_in[i], ip.g.pitch, rm, ip.g.H, ip.g.W, ip.R, state_of(ip), ip.T_cap});
-        rb.push_back(gr.gx * gr.gy);
-        cb.push_back(gc.gx * gc.gy);
-      }
-      if (ra.empty()) continue;
-      const std::vector<int> rs = starts_of(rb), cs = starts_of(cb);
-      GLaunch L{};
-      L.kind = 1;
-      L.dt = dt;
-      L.seq = seq;
-      L.cnt = (int)ra.size();
-      L.o[0] = bp.pack.add(ra);
-      L.o[1] = bp.pack.add(rs);
-      L.o[2] = bp.pack.add(ca);
-      L.o[3] = bp.pack.add(cs);
-      L.t[0] = rs.back();
-      L.t[1] = cs.back();
-      bp.launches.push_back(L);
+  for (bf_dtype dt : {BF_U8, BF_U16, BF_F32}) {
+    std::vector<RowmaxArgs> ra;
+    std::vector<ColmaxArgs> ca;
+    std::vector<int> rb, cb;
+    for (int i : gidx) {
+      const ImagePlan &ip = pl->im[i];
+      if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || range_tile_ok(ip.R, dt)) continue;
+      void *rm = (char *)pl->d_bws + pl->rowmax_off[i];
+      const GroupGrid gr = range_row_grid(ip.g), gc = range_col_grid(ip.g);
+      ra.push_back(RowmaxArgs{gr, d_in[i], ip.g.pitch, ip.g.H, ip.g.W, ip.R, rm, state_of(ip)});
+      ca.push_back(ColmaxArgs{gc, d_in[i], ip.g.pitch, rm, ip.g.H, ip.g.W, ip.R, state_of(ip), ip.T_cap});
+      rb.push_back(gr.gx * gr.gy);
+      cb.push_back(gc.gx * gc.gy);
     }
+    if (ra.empty()) continue;
+    const std::vector<int> rs = starts_of(rb), cs = starts_of(cb);
+    GLaunch L{};
+    L.kind = 1;
+    L.dt = dt;
+    L.cnt = (int)ra.size();
+    L.o[0] = bp.pack.add(ra);
+    L.o[1] = bp.pack.add(rs);
+    L.o[2] = bp.pack.add(ca);
+    L.o[3] = bp.pack.add(cs);
+    L.t[0] = rs.back();
+    L.t[1] = cs.back();
+    bp.launches.push_back(L);
+  }
   for (bf_dtype dt : {BF_U8, BF_U16, BF_F32})
     for (int v = BF_BLUR_TOEPLITZ_F16; v <= BF_BLUR_TOEPLITZ_BF16X2; v++) {
       std::vector<ToepVArgs> va;
@@ -689,7 +685,7 @@ bf_status enqueue_batch(bf_plan_s *pl, int n, const void *const *d_in, float *co
       pl->rec.end(BF_STAGE_RANGE, s);
     } else if (L.kind == 1) {
       pl->rec.begin(BF_STAGE_RANGE, s);
-      e = launch_range_group(s, L.dt, L.seq, (const RowmaxArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]),
+      e = launch_range_group(s, L.dt, (const RowmaxArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]),
                              L.t[0], (const ColmaxArgs *)(d_args + L.o[2]), (const int *)(d_args + L.o[3]), L.t[1],
                              L.cnt);
       pl->rec.end(BF_STAGE_RANGE, s);

@@ -235,11 +235,10 @@ hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw
 // tile kernel when range_tile_ok(R, dt), else reset + row pass + column pass).
 hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,
                         DevState st, RangeAcc acc, int32_t T_cap, const StageRec &rec);
-// Grids of the range stage for one image and whether its column pass is the
-// sequential kind (windows taller than the LDS tile).
+// Grids of the two-pass range stage for one image (R > 48), and the
+// one-launch kernel's coverage.
 GroupGrid range_row_grid(const Geom &g);
-GroupGrid range_col_grid(const Geom &g, int R);
-bool range_col_seq(int R);
+GroupGrid range_col_grid(const Geom &g);
 bool range_tile_ok(int R, bf_dtype dt);
 int range_tile_kr(int R);  // staged-block size class (32 or 48) of a tile-kernel image
 GroupGrid range_tile_grid(const Geom &g);
@@ -248,8 +247,8 @@ hipError_t launch_range_tile_group(hipStream_t s, bf_dtype dt, int kr, const Ran
                                    int total, int n, size_t lds);
 // Grouped launches over n images (device argument arrays and block starts).
 hipError_t launch_reset_group(hipStream_t s, const ResetArgs *a, const int *start, int total, int n);
-hipError_t launch_range_group(hipStream_t s, bf_dtype dt, bool seq, const RowmaxArgs *ra, const int *rstart,
-                              int rtotal, const ColmaxArgs *ca, const int *cstart, int ctotal, int n);
+hipError_t launch_range_group(hipStream_t s, bf_dtype dt, const RowmaxArgs *ra, const int *rstart, int rtotal,
+                              const ColmaxArgs *ca, const int *cstart, int ctotal, int n);
 hipError_t launch_iir_chunk(hipStream_t s, bf_dtype dt, const void *f, float *out, const Geom &g,
                             DevTables tab, DevState st, const float *iir, int k0, int kcount,
                             float4 *Z, float2 *PQ, bool first, bool last, float2 *glut, const StageRec &rec);

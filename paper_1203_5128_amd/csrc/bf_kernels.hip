@@ -258,130 +258,11 @@ __global__ __launch_bounds__(64) void k_rowmax_grp(const RowmaxArgs *__restrict_
 }
 
 // ---------------------------------------- Algorithm 1, column pass and T
-// A workgroup takes 16 columns and a band of 64 output rows.  The band's row
-// maxima with R rows of halo above and below, and f over the band, are staged
-// in LDS (row stride 17 floats: a wave reading down a column hits distinct
-// banks).  Each wave then takes 4 columns and runs the segmented right and
-// left running maxima with its lanes along the column, exactly as the row
-// pass does along rows; T = max (out - f) (Prop. 2.1, sign read from its
-// proof) is reduced over the band.
-constexpr int kColBand = 64;
-constexpr int kColMaxR = 48;
-constexpr int kColW = 16;
-constexpr int kColStride = kColW + 1;
-
-template <typename Tin>
-__device__ __forceinline__ void colmax_T_body(const ColmaxArgs &a, const Blk b) {
-  const Tin *__restrict__ f = (const Tin *)a.f;
-  const int64_t pitch = a.pitch;
-  const Tin *__restrict__ rowmax = (const Tin *)a.rowmax;
-  const int H = a.H, W = a.W, R = a.R;
-  const DevState st = a.st;
-  const int32_t T_cap = a.T_cap;
-
-  __shared__ float tile[(kColBand + 2 * kColMaxR) * kColStride];
-  __shared__ float fb[kColBand * kColStride];
-  __shared__ float rr[4][4][kColBand];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wv = tid >> 6;
-  const int x0 = b.x * kColW;
-  const int y0 = b.y * kColBand;
-  const int nb = min(kColBand, H - y0);
-  const int L = nb + 2 * R;  // tile rows: y = y0 - R + e
-  for (int base = 0; base < L * kColW; base += 4 * 256) {
-    float vb[4];
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const int idx = base + u * 256 + tid;
-      const int e = idx >> 4, c = idx & 15;
-      const int y = y0 - R + e, x = x0 + c;
-      const float raw = fval(rowmax[(int64_t)min(max(y, 0), H - 1) * W + min(x, W - 1)]);
-      vb[u] = (idx < L * kColW && y >= 0 && y < H && x < W) ? raw : -INFINITY;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const int idx = base + u * 256 + tid;
-      if (idx < L * kColW) tile[(idx >> 4) * kColStride + (idx & 15)] = vb[u];
-    }
-  }
-  {
-    float vb[4];
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const int idx = u * 256 + tid;
-      const int i = idx >> 4, x = x0 + (idx & 15);
-      const float raw = fval(f[(int64_t)(y0 + min(i, nb - 1)) * pitch + min(x, W - 1)]);
-      vb[u] = (i < nb && x < W) ? raw : 0.f;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const int idx = u * 256 + tid;
-      fb[(idx >> 4) * kColStride + (idx & 15)] = vb[u];
-    }
-  }
-  __syncthreads();
-  const int Wd = 2 * R + 1;
-  const float inv = 1.0f / (float)Wd;
-  const int c0 = wv * 4;
-  // right running maxima for e < nb (bottom-up tiles), four columns at once
-  float carry[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
-  for (int e0 = ((L - 1) / 64) * 64; e0 >= 0; e0 -= 64) {
-    const int e = e0 + lane;
-    const int sege = e - mod_small(e, Wd, inv) + Wd - 1;
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      float v = e < L ? tile[e * kColStride + c0 + k] : -INFINITY;
-      v = seg_max_down(v, e, sege, lane);
-      if (e0 + 64 <= sege) v = fmaxf(v, carry[k]);
-      carry[k] = lane_value(v, 0);
-      if (e < nb) rr[wv][k][e] = v;
-    }
-  }
-  // left running maxima (top-down); output row i has window e in [i, i+2R]
-  double tmax = 0.0;
-#pragma unroll
-  for (int k = 0; k < 4; k++) carry[k] = -INFINITY;
-  for (int e0 = 0; e0 < L; e0 += 64) {
-    const int e = e0 + lane;
-    const int segs = e - mod_small(e, Wd, inv);
-    const int i = e - 2 * R;
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      float v = e < L ? tile[e * kColStride + c0 + k] : -INFINITY;
-      v = seg_max_up(v, e, segs, lane);
-      if (e0 > 0 && e0 - 1 >= segs) v = fmaxf(v, carry[k]);
-      carry[k] = lane_value(v, 63);
-      if (i >= 0 && i < nb && x0 + c0 + k < W) {
-        const double d = (double)fmaxf(rr[wv][k][i], v) - (double)fb[i * kColStride + c0 + k];
-        tmax = d > tmax ? d : tmax;
-      }
-    }
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    double o = __shfl_xor(tmax, off, 64);
-    tmax = o > tmax ? o : tmax;
-  }
-  __shared__ double wmax[4];
-  if (lane == 0) wmax[wv] = tmax;
-  __syncthreads();
-  if (tid == 0) publish_T(st, fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3])), T_cap);
-}
-template <typename Tin>
-__global__ __launch_bounds__(256) void k_colmax_T(ColmaxArgs a) {
-  colmax_T_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
-}
-template <typename Tin>
-__global__ __launch_bounds__(256) void k_colmax_T_grp(const ColmaxArgs *__restrict__ a,
-                                                      const int *__restrict__ start, int n) {
-  const int i = group_find(start, n, blockIdx.x);
-  colmax_T_body<Tin>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
-}
-
-// Same column pass for windows too tall for the LDS tile: one lane per column
-// walks the band (plus halo) bottom-up for the right running maxima and
-// top-down for the left ones, loading 16 rows ahead.
+// (R > 48; smaller windows take the one-launch kernel below).  One lane per
+// column walks a band of kColBandSeq output rows (plus the R halo) of the row
+// maxima bottom-up for the right running maxima and top-down for the left
+// ones, loading 16 rows ahead; T = max (out - f) (Prop. 2.1, sign read from
+// its proof) is reduced over the wave.
 constexpr int kColBandSeq = 128;
 
 template <typename Tin>
@@ -1471,11 +1352,7 @@ hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw
 // Grids of the range stage for one image (also the per-image grids of a
 // grouped launch).
 GroupGrid range_row_grid(const Geom &g) { return GroupGrid{(g.W + kRowSeg - 1) / kRowSeg, g.H, 1}; }
-GroupGrid range_col_grid(const Geom &g, int R) {
-  if (R <= kColMaxR) return GroupGrid{(g.W + kColW - 1) / kColW, (g.H + kColBand - 1) / kColBand, 1};
-  return GroupGrid{(g.W + 63) / 64, (g.H + kColBandSeq - 1) / kColBandSeq, 1};
-}
-bool range_col_seq(int R) { return R > kColMaxR; }
+GroupGrid range_col_grid(const Geom &g) { return GroupGrid{(g.W + 63) / 64, (g.H + kColBandSeq - 1) / kColBandSeq, 1}; }
 
 // The one-launch range kernel covers R <= 48 (for float input with R > 32
 // its row pass reads global memory); larger R use the two passes.
@@ -1515,36 +1392,30 @@ static hipError_t range_t(hipStream_t s, const Tin *f, const Geom &g, int R, Tin
   hipError_t e = launch_reset(s, st, 0, 0.0);
   if (e != hipSuccess) return e;
   rec.begin(BF_STAGE_RANGE, s);
-  const GroupGrid gr = range_row_grid(g), gc = range_col_grid(g, R);
+  const GroupGrid gr = range_row_grid(g), gc = range_col_grid(g);
   RowmaxArgs ra{gr, f, g.pitch, g.H, g.W, R, rowmax, st};
   hipLaunchKernelGGL(k_rowmax<Tin>, dim3(gr.gx, gr.gy), dim3(64), 0, s, ra);
   ColmaxArgs ca{gc, f, g.pitch, (const Tin *)rowmax, g.H, g.W, R, st, T_cap};
-  if (!range_col_seq(R))
-    hipLaunchKernelGGL(k_colmax_T<Tin>, dim3(gc.gx, gc.gy), dim3(256), 0, s, ca);
-  else
-    hipLaunchKernelGGL(k_colmax_T_seq<Tin>, dim3(gc.gx, gc.gy), dim3(64), 0, s, ca);
+  hipLaunchKernelGGL(k_colmax_T_seq<Tin>, dim3(gc.gx, gc.gy), dim3(64), 0, s, ca);
   rec.end(BF_STAGE_RANGE, s);
   return hipGetLastError();
 }
 
 // Grouped range stage: the row pass of every image, then the column pass of
-// every image (all of one kind: LDS-tiled or sequential).
+// every image.
 template <typename Tin>
-static hipError_t range_group_t(hipStream_t s, bool seq, const RowmaxArgs *ra, const int *rstart, int rtotal,
+static hipError_t range_group_t(hipStream_t s, const RowmaxArgs *ra, const int *rstart, int rtotal,
                                 const ColmaxArgs *ca, const int *cstart, int ctotal, int n) {
   if (rtotal > 0) hipLaunchKernelGGL(k_rowmax_grp<Tin>, dim3(rtotal), dim3(64), 0, s, ra, rstart, n);
-  if (ctotal > 0) {
-    if (!seq) hipLaunchKernelGGL(k_colmax_T_grp<Tin>, dim3(ctotal), dim3(256), 0, s, ca, cstart, n);
-    else hipLaunchKernelGGL(k_colmax_T_seq_grp<Tin>, dim3(ctotal), dim3(64), 0, s, ca, cstart, n);
-  }
+  if (ctotal > 0) hipLaunchKernelGGL(k_colmax_T_seq_grp<Tin>, dim3(ctotal), dim3(64), 0, s, ca, cstart, n);
   return hipGetLastError();
 }
-hipError_t launch_range_group(hipStream_t s, bf_dtype dt, bool seq, const RowmaxArgs *ra, const int *rstart,
-                              int rtotal, const ColmaxArgs *ca, const int *cstart, int ctotal, int n) {
+hipError_t launch_range_group(hipStream_t s, bf_dtype dt, const RowmaxArgs *ra, const int *rstart, int rtotal,
+                              const ColmaxArgs *ca, const int *cstart, int ctotal, int n) {
   switch (dt) {
-    case BF_U8: return range_group_t<uint8_t>(s, seq, ra, rstart, rtotal, ca, cstart, ctotal, n);
-    case BF_U16: return range_group_t<uint16_t>(s, seq, ra, rstart, rtotal, ca, cstart, ctotal, n);
-    default: return range_group_t<float>(s, seq, ra, rstart, rtotal, ca, cstart, ctotal, n);
+    case BF_U8: return range_group_t<uint8_t>(s, ra, rstart, rtotal, ca, cstart, ctotal, n);
+    case BF_U16: return range_group_t<uint16_t>(s, ra, rstart, rtotal, ca, cstart, ctotal, n);
+    default: return range_group_t<float>(s, ra, rstart, rtotal, ca, cstart, ctotal, n);
   }
 }
 template <typename Tin>

@@ -51,8 +51,10 @@ MIXED = [  # (seed, H, W, dtype, blur, sigma_s, sigma_r)
     (5, 64, 300, "u16", "toeplitz_bf16x2", 2.0, 25.0 * 257),
     (6, 120, 140, "u8", "iir_f32", 3.5, 30.0),
     (7, 33, 45, "u8", "toeplitz_f16x2", 1.5, 12.0),
-    (8, 180, 100, "u8", "toeplitz_f16x2", 16.0, 50.0),  # R = 48: sequential column pass of the range stage
+    (8, 180, 100, "u8", "toeplitz_f16x2", 16.0, 50.0),  # R = 48: the largest block of the one-launch range kernel
     (9, 90, 90, "f32", "toeplitz_f16", 6.0, 40.0),
+    (10, 100, 120, "f32", "iir_f32", 12.0, 30.0),  # R = 36 on float input: the range kernel's row pass reads global memory
+    (11, 110, 150, "u8", "toeplitz_f16x2", 17.0, 45.0),  # R = 51: reset, row pass and sequential column pass
 ]
 
 
