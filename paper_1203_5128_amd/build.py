@@ -41,8 +41,12 @@ def _run(cmd, verbose):
 
 
 def build(verbose: bool = False) -> str:
+    """Compile the translation units concurrently (at most MAX_JOBS or the CPU
+    count at once), then link."""
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    jobs = []
     for name, is_hip in SOURCES:
         src = os.path.join(CSRC, name)
         if not os.path.exists(src):
@@ -51,8 +55,12 @@ def build(verbose: bool = False) -> str:
         cmd = [HIPCC, "-c"] + (["-x", "hip"] if is_hip else []) + [src, "-o", obj] + COMMON
         if is_hip:
             cmd += DEVICE_FLAGS + EXTRA
-        _run(cmd, verbose)
-        objs.append(obj)
+        jobs.append((cmd, obj))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        for f in [pool.submit(_run, cmd, verbose) for cmd, _ in jobs]:
+            f.result()  # re-raises a failed compile
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)
