@@ -58,9 +58,12 @@ typedef enum {
   BF_T_LOCAL = 1   /* T from Algorithm 1 over the (2R+1)^2 square window          */
 } bf_trange;
 
-/* Spatial smoother of SHIFTABLE-BF step 3. */
+/* Implementation of the spatial smoothing of SHIFTABLE-BF step 3.  Each
+ * variant implements one discrete spatial operator (see bf_spatial). */
 typedef enum {
-  BF_BLUR_AUTO = 0,            /* autotuner picks among variants that meet the error gate */
+  BF_BLUR_AUTO = 0,            /* autotuner picks among the implementations of the
+                                  operator bf_params.spatial names that meet the error
+                                  gate; it never changes the operator itself             */
   BF_BLUR_IIR_F32 = 1,         /* Young-van Vliet recursive Gaussian, FP32 scans          */
   BF_BLUR_TOEPLITZ_F16 = 2,    /* FIR taps exp(-j^2/2 s^2), |j|<=R, FP16 MFMA, FP32 acc   */
   BF_BLUR_TOEPLITZ_BF16 = 3,   /* same FIR, BF16 MFMA, FP32 accumulation                  */
@@ -68,13 +71,21 @@ typedef enum {
   BF_BLUR_TOEPLITZ_BF16X2 = 5  /* same FIR, BF16 hi+lo split operands, FP32 accumulation  */
 } bf_blur;
 
-/* Spatial kernel of eq. (BF) (the filter smoothed by step 3). */
+/* Spatial kernel of eq. (BF) (the filter smoothed by step 3).  The paper
+ * leaves the discrete O(1) smoother open (Section 1.2); the operator is fixed
+ * by this field and by nothing else, so equal parameters give equal images
+ * whatever the autotuner picks. */
 typedef enum {
-  BF_SPATIAL_GAUSSIAN = 0, /* Gaussian of sigma_s (the recursive or the FIR form above)  */
-  BF_SPATIAL_BOX = 1       /* constant filter over the (2R+1)^2 square (Section 4, the
-                              comparison with integral histograms); R = radius, or
-                              round(sigma_s) when radius is 0.  Toeplitz variants only
-                              (unit taps); BF_BLUR_AUTO takes BF_BLUR_TOEPLITZ_F16X2. */
+  BF_SPATIAL_GAUSSIAN = 0,     /* Gaussian of sigma_s.  With BF_BLUR_IIR_F32 or
+                                  BF_BLUR_AUTO: the recursive Young-van Vliet filter.
+                                  With a Toeplitz variant: the sampled FIR below (the
+                                  variant names the operator).                          */
+  BF_SPATIAL_BOX = 1,          /* constant filter over the (2R+1)^2 square (Section 4, the
+                                  comparison with integral histograms); R = radius, or
+                                  round(sigma_s) when radius is 0.  Toeplitz variants only
+                                  (unit taps).                                           */
+  BF_SPATIAL_GAUSSIAN_FIR = 2  /* sampled Gaussian taps exp(-j^2/2 sigma_s^2), |j| <= R.
+                                  Toeplitz variants only; BF_BLUR_AUTO picks among them. */
 } bf_spatial;
 
 typedef struct {
@@ -118,7 +129,7 @@ typedef struct bf_plan_s *bf_plan_t;
  * Errors: BF_ERR_INVALID_ARG (bad params, n_images < 1, NULL pointers),
  * BF_ERR_UNSUPPORTED (order beyond the build limits; width or height above
  * 8192 for the recursive blur; radius above 120 for the Toeplitz blur; the
- * box spatial filter with the recursive blur),
+ * box or sampled-FIR spatial filter with the recursive blur),
  * BF_ERR_OUT_OF_MEMORY, BF_ERR_DEVICE.  On error *out is set to NULL. */
 bf_status bf_plan(const bf_params *params, int32_t n_images, bf_plan_t *out);
 

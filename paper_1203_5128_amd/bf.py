@@ -117,7 +117,7 @@ def _check(status: int):
         raise BFError(status, bf_last_error_detail())
 
 
-SPATIALS = {"gaussian": 0, "box": 1}
+SPATIALS = {"gaussian": 0, "box": 1, "gaussian_fir": 2}
 
 
 def make_params(H, W, dtype="u8", sigma_s=3.0, sigma_r=30.0, eps=1e-3, radius=0, t_mode="local",
@@ -193,19 +193,51 @@ def bf_plan_destroy(plan: int):
 
 
 # ----------------------------------------------------------- torch helpers
+_TORCH_DTYPES = {BF_U8: ("uint8",), BF_U16: ("uint16", "int16"), BF_F32: ("float32",)}
+
+
+def _check_tensor(name, t, H, W, pitch, dts):
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dim() != 2 or tuple(t.shape) != (H, W):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, the plan expects ({H}, {W})")
+    if str(t.dtype).replace("torch.", "") not in dts:
+        raise ValueError(f"{name} has dtype {t.dtype}, the plan expects {' or '.join(dts)}")
+    if t.stride(1) != 1 or (H > 1 and t.stride(0) != (pitch if pitch > 0 else W)):
+        raise ValueError(f"{name} strides {t.stride()} do not match the plan's pitch "
+                         f"({pitch if pitch > 0 else W} elements per row, unit column stride)")
+
+
+def check_tensors(p: bf_params, img, out=None):
+    """The buffers handed to the C ABI must be what the plan's parameters
+    describe: the library reads H x W elements of the input type with the
+    plan's pitch and writes float32 with the output pitch, so a wrong shape,
+    dtype, stride or device would be read or written out of place.  Raises
+    ValueError on any mismatch (nothing is launched)."""
+    _check_tensor("input", img, p.height, p.width, p.in_pitch, _TORCH_DTYPES[p.dtype])
+    if out is not None:
+        _check_tensor("output", out, p.height, p.width, p.out_pitch, ("float32",))
+        if img.device != out.device:
+            raise ValueError("input and output are on different devices")
+
+
 @dataclass
 class Plan:
     """Owns a plan handle; images are torch tensors on the GPU."""
     handle: int
+    params: tuple = ()
 
     @classmethod
     def create(cls, params):
-        return cls(bf_plan(params))
+        plist = [params] if isinstance(params, bf_params) else list(params)
+        return cls(bf_plan(plist), tuple(plist))
 
     def filter(self, img, out=None, stream=None, report=True):
         import torch
         if out is None:
             out = torch.empty(img.shape, dtype=torch.float32, device=img.device)
+        if self.params:
+            check_tensors(self.params[0], img, out)
         rep = bf_filter(self.handle, img.data_ptr(), out.data_ptr(), stream, report)
         return out, rep
 
@@ -213,6 +245,11 @@ class Plan:
         import torch
         if outs is None:
             outs = [torch.empty(i.shape, dtype=torch.float32, device=i.device) for i in imgs]
+        if len(imgs) != len(outs) or (self.params and len(imgs) > len(self.params)):
+            raise ValueError("the number of inputs and outputs must match and not exceed the plan's images")
+        for i, (a, b) in enumerate(zip(imgs, outs)):
+            if self.params:
+                check_tensors(self.params[i], a, b)
         reps = bf_filter_batch(self.handle, [i.data_ptr() for i in imgs], [o.data_ptr() for o in outs],
                                stream, report)
         return outs, reps
@@ -224,6 +261,8 @@ class Plan:
         return bf_profile_read(self.handle)
 
     def dynamic_range(self, img, stream=None):
+        if self.params:
+            check_tensors(self.params[0], img)
         return bf_dynamic_range(self.handle, img.data_ptr(), stream)
 
     def close(self):

@@ -28,7 +28,6 @@ EXTRA = os.environ.get("BF_HIPCC_EXTRA", "").split()
 SOURCES = [
     ("bf_tables.cpp", False),
     ("bf_kernels.hip", True),
-    ("bf_batch.hip", True),
     ("bf_toeplitz.hip", True),
     ("bf_api.hip", True),
 ]
@@ -50,7 +49,7 @@ def build(verbose: bool = False) -> str:
     for name, is_hip in SOURCES:
         src = os.path.join(CSRC, name)
         if not os.path.exists(src):
-            continue
+            raise FileNotFoundError(f"translation unit {src} is missing")
         obj = os.path.join(BUILD, name + ".o")
         cmd = [HIPCC, "-c"] + (["-x", "hip"] if is_hip else []) + [src, "-o", obj] + COMMON
         if is_hip:

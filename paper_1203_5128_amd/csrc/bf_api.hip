@@ -177,11 +177,21 @@ bf_status check_params(const bf_params &p) {
   if (p.value_range < 0.0 || !std::isfinite(p.value_range))
     return fail(BF_ERR_INVALID_ARG, "value_range must be >= 0");
   if (p.blur < BF_BLUR_AUTO || p.blur > BF_BLUR_TOEPLITZ_BF16X2) return fail(BF_ERR_INVALID_ARG, "unknown blur");
-  if (p.spatial != BF_SPATIAL_GAUSSIAN && p.spatial != BF_SPATIAL_BOX)
+  if (p.spatial != BF_SPATIAL_GAUSSIAN && p.spatial != BF_SPATIAL_BOX && p.spatial != BF_SPATIAL_GAUSSIAN_FIR)
     return fail(BF_ERR_INVALID_ARG, "unknown spatial kernel");
   if (p.spatial == BF_SPATIAL_BOX && p.blur == BF_BLUR_IIR_F32)
     return fail(BF_ERR_UNSUPPORTED, "the box spatial filter runs on the Toeplitz blur variants");
+  if (p.spatial == BF_SPATIAL_GAUSSIAN_FIR && p.blur == BF_BLUR_IIR_F32)
+    return fail(BF_ERR_UNSUPPORTED, "the sampled FIR Gaussian runs on the Toeplitz blur variants");
   return BF_OK;
+}
+
+// The discrete spatial operator an image is filtered with: the recursive
+// Gaussian, or taps on the Toeplitz kernels (sampled Gaussian or box).  Fixed
+// by the parameters alone; the autotuner only chooses among implementations
+// of it.
+bool fir_operator(const bf_params &p) {
+  return p.spatial != BF_SPATIAL_GAUSSIAN || (p.blur != BF_BLUR_AUTO && p.blur != BF_BLUR_IIR_F32);
 }
 
 // Window radius R: the given radius, else ceil(3 sigma_s) for the Gaussian
@@ -193,9 +203,22 @@ int window_radius(const bf_params &p) {
   return (int)std::ceil(3.0 * p.sigma_s);
 }
 
+// Every device allocation of a plan goes through here.  BF_FAIL_ALLOC set in
+// the environment makes it fail before calling HIP (a test hook for the
+// out-of-memory path).
+bf_status dev_alloc(void **dst, size_t bytes, const char *what) {
+  if (std::getenv("BF_FAIL_ALLOC")) {
+    *dst = nullptr;
+    return fail(BF_ERR_OUT_OF_MEMORY, std::string("allocation failure requested by BF_FAIL_ALLOC: ") + what);
+  }
+  hipError_t e = hipMalloc(dst, bytes);
+  return e == hipSuccess ? BF_OK : dev_fail(e, what);
+}
+
 bf_status upload(void **dst, const void *src, size_t bytes) {
-  hipError_t e = hipMalloc(dst, bytes ? bytes : 16);
-  if (e != hipSuccess) return dev_fail(e, "hipMalloc(table)");
+  bf_status st = dev_alloc(dst, bytes ? bytes : 16, "hipMalloc(table)");
+  if (st) return st;
+  hipError_t e;
   if (bytes) {
     e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) return dev_fail(e, "hipMemcpy(table)");
@@ -226,11 +249,12 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   ip.T_cap = (int32_t)cap;
   ip.T_global = (int32_t)std::ceil(Tg);
   ip.T_global_raw = Tg;
+  const bool fir = fir_operator(p);
   int variant = kn.variant ? kn.variant
-                           : (p.blur != BF_BLUR_AUTO ? p.blur : (box ? BF_BLUR_TOEPLITZ_F16X2 : BF_BLUR_IIR_F32));
+                           : (p.blur != BF_BLUR_AUTO ? p.blur : (fir ? BF_BLUR_TOEPLITZ_F16X2 : BF_BLUR_IIR_F32));
   ip.variant = variant;
-  if (box && !is_toeplitz(variant))
-    return fail(BF_ERR_UNSUPPORTED, "the box spatial filter runs on the Toeplitz blur variants");
+  if (fir != is_toeplitz(variant))
+    return fail(BF_ERR_UNSUPPORTED, "blur variant does not implement the requested spatial operator");
   if (!is_toeplitz(variant) && (p.width > kMaxWidth || p.height > kMaxWidth))
     return fail(BF_ERR_UNSUPPORTED, "width or height above 8192 for the recursive blur");
   if (is_toeplitz(variant) && !toeplitz_shape(variant, ip.R, p.height, kn.lds_kb, ip.tc))
@@ -351,9 +375,8 @@ bf_status ensure(void **ptr, size_t &have, size_t need) {
   if (*ptr) (void)hipFree(*ptr);
   *ptr = nullptr;
   have = 0;
-  if (std::getenv("BF_FAIL_ALLOC")) return fail(BF_ERR_OUT_OF_MEMORY, "allocation failure requested by BF_FAIL_ALLOC");
-  hipError_t e = hipMalloc(ptr, need);
-  if (e != hipSuccess) return dev_fail(e, "hipMalloc(workspace)");
+  bf_status st = dev_alloc(ptr, need, "hipMalloc(workspace)");
+  if (st) return st;
   have = need;
   return BF_OK;
 }
@@ -743,8 +766,9 @@ bf_status run_batch_graph(bf_plan_s *pl, int n, const void *const *d_in, float *
   BatchPlan bp;
   build_batch(pl, n, d_in, d_out, bp);
   void *d_args = nullptr;
-  hipError_t e = hipMalloc(&d_args, std::max<size_t>(bp.pack.buf.size(), 256));
-  if (e != hipSuccess) return dev_fail(e, "hipMalloc(batch arguments)");
+  bf_status ast = dev_alloc(&d_args, std::max<size_t>(bp.pack.buf.size(), 256), "hipMalloc(batch arguments)");
+  if (ast) return ast;
+  hipError_t e = hipSuccess;
   if (!bp.pack.buf.empty()) e = hipMemcpy(d_args, bp.pack.buf.data(), bp.pack.buf.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !pl->cap_stream) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
@@ -1034,14 +1058,16 @@ bf_status bf_dynamic_range(bf_plan_t pl, const void *d_in, void *hip_stream, dou
 }  // extern "C"
 
 // ------------------------------------------------------------- autotuner
-// BF_BLUR_AUTO: among the variants whose worst error over the parity suite
-// (adversarial noise included) stays within the 2e-3 target -- the FP32
-// recursive blur and the split-FP16 Toeplitz blur -- and their tile choices
-// (horizontal chunk of the recursive pass, LDS budget of the Toeplitz
-// vertical tile), take the fastest on this device at the image's shape and
-// dtype with every pair kept (T at the full range).  Choices are cached in
-// the process and, when BF_TUNE_CACHE names a file, in that file (one JSON
-// object per line).
+// BF_BLUR_AUTO: among the implementations of the image's spatial operator
+// whose worst error over the parity suite (adversarial noise included) stays
+// within the 2e-3 target -- for the recursive Gaussian the FP32 recursive
+// blur with either horizontal chunk width, for the FIR operators (sampled
+// Gaussian, box) the split-FP16 Toeplitz blur with either LDS budget of its
+// vertical tile -- take the fastest on this device at the image's shape and
+// dtype with every pair kept (T at the full range).  The operator itself is
+// never changed, so the output does not depend on the choice beyond rounding.
+// Choices are cached in the process and, when BF_TUNE_CACHE names a file, in
+// that file (one JSON object per line).
 namespace {
 
 std::mutex g_tune_mu;
@@ -1131,22 +1157,23 @@ bf_status autotune(const bf_params &p, Knobs &best) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load();
     auto it = g_tune.find(key);
-    if (it != g_tune.end()) {
+    if (it != g_tune.end() && is_toeplitz(it->second.variant) == fir_operator(p)) {
       best = it->second;
       return BF_OK;
     }
   }
   std::vector<Knobs> cand;
   const int R = window_radius(p);
-  if (p.width <= kMaxWidth && p.height <= kMaxWidth && p.sigma_s >= 0.5 && p.spatial != BF_SPATIAL_BOX) {
+  if (!fir_operator(p)) {
+    if (p.width > kMaxWidth || p.height > kMaxWidth)
+      return fail(BF_ERR_UNSUPPORTED, "width or height above 8192 for the recursive blur");
     cand.push_back(Knobs{BF_BLUR_IIR_F32, kCSmall, 0});
-    if (p.width > kCSmall) cand.push_back(Knobs{BF_BLUR_IIR_F32, kCLarge, 0});
-  }
-  if (R <= 120) {
+    if (p.width > kCSmall && p.width <= kCSmall * kHThreads) cand.push_back(Knobs{BF_BLUR_IIR_F32, kCLarge, 0});
+  } else {
+    if (R > 120) return fail(BF_ERR_UNSUPPORTED, "radius above 120 for the Toeplitz blur");
     cand.push_back(Knobs{BF_BLUR_TOEPLITZ_F16X2, 0, kToepLdsMax / 2048 - 2});
     cand.push_back(Knobs{BF_BLUR_TOEPLITZ_F16X2, 0, kToepDynMax / 1024});
   }
-  if (cand.empty()) return fail(BF_ERR_UNSUPPORTED, "no blur variant supports these parameters");
   if (cand.size() == 1) {
     best = cand[0];
     return BF_OK;
@@ -1192,11 +1219,11 @@ bf_status autotune(const bf_params &p, Knobs &best) {
   return BF_OK;
 }
 
-// Batch-level choice: a batch runs one set of grouped launches per variant
-// class, so a mix of classes can lose to putting every image on one class
-// (fuller launches).  The per-image choice and the two single-class
-// assignments are timed on the whole batch (full-range checkerboards, every
-// pair kept) and the fastest kept.
+// Batch-level choice: a batch runs one set of grouped launches per kernel
+// instantiation, so a mix of tile choices can lose to giving every image of
+// an operator the same one (fuller launches).  The per-image choice and the
+// uniform default choice (each image keeps its operator) are timed on the
+// whole batch (full-range checkerboards, every pair kept) and the faster kept.
 double time_batch(const bf_params *params, int n, const std::vector<Knobs> &kn, std::vector<void *> &ins,
                   std::vector<float *> &outs, hipStream_t s, hipEvent_t a, hipEvent_t b) {
   std::vector<bf_params> q(params, params + n);
@@ -1236,28 +1263,20 @@ double time_batch(const bf_params *params, int n, const std::vector<Knobs> &kn, 
 }
 
 void autotune_batch(const bf_params *params, int n, std::vector<Knobs> &kn) {
-  // candidates: the per-image choice, every tuned image on the split-FP16
-  // Toeplitz path, every tuned image on the FP32 recursive path (each class
-  // then runs as one set of grouped launches)
+  // candidates: the per-image choice, and every tuned image on the default
+  // implementation of its own operator (one set of grouped launches each)
   std::vector<std::vector<Knobs>> cand(1, kn);
-  for (int v : {(int)BF_BLUR_TOEPLITZ_F16X2, (int)BF_BLUR_IIR_F32}) {
+  {
     std::vector<Knobs> alt = kn;
-    bool differs = false, ok = true;
+    bool differs = false;
     for (int i = 0; i < n; i++) {
-      if (params[i].blur != BF_BLUR_AUTO || kn[i].variant == v) continue;
-      const int R = window_radius(params[i]);
-      const bool fits = v == BF_BLUR_TOEPLITZ_F16X2
-                            ? R <= 120
-                            : (params[i].width <= kMaxWidth && params[i].height <= kMaxWidth &&
-                               params[i].sigma_s >= 0.5 && params[i].spatial != BF_SPATIAL_BOX);
-      if (!fits) {
-        ok = false;
-        break;
-      }
-      alt[i] = Knobs{v, v == BF_BLUR_IIR_F32 ? kCSmall : 0, 0};
-      differs = true;
+      if (params[i].blur != BF_BLUR_AUTO) continue;
+      const Knobs d = fir_operator(params[i]) ? Knobs{BF_BLUR_TOEPLITZ_F16X2, 0, kToepLdsMax / 2048 - 2}
+                                              : Knobs{BF_BLUR_IIR_F32, kCSmall, 0};
+      if (d.variant != kn[i].variant || d.hchunk != kn[i].hchunk || d.lds_kb != kn[i].lds_kb) differs = true;
+      alt[i] = d;
     }
-    if (ok && differs) cand.push_back(alt);
+    if (differs) cand.push_back(alt);
   }
   if (cand.size() == 1) return;
   std::vector<void *> ins(n, nullptr);
@@ -1284,7 +1303,7 @@ void autotune_batch(const bf_params *params, int n, std::vector<Knobs> &kn) {
       const double t = time_batch(params, n, cand[c], ins, outs, s, a, b);
       if (std::getenv("BF_TUNE_LOG"))
         std::fprintf(stderr, "[bf tune] batch of %d, assignment %zu (%s): %.3f ms\n", n, c,
-                     c == 0 ? "per-image choice" : (c == 1 ? "all split-FP16 Toeplitz" : "all FP32 recursive"), t);
+                     c == 0 ? "per-image choice" : "default implementation per operator", t);
       if (t > 0.0 && (best < 0.0 || t < best)) {
         best = t;
         pick = c;

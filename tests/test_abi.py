@@ -81,3 +81,73 @@ def test_box_spatial_filter_needs_a_toeplitz_variant():
     st = bf.lib().bf_plan(ctypes.byref(p), 1, ctypes.byref(h))
     assert st == bf.BF_ERR_UNSUPPORTED and h.value is None
     assert "box" in bf.bf_last_error_detail()
+
+
+class _FakeTensor:
+    """Stands in for a torch GPU tensor in the CPU tests of the binding's
+    argument checks (shape, dtype, strides, device)."""
+
+    def __init__(self, shape, dtype="uint8", strides=None, cuda=True, device="cuda:0"):
+        self.shape = tuple(shape)
+        self.dtype = f"torch.{dtype}"
+        self._st = strides or (shape[1], 1)
+        self.is_cuda = cuda
+        self.device = device
+
+    def dim(self):
+        return len(self.shape)
+
+    def stride(self, i=None):
+        return self._st if i is None else self._st[i]
+
+
+@pytest.mark.parametrize("img,out,ok", [
+    (dict(shape=(20, 30)), dict(shape=(20, 30), dtype="float32"), True),
+    (dict(shape=(20, 30), strides=(40, 1)), dict(shape=(20, 30), dtype="float32"), False),   # pitch 40 != 30
+    (dict(shape=(30, 20), strides=(20, 1)), dict(shape=(20, 30), dtype="float32"), False),   # transposed shape
+    (dict(shape=(20, 30), strides=(1, 20)), dict(shape=(20, 30), dtype="float32"), False),   # transposed view
+    (dict(shape=(20, 30), dtype="int32"), dict(shape=(20, 30), dtype="float32"), False),     # wrong dtype
+    (dict(shape=(20, 30), cuda=False), dict(shape=(20, 30), dtype="float32"), False),        # host tensor
+    (dict(shape=(20, 30)), dict(shape=(20, 31), dtype="float32"), False),                   # output shape
+    (dict(shape=(20, 30)), dict(shape=(20, 30), dtype="float16"), False),                   # output dtype
+    (dict(shape=(20, 30)), dict(shape=(20, 30), dtype="float32", device="cuda:1"), False),  # devices differ
+])
+def test_binding_checks_tensors_before_the_abi(img, out, ok):
+    p = bf.make_params(20, 30, "u8")
+    a, b = _FakeTensor(**img), _FakeTensor(**out)
+    if ok:
+        bf.check_tensors(p, a, b)
+    else:
+        with pytest.raises(ValueError):
+            bf.check_tensors(p, a, b)
+
+
+def test_binding_checks_pitched_views():
+    p = bf.make_params(20, 30, "u16", in_pitch=48, out_pitch=32)
+    bf.check_tensors(p, _FakeTensor((20, 30), "uint16", (48, 1)), _FakeTensor((20, 30), "float32", (32, 1)))
+    with pytest.raises(ValueError):
+        bf.check_tensors(p, _FakeTensor((20, 30), "uint16", (30, 1)), _FakeTensor((20, 30), "float32", (32, 1)))
+
+
+def test_allocation_failure_hook(monkeypatch):
+    """With BF_FAIL_ALLOC set every device allocation of a plan fails before
+    HIP is called: bf_plan returns BF_ERR_OUT_OF_MEMORY and no plan, with no
+    launch (no device is needed to reach it)."""
+    monkeypatch.setenv("BF_FAIL_ALLOC", "1")
+    for blur in ("iir_f32", "toeplitz_f16x2"):
+        p = bf.make_params(64, 48, "u8", sigma_s=2.0, sigma_r=20.0, blur=blur)
+        h = ctypes.c_void_p(123)
+        st = bf.lib().bf_plan(ctypes.byref(p), 1, ctypes.byref(h))
+        assert st == bf.BF_ERR_OUT_OF_MEMORY, bf.bf_last_error_detail()
+        assert h.value is None
+        assert "BF_FAIL_ALLOC" in bf.bf_last_error_detail()
+
+
+@pytest.mark.parametrize("spatial,blur", [("gaussian_fir", "iir_f32"), ("box", "iir_f32")])
+def test_operator_and_variant_must_agree(spatial, blur):
+    """The spatial operator is a parameter; a blur variant that implements
+    another operator is refused before any device work."""
+    p = bf.make_params(16, 16, "u8", sigma_s=2.0, sigma_r=20.0, blur=blur, spatial=spatial)
+    h = ctypes.c_void_p(123)
+    st = bf.lib().bf_plan(ctypes.byref(p), 1, ctypes.byref(h))
+    assert st == bf.BF_ERR_UNSUPPORTED and h.value is None

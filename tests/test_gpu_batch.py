@@ -170,28 +170,31 @@ def test_workload5_batch64_grouped_sampled():
     print(f"[batch] workload5 64 images sampled max={worst:.3e}", flush=True)
 
 
-def test_autotune_picks_a_gated_variant_and_caches(tmp_path):
-    """BF_BLUR_AUTO takes the fastest of the variants that meet the 2e-3
-    target (FP32 recursive, split-FP16 Toeplitz); the output matches the
-    oracle run with the chosen operator, and the choice is written to and
-    read back from the cache file."""
+@pytest.mark.parametrize("spatial,variants,op", [("gaussian", ("iir_f32",), "iir"),
+                                                  ("gaussian_fir", ("toeplitz_f16x2",), "fir")])
+def test_autotune_keeps_the_operator_and_caches(tmp_path, spatial, variants, op):
+    """BF_BLUR_AUTO takes the fastest implementation of the operator the
+    parameters name (recursive Gaussian: FP32 recursive blur, either chunk
+    width; sampled FIR Gaussian: split-FP16 Toeplitz, either tile budget); the
+    output matches the oracle run with that operator, whatever was chosen, and
+    the choice is written to and read back from the cache file."""
     torch = _torch()
     from paper_1203_5128_amd import Plan, make_params
     cache = tmp_path / "tune.jsonl"
     os.environ["BF_TUNE_CACHE"] = str(cache)
     try:
         img = gen_random(61, 200, 330, dtype="u8")
-        p = make_params(200, 330, "u8", sigma_s=4.0, sigma_r=20.0, eps=1e-3, blur="auto")
+        p = make_params(200, 330, "u8", sigma_s=4.0, sigma_r=20.0, eps=1e-3, blur="auto", spatial=spatial)
         plan = Plan.create(p)
         out, rep = plan.filter(torch.from_numpy(img).to("cuda"))
         torch.cuda.synchronize()
         plan.close()
-        assert rep["variant"] in ("iir_f32", "toeplitz_f16x2")
+        assert rep["variant"] in variants
         lines = cache.read_text().strip().splitlines()
         assert len(lines) == 1 and '"key": ' in lines[0]
-        ref = _oracle(img, "u8", rep["variant"], 4.0, 20.0, 1e-3, 12)
+        ref = o.algorithm2(img.astype(np.float64), op, 4.0, 12, 20.0, 1e-3, 255.0, True)
         err = np.abs(out.cpu().numpy().astype(np.float64) - ref["out"]).max()
-        print(f"[tune] chose {rep['variant']} max={err:.3e} ({lines[0]})", flush=True)
+        print(f"[tune] {spatial} chose {rep['variant']} max={err:.3e} ({lines[0]})", flush=True)
         assert err <= 2e-3
         plan2 = Plan.create(p)  # served from the cache: no new line
         _, rep2 = plan2.filter(torch.from_numpy(img).to("cuda"))
@@ -209,14 +212,15 @@ def test_autotuned_batch_uneven():
     torch = _torch()
     from paper_1203_5128_amd import Plan, make_params
     items = [(im[:min(im.shape[0], 300), :min(im.shape[1], 280)].copy(), ss, sr) for im, ss, sr in batch_images(6)]
-    params = [make_params(im.shape[0], im.shape[1], "u8", sigma_s=ss, sigma_r=sr, eps=1e-3, blur="auto")
-              for im, ss, sr in items]
+    spat = ["gaussian" if i % 2 else "gaussian_fir" for i in range(len(items))]
+    params = [make_params(im.shape[0], im.shape[1], "u8", sigma_s=ss, sigma_r=sr, eps=1e-3, blur="auto",
+                          spatial=sp) for (im, ss, sr), sp in zip(items, spat)]
     plan = Plan.create(params)
     outs, reps = plan.filter_batch([torch.from_numpy(im).to("cuda") for im, _, _ in items])
     torch.cuda.synchronize()
     plan.close()
-    for (im, ss, sr), out, rep in zip(items, outs, reps):
-        assert rep["variant"] in ("iir_f32", "toeplitz_f16x2")
+    for (im, ss, sr), out, rep, sp in zip(items, outs, reps, spat):
+        assert rep["variant"] == ("iir_f32" if sp == "gaussian" else "toeplitz_f16x2")
         ref = _oracle(im, "u8", rep["variant"], ss, sr, 1e-3, int(np.ceil(3 * ss)))
         err = np.abs(out.cpu().numpy().astype(np.float64) - ref["out"]).max()
         print(f"[tune] batch {im.shape} ss={ss:.2f} sr={sr:.2f} -> {rep['variant']} max={err:.3e}", flush=True)

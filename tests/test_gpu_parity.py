@@ -142,6 +142,15 @@ def test_widths_and_cross_wave_scan(width):
     compare(img, "u8", 3.0, 30.0, 1e-3, label=f"W={width}")
 
 
+@pytest.mark.parametrize("shape", [(4097, 40), (6000, 64), (8192, 33), (24, 8192)])
+def test_recursive_path_size_limits(shape):
+    """Heights above 4096 take the vertical instantiation with 256 threads per
+    column (one column per row group of the recursive scan); 8192 rows or
+    columns is the declared limit of the recursive blur."""
+    img = gen_random(shape[0] + 7 * shape[1], *shape, dtype="u8")
+    compare(img, "u8", 2.0, 25.0, 1e-3, label=f"limit {shape}")
+
+
 def test_global_mode_original_shiftable():
     img = gen_random(5, 80, 90, dtype="u8")
     compare(img, "u8", 3.0, 30.0, 1e-3, t_mode="global", t_value=255.0, label="global")
@@ -215,7 +224,9 @@ def test_pitched_buffers():
     plan = Plan.create(make_params(45, 70, "u8", sigma_s=2.0, sigma_r=20.0, in_pitch=96, out_pitch=80))
     tin = torch.from_numpy(big).to("cuda")
     tout = torch.full((45, 80), -7.0, device="cuda")
-    plan.filter(tin, tout)
+    with pytest.raises(ValueError):  # the whole padded buffer is not a 45 x 70 image
+        plan.filter(tin, tout)
+    plan.filter(tin[:, :70], tout[:, :70])
     torch.cuda.synchronize()
     plan.close()
     ref, _ = run_gpu(img, "u8", sigma_s=2.0, sigma_r=20.0, eps=1e-3)

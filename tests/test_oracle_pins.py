@@ -79,6 +79,38 @@ def test_chernoff_rule_is_conservative(eps):
             assert M <= o.exact_trunc(N, eps)
 
 
+@pytest.mark.parametrize("eps", [0.05, 1e-2, 1e-3, 1e-4, 1e-6])
+def test_chernoff_rule_sets_the_bound_to_half_eps(eps):
+    """Eq. (Chernoff) comes from setting the Chernoff bound
+    exp(-(N - 2M)^2 / (4N)) of the binomial tail equal to eps/2 (Section 3):
+    M is the largest non-negative integer whose bound is <= eps/2, so the
+    bound at M holds and the bound at M + 1 would fail.  A natural log, the
+    eps/2 budget and rounding down are each fixed by this; log(1/eps),
+    log10, or rounding up fail it for some N of the sweep."""
+    def bound(N, M):
+        return math.exp(-((N - 2 * M) ** 2) / (4.0 * N))
+    for N in list(range(1, 400)) + [411, 500, 1053, 1582, 2718, 2929, 5000]:
+        M = o.trunc_chernoff(N, eps)
+        assert 0 <= M <= N // 2
+        if M > 0:
+            assert bound(N, M) <= eps / 2, (N, M)
+        else:  # M = 0 is the clamp when even M = 0 misses the bound, or the largest fit
+            assert bound(N, 0) <= eps / 2 or 2 * math.sqrt(N * math.log(2 / eps)) >= N
+        if N - 2 * (M + 1) >= 0:
+            assert bound(N, M + 1) > eps / 2, (N, M)
+
+
+def test_chernoff_rule_worked_values():
+    """Worked values of eq. (Chernoff) at the Fig. 1 setting, from the closed
+    form by hand: N = 263, eps = 0.01 gives (263 - sqrt(4 263 ln 200))/2
+    = (263 - 74.67...)/2 = 94.16..., so M = 94 and N - 2M + 1 = 76 kept terms
+    (the exact rule keeps 42: the estimate is conservative)."""
+    v = 0.5 * (263 - math.sqrt(4 * 263 * math.log(200.0)))
+    assert 94.0 < v < 94.5
+    assert o.trunc_chernoff(263, 0.01) == 94
+    assert o.trunc_exact(263, 0.01) == 111
+
+
 def test_band_rule_selects_per_sigma_r():
     N = 263
     assert o.trunc_rule(N, 41.0, 1e-3) == 0
@@ -271,6 +303,54 @@ def test_shiftable_equals_direct(H, W, kind, op):
     ref = o.direct_bf_dense(f, Sv, Sh, o.phi_eps_vec(N, M, sr))
     assert bad == 0
     assert np.allclose(out, ref, rtol=1e-9, atol=1e-9 * 255)
+
+
+def qneg_image(H=100, W=131, bg=200.0, spot=60.0):
+    """Background `bg` with isolated pixels of value `spot` every 32 rows and
+    33 columns: at sigma_r = 25, eps = 0.05 and T = 255 the truncated kernel
+    phi_eps (eq. (approx)) dips to about -0.021 at the difference 140, so the
+    denominator (f2) of each isolated pixel is its own weight phi_eps(0) ~ 1
+    minus about 0.021 times the rest of the spatial mass: negative for
+    sigma_s >= 3 (Section 3 allows overshoots down to -eps)."""
+    f = np.full((H, W), bg)
+    ys, xs = np.meshgrid(np.arange(10, H, 32), np.arange(12, W, 33), indexing="ij")
+    f[ys, xs] = spot
+    return f, ys.ravel(), xs.ravel()
+
+
+@pytest.mark.parametrize("op", ["fir", "iir", "box"])
+def test_nonpositive_denominator_fallback(op):
+    """Where the denominator (f2) is not positive the output is the input pixel
+    and the pixel is counted.  The pixels so counted are exactly those where
+    eq. (BF) evaluated directly (materialised operator, same phi_eps) has a
+    non-positive denominator, on a crop small enough for the dense form."""
+    sr, eps, ss = 25.0, 0.05, 4.0
+    R = 12
+    N = o.order(255.0, sr)
+    M = o.trunc_rule(N, sr, eps)
+    assert (N, M) == (42, 15)
+    k = o.phi_eps_vec(N, M, sr)
+    assert k(np.array([140.0]))[0] < -0.02
+    f, ys, xs = qneg_image(30, 58)
+    out, P, Q, bad = o.shiftable_bf(f, op, ss, R, N, M, sr)
+    H, W = f.shape
+    Sv = o.operator_matrix(H, op, ss, R)
+    Sh = o.operator_matrix(W, op, ss, R)
+    Wsp = np.einsum("ac,bd->abcd", Sv, Sh).reshape(H * W, H * W)
+    fv = f.ravel()
+    den = (Wsp * k(fv[None, :] - fv[:, None])).sum(axis=1).reshape(H, W)
+    num = (Wsp * k(fv[None, :] - fv[:, None]) @ fv).reshape(H, W)
+    assert np.allclose(Q, den, rtol=1e-9, atol=1e-9 * np.abs(den).max())
+    neg = den <= 0
+    assert neg.sum() == bad == len(ys) == 2
+    assert np.all(neg[ys, xs])
+    assert np.array_equal(out[neg], f[neg])
+    assert np.allclose(out[~neg], num[~neg] / den[~neg], rtol=1e-9, atol=1e-9)
+    # the full-size image the GPU tests use: one count per isolated pixel
+    f2, ys2, xs2 = qneg_image()
+    r = o.algorithm2(f2, op, 6.0, 18, sr, eps, 255.0, False, 255.0)
+    assert r["n_nonpos"] == len(ys2) == 12
+    assert np.array_equal(r["out"][ys2, xs2], f2[ys2, xs2])
 
 
 @pytest.mark.parametrize("op", ["fir", "iir", "box"])
