@@ -146,6 +146,26 @@ bf_status bf_filter(bf_plan_t plan, const void *d_in, float *d_out, void *hip_st
 bf_status bf_filter_batch(bf_plan_t plan, int32_t n, const void *const *d_in, float *const *d_out,
                           void *hip_stream, bf_report *reps);
 
+/* bf_filter for callers that cannot allocate device memory during the call:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Filters image 0 of the plan with the same kernels and tables as
+ * bf_filter; the working memory (device state, row maxima, cos/sin tables,
+ * partial sums, smoothed images) comes from a static array of 256 MiB per
+ * device that the library holds until the process ends, not from the plan.
+ * The call launches its kernels directly on hip_stream (no graph of its own,
+ * so a caller may capture it) and calls no hipMalloc, hipFree or other
+ * allocating routine.  The frequency pairs run in as many launches as the
+ * 256 MiB need (one for images up to about 0.5 megapixels at 40 pairs).
+ * Every call on one device shares that device's array: calls that overlap on
+ * one GPU (any plan, any stream) race and give undefined results; callers
+ * serialise them.  rep (nullable) makes the call synchronise its stream, so
+ * pass NULL under capture.
+ * Errors: as bf_filter; BF_ERR_UNSUPPORTED when the working memory of one
+ * pair per launch exceeds 256 MiB (about 10 megapixels on the recursive
+ * blur); BF_ERR_INVALID_ARG when the current device is not the one the plan
+ * was made on. */
+bf_status bf_filter_noalloc(bf_plan_t plan, const void *d_in, float *d_out, void *hip_stream, bf_report *rep);
+
 /* Algorithm 1 alone for image 0: writes the dynamic range T (raw, before any
  * ceil) to *T_out after synchronising hip_stream. */
 bf_status bf_dynamic_range(bf_plan_t plan, const void *d_in, void *hip_stream, double *T_out);

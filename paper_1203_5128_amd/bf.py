@@ -37,7 +37,7 @@ BLURS = {"auto": BF_BLUR_AUTO, "iir_f32": BF_BLUR_IIR_F32, "toeplitz_f16": BF_BL
 BLUR_NAMES = {v: k for k, v in BLURS.items()}
 
 EXPORTS = ["bf_plan", "bf_filter", "bf_filter_batch", "bf_dynamic_range", "bf_profile", "bf_profile_read",
-           "bf_plan_destroy", "bf_status_string", "bf_last_error_detail"]
+           "bf_plan_destroy", "bf_status_string", "bf_last_error_detail", "bf_filter_noalloc"]
 STAGES = ["range", "v_iir", "v_toeplitz", "h_combine"]
 
 
@@ -85,6 +85,8 @@ def lib():
         L.bf_plan.restype = ctypes.c_int
         L.bf_filter.argtypes = [P, P, P, P, ctypes.POINTER(bf_report)]
         L.bf_filter.restype = ctypes.c_int
+        L.bf_filter_noalloc.argtypes = [P, P, P, P, ctypes.POINTER(bf_report)]
+        L.bf_filter_noalloc.restype = ctypes.c_int
         L.bf_filter_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P), P,
                                       ctypes.POINTER(bf_report)]
         L.bf_filter_batch.restype = ctypes.c_int
@@ -157,6 +159,14 @@ def bf_filter(plan: int, d_in: int, d_out: int, stream=None, report: bool = True
     rep = bf_report() if report else None
     st = lib().bf_filter(plan, d_in, d_out, _stream_handle(stream),
                          ctypes.byref(rep) if rep is not None else None)
+    _check(st)
+    return rep.as_dict() if rep is not None else None
+
+
+def bf_filter_noalloc(plan: int, d_in: int, d_out: int, stream=None, report: bool = True):
+    rep = bf_report() if report else None
+    st = lib().bf_filter_noalloc(plan, d_in, d_out, _stream_handle(stream),
+                                 ctypes.byref(rep) if rep is not None else None)
     _check(st)
     return rep.as_dict() if rep is not None else None
 
@@ -239,6 +249,14 @@ class Plan:
         if self.params:
             check_tensors(self.params[0], img, out)
         rep = bf_filter(self.handle, img.data_ptr(), out.data_ptr(), stream, report)
+        return out, rep
+
+    def filter_noalloc(self, img, out, stream=None, report=True):
+        """bf_filter_noalloc: the caller passes the output buffer; the call
+        itself allocates nothing on the device."""
+        if self.params:
+            check_tensors(self.params[0], img, out)
+        rep = bf_filter_noalloc(self.handle, img.data_ptr(), out.data_ptr(), stream, report)
         return out, rep
 
     def filter_batch(self, imgs, outs=None, stream=None, report=True):

@@ -57,6 +57,15 @@ struct ImagePlan {
   ToepCfg tc{};
   size_t z_per_pair = 0;    // workspace bytes of the smoothed images of one pair
   void *d_state = nullptr;  // T_used, flags, T_raw, q_nonpos
+  // launch shape of bf_filter_noalloc, whose working memory is the fixed
+  // static array: pairs per launch and offsets of the regions in it
+  struct NoAlloc {
+    bool ok = false;
+    Geom g{};
+    ToepCfg tc{};
+    int KC = 0;
+    size_t rowmax = 0, lut = 0, pq = 0, z = 0, end = 0;
+  } na;
 };
 
 bool is_toeplitz(int v) { return v >= BF_BLUR_TOEPLITZ_F16 && v <= BF_BLUR_TOEPLITZ_BF16X2; }
@@ -87,6 +96,9 @@ bool toeplitz_shape(int variant, int R, int H, int lds_kb, ToepCfg &tc) {
 }
 
 size_t elem_size(bf_dtype d) { return d == BF_U8 ? 1 : (d == BF_U16 ? 2 : 4); }
+
+// Size of the static working memory of bf_filter_noalloc (per device).
+constexpr size_t kScratchBytes = (size_t)256 << 20;
 
 }  // namespace
 
@@ -133,9 +145,9 @@ struct bf_plan_s {
 
 namespace {
 
-DevState state_of(const ImagePlan &ip) {
+DevState state_at(void *d_state) {
   DevState st;
-  char *b = (char *)ip.d_state;
+  char *b = (char *)d_state;
   st.T_used = (int32_t *)(b + 0);
   st.flags = (int32_t *)(b + 4);
   st.T_raw = (unsigned long long *)(b + 8);
@@ -145,10 +157,12 @@ DevState state_of(const ImagePlan &ip) {
 // d_state: the published state (24 bytes), then the range accumulators
 // (top slot at 32, kRangeSubs slots from 48).
 constexpr size_t kStateBytes = 48 + kRangeSubs * sizeof(RangeAccSlot);
-RangeAcc acc_of(const ImagePlan &ip) {
-  char *b = (char *)ip.d_state;
+RangeAcc acc_at(void *d_state) {
+  char *b = (char *)d_state;
   return RangeAcc{(RangeAccSlot *)(b + 32), (RangeAccSlot *)(b + 48)};
 }
+DevState state_of(const ImagePlan &ip) { return state_at(ip.d_state); }
+RangeAcc acc_of(const ImagePlan &ip) { return acc_at(ip.d_state); }
 
 DevTables tables_of(const ImagePlan &ip) {
   DevTables t;
@@ -232,6 +246,83 @@ struct Knobs {
   int hchunk = 0;   // pixels per thread of the recursive horizontal pass (16 or 32)
   int lds_kb = 0;   // preferred LDS of a Toeplitz vertical tile
 };
+
+// Launch shape of the blur passes for KC pairs per launch: the vertical
+// pass's pairs per workgroup, the horizontal pass's pair groups (recursive
+// path) or the Toeplitz pass's pair groups.
+void set_chunk(ImagePlan &ip, int KC) {
+  Geom &g = ip.g;
+  ip.KC = KC;
+  g.hgroups = 1;
+  g.hkpg = KC;
+  {
+    // vertical pass: pairs per workgroup for about one round of workgroups
+    const int ncb = (g.Spos + kHThreads / g.vS - 1) / (kHThreads / g.vS);
+    const int gx = 8 * ((ncb + 7) / 8);
+    int target = kVWorkgroups;
+    if (const char *w = std::getenv("BF_V_WG")) target = std::max(1, std::atoi(w));
+    const int groups = std::max(1, std::min(KC, (target + gx - 1) / gx));
+    g.vppw = (KC + groups - 1) / groups;
+  }
+  if (!is_toeplitz(ip.variant)) {
+    // horizontal pass: split the pairs of a launch over enough rows of
+    // workgroups to fill the GPU, each group a whole number of the NG pairs a
+    // workgroup handles at once
+    const int ng = kHThreads / g.S;
+    const int slots = (KC + ng - 1) / ng;
+    int target = kHWorkgroups;
+    if (const char *w = std::getenv("BF_H_WG")) target = std::max(1, std::atoi(w));
+    const int groups = std::max(1, std::min(slots, (target + g.H - 1) / g.H));
+    g.hkpg = (slots + groups - 1) / groups * ng;
+    g.hgroups = (KC + g.hkpg - 1) / g.hkpg;
+  } else {
+    // split the pairs of a launch over enough horizontal workgroups to fill the GPU
+    const int tiles = toeplitz_h_tiles(ip.variant, g.H, g.W);
+    const int groups = std::max(1, std::min(KC, (2048 + tiles - 1) / tiles));
+    ip.tc.kpg = (KC + groups - 1) / groups;
+    ip.tc.groups = (KC + ip.tc.kpg - 1) / ip.tc.kpg;
+  }
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Shape of bf_filter_noalloc for an image: the most pairs per launch whose
+// working memory (device state, row maxima of the two-pass range stage,
+// 8-bit cos/sin tables, partial sums, smoothed images) fits kScratchBytes.
+// Leaves the plan's own launch shape as it was.
+void noalloc_shape(ImagePlan &ip) {
+  const Geom g0 = ip.g;
+  const ToepCfg tc0 = ip.tc;
+  const int KC0 = ip.KC;
+  const size_t px = (size_t)g0.H * g0.W;
+  const bool toep = is_toeplitz(ip.variant);
+  const size_t state = align256(kStateBytes);
+  const size_t rowmax =
+      (ip.p.t_mode == BF_T_LOCAL && !range_tile_ok(ip.R, ip.p.dtype)) ? align256(px * elem_size(ip.p.dtype)) : 0;
+  ImagePlan::NoAlloc na;
+  auto fits = [&](int kc) {
+    set_chunk(ip, kc);
+    na.rowmax = state;
+    na.lut = na.rowmax + rowmax;
+    na.pq = na.lut + (toep ? 0 : align256((size_t)kc * 256 * sizeof(float2)));
+    na.z = na.pq + align256((size_t)(toep ? ip.tc.groups : ip.g.hgroups) * px * sizeof(float2));
+    na.end = na.z + align256((size_t)kc * ip.z_per_pair);
+    return na.end <= kScratchBytes;
+  };
+  const size_t fixed = state + rowmax + align256(px * sizeof(float2));
+  int kc = fixed >= kScratchBytes ? 1
+                                  : (int)std::max<size_t>(1, std::min<size_t>((size_t)ip.tab.K_max,
+                                                                              (kScratchBytes - fixed) / ip.z_per_pair));
+  while (kc > 1 && !fits(kc)) kc = std::max(1, kc - std::max(1, kc / 8));
+  na.ok = fits(kc);
+  na.KC = kc;
+  na.g = ip.g;
+  na.tc = ip.tc;
+  ip.na = na;
+  ip.g = g0;
+  ip.tc = tc0;
+  ip.KC = KC0;
+}
 
 bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   ip.p = p;
@@ -324,36 +415,9 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   if (const char *b = std::getenv("BF_Z_BUDGET_MB")) budget = (size_t)std::atoll(b) << 20;
   size_t kc = budget / per_pair;
   if (kc < 1) kc = 1;
-  ip.KC = (int)std::min<size_t>(std::min<size_t>(kc, (size_t)ip.tab.K_max), 65535);
-  g.hgroups = 1;
-  g.hkpg = ip.KC;
-  {
-    // vertical pass: pairs per workgroup for about one round of workgroups
-    const int ncb = (g.Spos + kHThreads / g.vS - 1) / (kHThreads / g.vS);
-    const int gx = 8 * ((ncb + 7) / 8);
-    int target = kVWorkgroups;
-    if (const char *w = std::getenv("BF_V_WG")) target = std::max(1, std::atoi(w));
-    const int groups = std::max(1, std::min(ip.KC, (target + gx - 1) / gx));
-    g.vppw = (ip.KC + groups - 1) / groups;
-  }
-  if (!is_toeplitz(variant)) {
-    // horizontal pass: split the pairs of a launch over enough rows of
-    // workgroups to fill the GPU, each group a whole number of the NG pairs a
-    // workgroup handles at once
-    const int ng = kHThreads / g.S;
-    const int slots = (ip.KC + ng - 1) / ng;
-    int target = kHWorkgroups;
-    if (const char *w = std::getenv("BF_H_WG")) target = std::max(1, std::atoi(w));
-    const int groups = std::max(1, std::min(slots, (target + g.H - 1) / g.H));
-    g.hkpg = (slots + groups - 1) / groups * ng;
-    g.hgroups = (ip.KC + g.hkpg - 1) / g.hkpg;
-  }
+  set_chunk(ip, (int)std::min<size_t>(std::min<size_t>(kc, (size_t)ip.tab.K_max), 65535));
+  noalloc_shape(ip);
   if (is_toeplitz(variant)) {
-    // split the pairs of a launch over enough horizontal workgroups to fill the GPU
-    const int tiles = toeplitz_h_tiles(variant, g.H, g.W);
-    int groups = std::max(1, std::min(ip.KC, (2048 + tiles - 1) / tiles));
-    ip.tc.kpg = (ip.KC + groups - 1) / groups;
-    ip.tc.groups = (ip.KC + ip.tc.kpg - 1) / ip.tc.kpg;
     hipError_t he = toeplitz_setup();
     if (he != hipSuccess) return dev_fail(he, "Toeplitz LDS attributes");
   }
@@ -410,7 +474,29 @@ void stage_mark(void *ctx, int stage, hipStream_t s, bool end) {
   pl->pending.push_back({stage, a, b});
 }
 
-bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out, hipStream_t s);
+// Working memory of one image's launch sequence: the row maxima of the
+// two-pass range stage, the smoothed images of the pairs of a launch, the
+// pair groups' partial sums and the 8-bit cos/sin tables of the pairs.
+struct Workspace {
+  void *rowmax;
+  float4 *Z;
+  float2 *PQ;
+  float2 *lut;
+};
+// Launch shape of one image: geometry, Toeplitz configuration, pairs per
+// launch and the device state (T, flags, range accumulators) it runs with.
+struct Shape {
+  const Geom *g;
+  const ToepCfg *tc;
+  int KC;
+  void *d_state;
+};
+bf_status run_image_ws(const Workspace &ws, const StageRec &rec, const ImagePlan &ip, const Shape &sh,
+                       const void *d_in, float *d_out, hipStream_t s);
+bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out, hipStream_t s) {
+  return run_image_ws(Workspace{pl->d_rowmax, pl->d_Z, pl->d_PQ, pl->d_lut}, pl->rec, ip,
+                      Shape{&ip.g, &ip.tc, ip.KC, ip.d_state}, d_in, d_out, s);
+}
 
 // Launch image img through a captured graph of its kernel sequence.  The
 // graph is captured once per (image, input, output) on a private stream and
@@ -450,13 +536,15 @@ bf_status run_image_graph(bf_plan_s *pl, int img, const void *d_in, float *d_out
 }
 
 // Enqueue the whole of Algorithm 2 for one image.
-bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out, hipStream_t s) {
-  const Geom &g = ip.g;
-  DevState st = state_of(ip);
+bf_status run_image_ws(const Workspace &ws, const StageRec &rec, const ImagePlan &ip, const Shape &sh,
+                       const void *d_in, float *d_out, hipStream_t s) {
+  const Geom &g = *sh.g;
+  const int KC = sh.KC;
+  DevState st = state_at(sh.d_state);
   DevTables tab = tables_of(ip);
   hipError_t e;
   if (ip.p.t_mode == BF_T_LOCAL) {
-    e = launch_range(s, ip.p.dtype, d_in, g, ip.R, pl->d_rowmax, st, acc_of(ip), ip.T_cap, pl->rec);
+    e = launch_range(s, ip.p.dtype, d_in, g, ip.R, ws.rowmax, st, acc_at(sh.d_state), ip.T_cap, rec);
     if (e != hipSuccess) return dev_fail(e, "dynamic range");
   } else {
     e = launch_reset(s, st, ip.T_global, ip.T_global_raw);
@@ -464,18 +552,18 @@ bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out
   }
   const int Kmax = ip.tab.K_max;
   if (is_toeplitz(ip.variant)) {
-    for (int k0 = 0; k0 < Kmax; k0 += ip.KC) {
-      const int kcount = std::min(ip.KC, Kmax - k0);
-      e = launch_toeplitz_chunk(s, ip.p.dtype, ip.variant, d_in, d_out, g, tab, st, ip.tc, k0, kcount, pl->d_Z,
-                                pl->d_PQ, k0 == 0, k0 + ip.KC >= Kmax, pl->rec);
+    for (int k0 = 0; k0 < Kmax; k0 += KC) {
+      const int kcount = std::min(KC, Kmax - k0);
+      e = launch_toeplitz_chunk(s, ip.p.dtype, ip.variant, d_in, d_out, g, tab, st, *sh.tc, k0, kcount, ws.Z,
+                                ws.PQ, k0 == 0, k0 + KC >= Kmax, rec);
       if (e != hipSuccess) return dev_fail(e, "Toeplitz blur");
     }
     return BF_OK;
   }
-  for (int k0 = 0; k0 < Kmax; k0 += ip.KC) {
-    const int kcount = std::min(ip.KC, Kmax - k0);
-    e = launch_iir_chunk(s, ip.p.dtype, d_in, d_out, g, tab, st, ip.d_iir, k0, kcount, pl->d_Z,
-                         pl->d_PQ, k0 == 0, k0 + ip.KC >= Kmax, pl->d_lut, pl->rec);
+  for (int k0 = 0; k0 < Kmax; k0 += KC) {
+    const int kcount = std::min(KC, Kmax - k0);
+    e = launch_iir_chunk(s, ip.p.dtype, d_in, d_out, g, tab, st, ip.d_iir, k0, kcount, ws.Z, ws.PQ, k0 == 0,
+                         k0 + KC >= Kmax, ws.lut, rec);
     if (e != hipSuccess) return dev_fail(e, "blur");
   }
   return BF_OK;
@@ -796,9 +884,9 @@ bf_status run_batch_graph(bf_plan_s *pl, int n, const void *const *d_in, float *
   return e == hipSuccess ? BF_OK : dev_fail(e, "hipGraphLaunch");
 }
 
-bf_status fill_report(ImagePlan &ip, bf_report *rep, float ms) {
+bf_status fill_report(const ImagePlan &ip, const void *d_state, bf_report *rep, float ms) {
   unsigned char buf[24];
-  hipError_t e = hipMemcpy(buf, ip.d_state, 24, hipMemcpyDeviceToHost);
+  hipError_t e = hipMemcpy(buf, d_state, 24, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return dev_fail(e, "read report");
   int32_t Tu, flags;
   unsigned long long traw, qn;
@@ -1012,7 +1100,72 @@ bf_status bf_filter(bf_plan_t pl, const void *d_in, float *d_out, void *hip_stre
   if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
-  return fill_report(ip, rep, ms);
+  return fill_report(ip, ip.d_state, rep, ms);
+}
+
+}  // extern "C"
+
+// ------------------------------------------ working memory without allocation
+// bf_filter_noalloc runs the launch sequence of bf_filter with its working
+// memory (device state, row maxima, cos/sin tables, partial sums, smoothed
+// images) in this array instead of the plan's.  Each GPU the library runs on
+// holds its own copy until the process ends.  Host code never uses the name
+// as an address: the device address comes from hipGetSymbolAddress, once per
+// device, with that device current.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+bf_status scratch_on(int dev, unsigned char **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(BF_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return dev_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(BF_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = (unsigned char *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+bf_status bf_filter_noalloc(bf_plan_t pl, const void *d_in, float *d_out, void *hip_stream, bf_report *rep) {
+  if (!pl || !d_in || !d_out) return fail(BF_ERR_INVALID_ARG, "NULL plan or buffer");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return dev_fail(e, "hipGetDevice");
+  if (dev != pl->device) return fail(BF_ERR_INVALID_ARG, "the current device is not the plan's");
+  ImagePlan &ip = pl->im[0];
+  if (!ip.na.ok)
+    return fail(BF_ERR_UNSUPPORTED, "image needs more than the " + std::to_string(kScratchBytes >> 20) +
+                                        " MiB of static working memory for one frequency pair per launch");
+  unsigned char *base = nullptr;
+  bf_status st = scratch_on(dev, &base);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (rep) (void)hipEventRecord(pl->ev0, s);
+  // the range accumulators and counters must start at zero; the array keeps
+  // whatever the previous call on this device left in it
+  e = launch_zero(s, base, align256(kStateBytes));
+  if (e != hipSuccess) return dev_fail(e, "clear state");
+  const ImagePlan::NoAlloc &na = ip.na;
+  const Workspace ws{base + na.rowmax, (float4 *)(base + na.z), (float2 *)(base + na.pq), (float2 *)(base + na.lut)};
+  st = run_image_ws(ws, StageRec(), ip, Shape{&na.g, &na.tc, na.KC, base}, d_in, d_out, s);
+  if (st) return st;
+  if (!rep) return BF_OK;
+  (void)hipEventRecord(pl->ev1, s);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
+  return fill_report(ip, base, rep, ms);
 }
 
 bf_status bf_filter_batch(bf_plan_t pl, int32_t n, const void *const *d_in, float *const *d_out, void *hip_stream,
@@ -1034,7 +1187,7 @@ bf_status bf_filter_batch(bf_plan_t pl, int32_t n, const void *const *d_in, floa
   (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
   bf_status first = BF_OK;
   for (int i = 0; i < n; i++) {
-    bf_status st = fill_report(pl->im[i], &reps[i], ms);
+    bf_status st = fill_report(pl->im[i], pl->im[i].d_state, &reps[i], ms);
     if (st && !first) first = st;
   }
   return first;

@@ -231,6 +231,8 @@ struct StageRec {
 // ---- launch wrappers (bf_kernels.hip) ----
 hipError_t launch_fill_checker(hipStream_t s, bf_dtype dt, void *f, int H, int W, double top);
 hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw);
+// Zero fill of `bytes` (a multiple of 4) at p, as a kernel.
+hipError_t launch_zero(hipStream_t s, void *p, size_t bytes);
 // Algorithm 1 for one image, with the state reset it needs (the one-launch
 // tile kernel when range_tile_ok(R, dt), else reset + row pass + column pass).
 hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,

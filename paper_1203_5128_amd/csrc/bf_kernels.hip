@@ -1343,6 +1343,19 @@ hipError_t launch_fill_checker(hipStream_t s, bf_dtype dt, void *f, int H, int W
   return hipGetLastError();
 }
 
+// Zero fill of n 32-bit words (a kernel, so that it can sit in a captured
+// graph where a memset node could not).
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t *__restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+hipError_t launch_zero(hipStream_t s, void *p, size_t bytes) {
+  const int64_t n = (int64_t)(bytes / 4);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint32_t *)p, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw) {
   ResetArgs a{GroupGrid{1, 1, 1}, st, T_used, T_raw};
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a);
