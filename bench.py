@@ -1,25 +1,42 @@
 """Benchmark of the shiftable bilateral filter on one MI355X.
 
-One step = one call of bf_filter on the resident 512x512 8-bit workload
-(gradient + step edges + noise, sigma_s = 10, sigma_r = 10, local T over the
-61x61 window, eps = 1e-3, FP32 recursive Gaussian): the dynamic-range stage,
-every frequency pair's blur, and the combine/divide.  The output of the timed
-steps is checked against the FP64 oracle, and the oracle itself is timed on
-the host cores as the CPU baseline.
+Headline (`value`): the 64-image batch workload -- 8-bit images of uneven
+sizes (128..1024 per side), per-image sigma_s ~ U[2,16] and sigma_r ~
+U[10,60], local T over the (2 ceil(3 sigma_s) + 1)^2 window, eps = 1e-3 --
+filtered by one bf_filter_batch call per step (one captured graph of grouped
+launches), every image on the blur variant the autotuner picks.  This is the
+largest single-GPU workload (23.3 megapixels per step).  A step is the whole
+of Algorithm 2 for all 64 images: the dynamic-range stage, every frequency
+pair's blur and the combine/divide.
 
-Besides this plain FP32 line (`value`), the same JSON line carries the mixed
-path on the same workload (split-FP16 Toeplitz blur, its error against the
-oracle with the FIR operator), the batched path (64 images of uneven sizes
-with per-image sigma_s, sigma_r, one grouped graph launch per step, its error
-at sampled pixels against eq. (BF) evaluated directly, and the same images
-filtered one by one for comparison), and the constant (box) spatial filter of
-Section 4 (radius 20, sigma_r 5, eps 0.01) on the same image.
+The same JSON line carries, per workload (`configs`), the other four
+workloads as sub-lines, each timed, profiled by stage and checked against
+the FP64 oracle: the 256x256 rectangles image with global T = 255; the
+512x512 gradient image (recursive blur, split-FP16 Toeplitz blur, and the
+constant spatial filter of Section 4); the 2048x2048 16-bit polygons image;
+the 4096x4096 float mosaic on the recursive blur and on the four Toeplitz
+variants (split FP16, split BF16, FP16, BF16 operands).  `batched` holds the
+batch on the recursive and on the split-FP16 path alone and the 64 images
+filtered one after another by single-image plans.
+
+Roofline: for every line the stage with the largest device time (HIP events
+recorded between the stages on the launch stream, in a second pass of the
+same steps launched directly), its algorithmic bytes per step (the images'
+real pair counts) over its time, against 8 TB/s; the Toeplitz lines also
+report their matrix-core rate against 2.5 PFLOP/s dense FP16/BF16.
+
+CPU baseline: the FP64 oracle (the operator of each image's variant) on a
+bounded sample of the batch workload -- the first images until about 15 s of
+work -- on every host thread, and once on one thread; the CPU model is
+recorded.
 
 Prints one JSON line.  Only one GPU is supported: --gpus above 1 exits.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -31,83 +48,62 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense FP16/BF16 matrix cores
+B_IN = {"u8": 1, "u16": 2, "f32": 4}
+TOL = {"u8": 2e-3, "u16": 2e-3 * 257, "f32": 2e-3}
+RANGE = {"u8": 255.0, "u16": 65535.0, "f32": 255.0}
 
 
-def algorithmic_bytes(stage: str, H: int, W: int, pairs: int, b_in: int, kcount: int) -> float:
-    """Bytes a stage must move per launch.
+# --------------------------------------------------------------- byte models
+def z_bytes(blur: str) -> int:
+    """Bytes of one smoothed image element: FP32 on the recursive path and on
+    the split Toeplitz variants, 16 bits on the single-operand ones."""
+    return 2 if blur in ("toeplitz_f16", "toeplitz_bf16") else 4
 
-    v_iir generates the four images of each pair from f and writes them
-    smoothed down the columns (16 B per pixel and pair, FP32); h_combine reads
+
+def stage_bytes(stage: str, px: int, pairs: int, b_in: int, blur: str) -> float:
+    """Algorithmic HBM bytes of one stage of one image.
+
+    The vertical pass generates the four images of each pair from f and
+    writes them smoothed down the columns once; the horizontal pass reads
     them back and writes the output.  The range stage reads f twice and
-    writes/reads the row maxima once."""
-    px = H * W
-    if stage == "v_iir":
-        return px * (16.0 * pairs + b_in)
+    writes/reads the row maxima once (Algorithm 1, separable)."""
+    zb = 4 * z_bytes(blur)
+    if stage in ("v_iir", "v_toeplitz"):
+        return px * (zb * pairs + b_in)
     if stage == "h_combine":
-        return px * (16.0 * pairs + b_in + 4.0)
+        return px * (zb * pairs + b_in + 4.0)
     if stage == "range":
         return px * 4.0 * b_in
     return 0.0
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_grad512_u8.json")
+def mfma_flops(stage: str, px: int, pairs: int, R: int) -> float:
+    """Banded FIR multiply-adds of a Toeplitz stage: four images per pair,
+    2 (2R + 1) flops per output and pass."""
+    if stage in ("v_toeplitz", "h_combine"):
+        return px * pairs * 4 * 2.0 * (2 * R + 1)
+    return 0.0
+
+
+def measured_traffic(stage: str, workload: str):
+    """HBM bytes per step of `stage` from the committed rocprofv3 counter
+    summary of `workload`, or None when a kernel source changed since it was
+    taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{stage}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()
-    return rec["traffic_bytes"] if sha.startswith(rec["source_sha256_prefix"]) else None
+    for src, pre in rec["sources"].items():
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            if not hashlib.sha256(fh.read()).hexdigest().startswith(pre):
+                return None
+    return rec["traffic_bytes_per_step"]
 
 
-def cpu_baseline(img, c, mixed=None, batch=None, box=None, budget_s=25.0):
-    """The CPU leg: the FP64 oracle timed on the main workload (Algorithm 2
-    with the recursive operator, all host threads).  Its outputs, and the
-    oracle values it computes afterwards (untimed) for the mixed line (whole
-    image, FIR operator) and the batched line (sampled pixels of every image,
-    each with the operator its autotuned variant uses), are the references of
-    the error checks."""
-    import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    f = img.astype(np.float64)
-    times = []
-    t_start = time.time()
-    while len(times) < 3 and (time.time() - t_start) < budget_s:
-        t0 = time.perf_counter()
-        r = oracle.algorithm2(f, "iir", c["sigma_s"], c["radius"], c["sigma_r"], c["eps"], 255.0, True)
-        times.append(time.perf_counter() - t0)
-    med = float(np.median(times))
-    base = dict(value=img.size / med / 1e6, unit="megapixels/sec", cores=threads, kind="oracle",
-                sample=f"whole {img.shape[0]}x{img.shape[1]} image, Algorithm 2 end to end (FP64, IIR "
-                       f"operator), median of {len(times)} runs, {med:.2f} s each")
-    refs = dict(iir=r)
-    if mixed is not None:
-        refs["fir"] = oracle.algorithm2(f, "fir", c["sigma_s"], c["radius"], c["sigma_r"], c["eps"], 255.0, True)
-    if batch is not None:
-        vals = []
-        for (im, ss, sr), rep, (ys, xs) in batch:
-            g = im.astype(np.float64)
-            R = int(np.ceil(3 * ss))
-            if rep["variant"] == "iir_f32":  # no pointwise form of the recursive operator: whole image
-                vals.append(oracle.algorithm2(g, "iir", ss, R, sr, 1e-3, 255.0, True)["out"][ys, xs])
-            else:
-                vals.append(oracle.direct_fir_at(g, ss, R, rep["N"], rep["M"], sr, ys, xs))
-        refs["batch"] = vals
-    if box is not None:  # eq. (BF) directly with the box filter at the sampled pixels
-        ys, xs = box
-        R, sr, eps = BOX["radius"], BOX["sigma_r"], BOX["eps"]
-        T = oracle.range_T(f, R)
-        N = oracle.order(T, sr)
-        M = oracle.trunc_rule(N, sr, eps)
-        refs["box"] = dict(T=T, N=N, M=M, vals=oracle.direct_box_at(f, R, N, M, sr, ys, xs))
-    return refs, base
-
-
+# ------------------------------------------------------------------- timing
 def time_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -120,53 +116,126 @@ def time_steps(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def mixed_line(img, c, x, steps, warmup):
-    """The split-FP16 Toeplitz path on the same workload; returns the line
-    and the output (host) for the error check."""
+def stage_profile(plan, run, steps):
+    """Per-stage device time of `steps` direct launches (HIP events between
+    the stages on the launch stream)."""
     import torch
+    plan.profile(True)
+    plan.profile_read()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    return {s: dict(ms_per_step=v[0] / steps, launches_per_step=v[1] / steps) for s, v in prof.items() if v[1]}
+
+
+def roofline(stages, images, workload):
+    """Roofline of the stage with the largest device time.  images: list of
+    (px, pairs, b_in, blur, R)."""
+    dom = max(stages, key=lambda s: stages[s]["ms_per_step"])
+    ms = stages[dom]["ms_per_step"]
+    nb = sum(stage_bytes(dom, px, pr, b, bl) for px, pr, b, bl, _ in images)
+    ach = nb / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    launches = stages[dom]["launches_per_step"]
+    roof = dict(bound="hbm", kernel=dom, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(ach / HBM_PEAK_GBS, 4), avg_launch_ms=round(ms / max(launches, 1), 5),
+                launches_per_step=launches, bytes_per_step=nb, traffic=measured_traffic(dom, workload))
+    mf = {}
+    for s in ("v_toeplitz", "h_combine"):
+        fl = sum(mfma_flops(s, px, pr, R) for px, pr, _, bl, R in images if bl.startswith("toeplitz"))
+        if fl and s in stages and stages[s]["ms_per_step"] > 0:
+            t = fl / (stages[s]["ms_per_step"] * 1e-3) / 1e12
+            mf[s] = dict(achieved=round(t, 2), peak=MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                         frac=round(t / MFMA_PEAK_TFLOPS, 5))
+    if mf:
+        roof["mfma"] = mf
+    return roof
+
+
+def err_stats(got, ref, tol):
+    e = np.abs(np.asarray(got, np.float64) - ref)
+    return dict(max_err=float(e.max()), rms_err=float(np.sqrt((e ** 2).mean())), err_ok=bool(e.max() <= tol))
+
+
+def sample_pixels(H, W, n, seed):
+    rng = np.random.default_rng(seed)
+    ys = np.concatenate([rng.integers(0, H, n), [0, H - 1, 0, H - 1]])
+    xs = np.concatenate([rng.integers(0, W, n), [0, W - 1, W - 1, 0]])
+    return ys, xs
+
+
+# ------------------------------------------------------- single-image lines
+def single_line(idx, blur, steps, warmup, spatial="gaussian", sigma_s=None, radius=None, sigma_r=None,
+                eps=None, label=None):
+    """One workload on one blur variant: timed graph replays, stage profile,
+    roofline; returns (line, output on the host, report)."""
+    import torch
+    from bfsynth import CONFIGS, config_image
     from paper_1203_5128_amd import Plan, make_params
+    c = dict(CONFIGS[idx])
+    for k, v in (("sigma_s", sigma_s), ("radius", radius), ("sigma_r", sigma_r), ("eps", eps)):
+        if v is not None:
+            c[k] = v
+    img = config_image(idx)
     H, W = img.shape
+    x = torch.from_numpy(img).to("cuda:0")
     out = torch.empty((H, W), dtype=torch.float32, device=x.device)
-    plan = Plan.create(make_params(H, W, "u8", c["sigma_s"], c["sigma_r"], c["eps"], c["radius"], "local",
-                                   blur="toeplitz_f16x2"))
+    plan = Plan.create(make_params(H, W, c["dtype"], c["sigma_s"], c["sigma_r"], c["eps"], c["radius"],
+                                   c["t_mode"], t_value=c["t_value"], blur=blur, spatial=spatial))
+    print(f"[bench] {label or c['name']} {blur} {spatial}", file=sys.stderr, flush=True)
     _, rep = plan.filter(x, out, report=True)
     sec = time_steps(lambda: plan.filter(x, out, report=False), steps, warmup)
+    stages = stage_profile(plan, lambda: plan.filter(x, out, report=False), max(3, steps // 2))
     plan.close()
-    line = dict(blur="toeplitz_f16x2", value=round(H * W / sec / 1e6, 3), unit="megapixels/sec",
-                ms_per_step=round(sec * 1e3, 5), dtype="f16 hi+lo operands, f32 accumulation",
-                N=rep["N"], M=rep["M"])
-    return line, out.cpu().numpy().astype(np.float64)
+    workload = label or c["name"]
+    imgs = [(H * W, rep["pairs"], B_IN[c["dtype"]], blur, c["radius"])]
+    line = dict(workload=workload, blur=blur, spatial=spatial, H=H, W=W, input=c["dtype"],
+                sigma_s=c["sigma_s"], radius=c["radius"], sigma_r=c["sigma_r"], eps=c["eps"], t_mode=c["t_mode"],
+                value=round(H * W / sec / 1e6, 3), unit="megapixels/sec", ms_per_step=round(sec * 1e3, 5),
+                steps=steps, T=rep["T"], N=rep["N"], M=rep["M"], pairs=rep["pairs"], stages=stages,
+                roofline=roofline(stages, imgs, workload))
+    return line, out.cpu().numpy(), c, img
 
 
-BOX = dict(radius=20, sigma_r=5.0, eps=1e-2)  # the paper's box setting (Section 4)
-
-
-def box_line(img, x, steps, warmup):
-    """The constant (box) spatial filter of radius 20 with sigma_r = 5 and
-    eps = 0.01 on the same image (split-FP16 Toeplitz kernels, unit taps);
-    returns the line and the output at sampled pixels for the error check."""
+# -------------------------------------------------------------------- batch
+def batch_run(blur, steps, warmup, profile=False):
+    """The 64-image workload with every image on `blur` ("auto": each
+    image's autotuned variant).  Returns the line, the reports and the
+    outputs (host)."""
     import torch
+    from bfsynth import batch_images
     from paper_1203_5128_amd import Plan, make_params
-    H, W = img.shape
-    out = torch.empty((H, W), dtype=torch.float32, device=x.device)
-    plan = Plan.create(make_params(H, W, "u8", float(BOX["radius"]), BOX["sigma_r"], BOX["eps"], BOX["radius"],
-                                   "local", blur="toeplitz_f16x2", spatial="box"))
-    _, rep = plan.filter(x, out, report=True)
-    sec = time_steps(lambda: plan.filter(x, out, report=False), steps, warmup)
+    items = batch_images()
+    xs = [torch.from_numpy(im).to("cuda:0") for im, _, _ in items]
+    outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in xs]
+    print(f"[bench] batch64_u8_local {blur}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    plan = Plan.create([make_params(im.shape[0], im.shape[1], "u8", sigma_s=ss, sigma_r=sr, eps=1e-3, blur=blur)
+                        for im, ss, sr in items])
+    plan_s = time.perf_counter() - t0
+    _, reps = plan.filter_batch(xs, outs, report=True)
+    sec = time_steps(lambda: plan.filter_batch(xs, outs, report=False), steps, warmup)
+    px = sum(im.size for im, _, _ in items)
+    chosen = {}
+    for r in reps:
+        chosen[r["variant"]] = chosen.get(r["variant"], 0) + 1
+    line = dict(workload="batch64_u8_local", blur=blur, images=len(items), megapixels=round(px / 1e6, 3),
+                value=round(px / sec / 1e6, 3), unit="megapixels/sec", ms_per_step=round(sec * 1e3, 5),
+                steps=steps, variants=chosen, pairs_total=int(sum(r["pairs"] for r in reps)),
+                plan_s=round(plan_s, 2))
+    if profile:
+        stages = stage_profile(plan, lambda: plan.filter_batch(xs, outs, report=False), max(3, steps // 2))
+        imgs = [(im.size, r["pairs"], 1, r["variant"], int(np.ceil(3 * ss))) for (im, ss, _), r in zip(items, reps)]
+        line["stages"] = stages
+        line["roofline"] = roofline(stages, imgs, "batch64_u8_local")
     plan.close()
-    line = dict(spatial="box", blur="toeplitz_f16x2", radius=BOX["radius"], sigma_r=BOX["sigma_r"],
-                eps=BOX["eps"], value=round(H * W / sec / 1e6, 3), unit="megapixels/sec",
-                ms_per_step=round(sec * 1e3, 5), T=rep["T"], N=rep["N"], M=rep["M"], pairs=rep["pairs"])
-    rng = np.random.default_rng(9)
-    ys = np.concatenate([rng.integers(0, H, 150), [0, H - 1, 0, H - 1]])
-    xs = np.concatenate([rng.integers(0, W, 150), [0, W - 1, W - 1, 0]])
-    return line, (ys, xs, out.cpu().numpy()[ys, xs].astype(np.float64))
+    return line, reps, [o.cpu().numpy() for o in outs]
 
 
 def sequential_batch(steps, warmup):
-    """The 64 images of the batch workload filtered one after another, each
-    by its own single-image plan (recursive blur): the reference for what the
-    grouped batch launch gains."""
+    """The 64 images filtered one after another, each by its own
+    single-image plan (recursive blur): what the grouped batch launch gains."""
     import torch
     from bfsynth import batch_images
     from paper_1203_5128_amd import Plan, make_params
@@ -184,54 +253,174 @@ def sequential_batch(steps, warmup):
         pl.close()
     px = sum(im.size for im, _, _ in items)
     return dict(blur="iir_f32", images=len(items), value=round(px / sec / 1e6, 3), unit="megapixels/sec",
-                ms_per_step=round(sec * 1e3, 5)), [o.cpu() for o in outs]
+                ms_per_step=round(sec * 1e3, 5))
 
 
-def batched_line(blur, steps, warmup):
-    """The 64-image workload (uneven sizes, per-image sigma_s, sigma_r) with
-    every image on `blur` ("auto": each image's autotuned variant); returns
-    the line and (item, report, sampled pixels, sampled outputs) of the
-    images whose outputs are checked (all for the FIR variants, every fourth
-    for the recursive one, whose oracle runs on the whole image)."""
-    import torch
+def batch_errors(reps, outs, seed=5):
+    """Oracle check of a batch: the whole image for every fourth image on the
+    recursive operator (it has no pointwise form), eq. (BF) evaluated
+    directly at 12 sampled pixels of every image on a FIR variant."""
+    import oracle
     from bfsynth import batch_images
-    from paper_1203_5128_amd import Plan, make_params
+    rng = np.random.default_rng(seed)
+    worst, sq, n = 0.0, 0.0, 0
+    for i, ((im, ss, sr), r, out) in enumerate(zip(batch_images(), reps, outs)):
+        f = im.astype(np.float64)
+        R = int(np.ceil(3 * ss))
+        if r["variant"] == "iir_f32":
+            if i % 4:
+                continue
+            ref = oracle.algorithm2(f, "iir", ss, R, sr, 1e-3, 255.0, True)
+            assert (ref["N"], ref["M"]) == (r["N"], r["M"])
+            e = np.abs(out.astype(np.float64) - ref["out"])
+        else:
+            ys, xs = rng.integers(0, im.shape[0], 12), rng.integers(0, im.shape[1], 12)
+            e = np.abs(out[ys, xs].astype(np.float64) - oracle.direct_fir_at(f, ss, R, r["N"], r["M"], sr, ys, xs))
+        worst = max(worst, float(e.max()))
+        sq += float((e ** 2).sum())
+        n += e.size
+    return dict(max_err=worst, rms_err=float(np.sqrt(sq / max(n, 1))), err_ok=bool(worst <= 2e-3),
+                checked="whole image of every 4th recursive-path image; 12 sampled pixels of every FIR-path image")
+
+
+# ------------------------------------------------------------- CPU baseline
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def omp_threads(n):
+    """Set the OpenMP thread count of the oracle library (same libgomp)."""
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
+def cpu_baseline(reps, budget_s=20.0):
+    """The oracle as it stands on the headline workload: Algorithm 2 end to
+    end (FP64, the operator of each image's variant) over the batch images
+    in order, all host threads, repeated up to three times within `budget_s`
+    (median); then the first four images on one thread and again on all
+    threads, for the scaling of the oracle itself."""
+    import oracle
+    from bfsynth import batch_images
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     items = batch_images()
-    xs = [torch.from_numpy(im).to("cuda:0") for im, _, _ in items]
-    outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in xs]
-    t0 = time.perf_counter()
-    plan = Plan.create([make_params(im.shape[0], im.shape[1], "u8", sigma_s=ss, sigma_r=sr, eps=1e-3, blur=blur)
-                        for im, ss, sr in items])
-    plan_s = time.perf_counter() - t0
-    _, reps = plan.filter_batch(xs, outs, report=True)
-    sec = time_steps(lambda: plan.filter_batch(xs, outs, report=False), steps, warmup)
-    plan.close()
-    px = sum(im.size for im, _, _ in items)
-    chosen = {}
-    for r in reps:
-        chosen[r["variant"]] = chosen.get(r["variant"], 0) + 1
-    line = dict(blur=blur, images=len(items), megapixels=round(px / 1e6, 3), value=round(px / sec / 1e6, 3),
-                unit="megapixels/sec", ms_per_step=round(sec * 1e3, 5), variants=chosen,
-                plan_s=round(plan_s, 2))
-    rng = np.random.default_rng(5)
-    samples = []
-    for i, (it, out, r) in enumerate(zip(items, outs, reps)):
-        if r["variant"] == "iir_f32" and i % 4:
-            continue
-        ys, xs_ = rng.integers(0, it[0].shape[0], 12), rng.integers(0, it[0].shape[1], 12)
-        samples.append((it, r, (ys, xs_), out.cpu().numpy()[ys, xs_].astype(np.float64)))
-    return line, samples
+
+    def run(sel):
+        t0 = time.perf_counter()
+        px = 0
+        for (im, ss, sr), r in sel:
+            op = "iir" if r["variant"] == "iir_f32" else "fir"
+            oracle.algorithm2(im.astype(np.float64), op, ss, int(np.ceil(3 * ss)), sr, 1e-3, 255.0, True)
+            px += im.size
+            if time.perf_counter() - t0 > budget_s:
+                break
+        return px, time.perf_counter() - t0
+
+    omp_threads(threads)
+    runs = []
+    t_start = time.perf_counter()
+    while len(runs) < 3 and time.perf_counter() - t_start < budget_s:
+        runs.append(run(list(zip(items, reps))))
+    px, dt = sorted(runs, key=lambda r: r[0] / r[1])[len(runs) // 2]
+    head = list(zip(items, reps))[:4]
+    px4, dt4_all = run(head)
+    one = omp_threads(1)
+    _, dt4_one = run(head)
+    omp_threads(threads)
+    return dict(value=px / dt / 1e6, unit="megapixels/sec", cores=threads, kind="oracle", cpu_model=cpu_model(),
+                sample=f"{px / 1e6:.2f} MP of the 64-image batch (all of it unless the {budget_s:.0f} s budget "
+                       f"ran out), Algorithm 2 end to end in FP64 with each image's operator, median of "
+                       f"{len(runs)} runs of {dt:.1f} s on {threads} threads",
+                single_thread=dict(value=px4 / dt4_one / 1e6 if one else None, unit="megapixels/sec", cores=1,
+                                   same_sample_all_threads=px4 / dt4_all / 1e6,
+                                   sample=f"batch images 0-3 ({px4 / 1e6:.2f} MP): {dt4_one:.2f} s on one "
+                                          f"thread, {dt4_all:.2f} s on {threads}"))
+
+
+# --------------------------------------------------------------------- main
+def config_lines(steps, warmup, which):
+    """Sub-lines of the four single-image workloads, each checked against the
+    FP64 oracle (whole image for the recursive operator, eq. (BF) evaluated
+    directly at sampled pixels for the FIR and box operators)."""
+    import oracle
+    res = {}
+    big = max(5, steps // 10)
+    if "cfg1" in which:  # 256x256 u8, global T = 255
+        line, out, c, img = single_line(1, "iir_f32", steps, warmup)
+        ref = oracle.algorithm2(img.astype(np.float64), "iir", c["sigma_s"], c["radius"], c["sigma_r"], c["eps"],
+                                255.0, False, c["t_value"])
+        line.update(err_stats(out, ref["out"], TOL["u8"]))
+        line["err_ok"] = line["err_ok"] and (ref["N"], ref["M"]) == (line["N"], line["M"])
+        res[c["name"]] = line
+    if "cfg2" in which:  # 512x512 u8: recursive, split FP16 Toeplitz, box filter
+        sub = {}
+        line, out, c, img = single_line(2, "iir_f32", steps, warmup)
+        f = img.astype(np.float64)
+        ref = oracle.algorithm2(f, "iir", c["sigma_s"], c["radius"], c["sigma_r"], c["eps"], 255.0, True)
+        line.update(err_stats(out, ref["out"], TOL["u8"]))
+        sub["iir_f32"] = line
+        line, out, c, img = single_line(2, "toeplitz_f16x2", steps, warmup)
+        ref = oracle.algorithm2(f, "fir", c["sigma_s"], c["radius"], c["sigma_r"], c["eps"], 255.0, True)
+        line.update(err_stats(out, ref["out"], TOL["u8"]))
+        sub["toeplitz_f16x2"] = line
+        # the constant spatial filter of Section 4: radius 20, sigma_r 5, eps 0.01
+        line, out, c, img = single_line(2, "toeplitz_f16x2", steps, warmup, spatial="box", sigma_s=20.0,
+                                        radius=20, sigma_r=5.0, eps=1e-2, label="grad512_u8_box20")
+        ys, xs = sample_pixels(512, 512, 150, 9)
+        T = oracle.range_T(f, 20)
+        N = oracle.order(T, 5.0)
+        M = oracle.trunc_rule(N, 5.0, 1e-2)
+        line.update(err_stats(out[ys, xs], oracle.direct_box_at(f, 20, N, M, 5.0, ys, xs), TOL["u8"]))
+        line["err_checked"] = "154 sampled pixels against eq. (BF) evaluated directly with the box"
+        sub["box_toeplitz_f16x2"] = line
+        res["grad512_u8_local"] = sub
+    if "cfg3" in which:  # 2048x2048 u16
+        line, out, c, img = single_line(3, "iir_f32", big, 2)
+        ref = oracle.algorithm2(img.astype(np.float64), "iir", c["sigma_s"], c["radius"], c["sigma_r"], c["eps"],
+                                65535.0, True)
+        line.update(err_stats(out, ref["out"], TOL["u16"]))
+        line["tolerance"] = TOL["u16"]
+        res[c["name"]] = line
+    if "cfg4" in which:  # 4096x4096 f32: recursive and the four Toeplitz variants
+        sub = {}
+        ys, xs = sample_pixels(4096, 4096, 300, 4)
+        fir_ref = None
+        for blur in ("iir_f32", "toeplitz_f16x2", "toeplitz_bf16x2", "toeplitz_f16", "toeplitz_bf16"):
+            line, out, c, img = single_line(4, blur, big, 2)
+            f = img.astype(np.float64)
+            if blur == "iir_f32":
+                ref = oracle.algorithm2(f, "iir", c["sigma_s"], c["radius"], c["sigma_r"], c["eps"], 255.0, True)
+                line.update(err_stats(out, ref["out"], TOL["f32"]))
+            else:
+                if fir_ref is None:
+                    fir_ref = oracle.direct_fir_at(f, c["sigma_s"], c["radius"], line["N"], line["M"], c["sigma_r"],
+                                                   ys, xs)
+                line.update(err_stats(out[ys, xs], fir_ref, TOL["f32"]))
+                line["err_checked"] = "304 sampled pixels against eq. (BF) evaluated directly with the FIR"
+            sub[blur] = line
+        res[c["name"]] = sub
+    return res
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="plain FP32 line only (no mixed/batched lines)")
-    ap.add_argument("--lines", default="mixed,batch,box",
-                    help="extra lines besides the plain one: any of mixed, batch, box (empty: none)")
+    ap.add_argument("--lines", default="cfg1,cfg2,cfg3,cfg4,batch",
+                    help="sub-lines besides the headline batch: any of cfg1..cfg4, batch (empty: none)")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle checks (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB mebibytes (a kernel of known "
                          "traffic against which the HBM byte counters are scaled)")
@@ -242,8 +431,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from bfsynth import CONFIGS, config_image
-    from paper_1203_5128_amd import Plan, make_params
 
     if args.copy_calibration:
         n = args.copy_calibration << 20
@@ -255,116 +442,33 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    c = CONFIGS[2]
-    img = config_image(2)
-    H, W = img.shape
-    dev = torch.device("cuda:0")
-    x = torch.from_numpy(img).to(dev)
-    out = torch.empty((H, W), dtype=torch.float32, device=dev)
-    plan = Plan.create(make_params(H, W, "u8", c["sigma_s"], c["sigma_r"], c["eps"], c["radius"], "local",
-                                   blur="iir_f32"))
-    stream = torch.cuda.current_stream()
-
-    _, rep = plan.filter(x, out, stream=stream, report=True)
-    for _ in range(args.warmup):
-        plan.filter(x, out, stream=stream, report=False)
-    torch.cuda.synchronize()
-
-    # timed region: the captured launch sequence replayed, nothing else
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.filter(x, out, stream=stream, report=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = H * W * args.steps / (t1 - t0) / 1e6
-
-    # per-stage device time: the same steps launched directly with HIP events
-    # between the stages on the launch stream
-    plan.profile(True)
-    plan.profile_read()
-    for _ in range(args.steps):
-        plan.filter(x, out, stream=stream, report=False)
-    torch.cuda.synchronize()
-    prof = plan.profile_read()
-    plan.profile(False)
-
-    # the dominant kernel and its roofline
-    pairs = rep["pairs"]
-    b_in = 1
-    dom = max(prof, key=lambda s: prof[s][0])
-    dom_ms, dom_n = prof[dom]
-    avg_ms = dom_ms / max(dom_n, 1)
-    bytes_launch = algorithmic_bytes(dom, H, W, pairs, b_in, pairs)
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    stages = {s: dict(ms_per_step=v[0] / args.steps, launches_per_step=v[1] / args.steps)
-              for s, v in prof.items() if v[1]}
-
+    which = {t for t in args.lines.split(",") if t}
+    head, reps, outs = batch_run("auto", args.steps, args.warmup, profile=True)
     result = dict(metric="megapixels/sec of shiftable BF at max err <=2e-3 (plain FP32 vs mixed/batched)",
-                  value=round(value, 3), unit="megapixels/sec", n_gpus=1, steps=args.steps, warmup=args.warmup,
-                  ms_per_step=round(ms_step, 5), higher_is_better=True, scaling="weak", vs_baseline=None,
+                  value=head["value"], unit="megapixels/sec", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                  ms_per_step=head["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
                   dtype="f32", data="synthetic",
-                  config=dict(workload="grad512_u8_local", H=H, W=W, input="u8", sigma_s=c["sigma_s"],
-                              radius=c["radius"], sigma_r=c["sigma_r"], eps=c["eps"], t_mode="local",
-                              blur="iir_f32", T=rep["T"], N=rep["N"], M=rep["M"], pairs=pairs),
-                  roofline=dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                                avg_launch_ms=round(avg_ms, 5), bytes_per_launch=bytes_launch,
-                                traffic=measured_traffic(dom)),
-                  stages=stages)
-
-    got = out.cpu().numpy().astype(np.float64)
-    plan.close()
-    mixed = None
-    batches = {}
-    lines = set() if args.no_extra else {t for t in args.lines.split(",") if t}
-    if "mixed" in lines:
-        mixed, mixed_out = mixed_line(img, c, x, args.steps, args.warmup)
-        result["mixed"] = mixed
-    if "batch" in lines:
-        bsteps = max(3, args.steps // 20)
-        for key, blur in (("plain", "iir_f32"), ("mixed", "toeplitz_f16x2"), ("auto", "auto")):
-            batches[key] = batched_line(blur, bsteps, 2)
-        result["batched"] = dict(workload="batch64_u8_local", **{k: v[0] for k, v in batches.items()})
-        result["batched"]["speedup_mixed_vs_plain"] = round(
-            batches["mixed"][0]["value"] / batches["plain"][0]["value"], 3)
-        result["batched"]["speedup_auto_vs_plain"] = round(
-            batches["auto"][0]["value"] / batches["plain"][0]["value"], 3)
-        seq, seq_outs = sequential_batch(max(2, bsteps // 4), 1)
-        result["batched"]["sequential"] = seq
-        result["batched"]["speedup_batched_vs_sequential"] = round(batches["plain"][0]["value"] / seq["value"], 3)
-    box = None
-    if "box" in lines:
-        box, box_out = box_line(img, x, args.steps, args.warmup)
-        result["box"] = box
-    # accuracy of the timed outputs against the FP64 oracle (the CPU leg)
+                  config=dict(workload="batch64_u8_local", images=64, megapixels=head["megapixels"], input="u8",
+                              sigma_s="U[2,16] per image", sigma_r="U[10,60] per image", eps=1e-3,
+                              t_mode="local", blur="auto", variants=head["variants"],
+                              pairs_total=head["pairs_total"], launch="one captured graph of grouped launches"),
+                  roofline=head["roofline"], stages=head["stages"])
+    if "batch" in which:
+        bsteps = max(5, args.steps // 5)
+        plain, _, _ = batch_run("iir_f32", bsteps, 2)
+        mixed, mreps, mouts = batch_run("toeplitz_f16x2", bsteps, 2)
+        seq = sequential_batch(max(2, bsteps // 4), 1)
+        result["batched"] = dict(plain=plain, mixed=mixed, sequential=seq,
+                                 speedup_mixed_vs_plain=round(mixed["value"] / plain["value"], 3),
+                                 speedup_auto_vs_plain=round(head["value"] / plain["value"], 3),
+                                 speedup_batched_vs_sequential=round(plain["value"] / seq["value"], 3))
+    result["configs"] = config_lines(args.steps, args.warmup, which)
+    if not args.no_check:
+        result.update(batch_errors(reps, outs))
+        if "batch" in which:
+            result["batched"]["mixed"].update(batch_errors(mreps, mouts))
     if not args.no_cpu_baseline:
-        samples = [smp for v in batches.values() for smp in v[1]]
-        refs, cpu = cpu_baseline(img, c, mixed=mixed, batch=[(it, r, p) for it, r, p, _ in samples] or None,
-                                 box=(box_out[0], box_out[1]) if box is not None else None)
-        ref = refs["iir"]
-        err = np.abs(got - ref["out"])
-        result["max_err"] = float(err.max())
-        result["rms_err"] = float(np.sqrt((err ** 2).mean()))
-        result["err_ok"] = bool(err.max() <= 2e-3 and (ref["N"], ref["M"]) == (rep["N"], rep["M"]))
-        result["cpu_baseline"] = cpu
-        if mixed is not None:
-            e2 = np.abs(mixed_out - refs["fir"]["out"])
-            mixed.update(max_err=float(e2.max()), rms_err=float(np.sqrt((e2 ** 2).mean())),
-                         err_ok=bool(e2.max() <= 2e-3 and (refs["fir"]["N"], refs["fir"]["M"]) == (mixed["N"], mixed["M"])))
-        if batches:
-            errs = [float(np.abs(v - r).max()) for (_, _, _, v), r in zip(samples, refs["batch"])]
-            i0 = 0
-            for key, (line, smp) in batches.items():
-                worst = max(errs[i0:i0 + len(smp)])
-                i0 += len(smp)
-                line.update(sampled_max_err=worst, err_ok=bool(worst <= 2e-3))
-        if box is not None:
-            rb = refs["box"]
-            e3 = np.abs(box_out[2] - rb["vals"])
-            box.update(sampled_max_err=float(e3.max()),
-                       err_ok=bool(e3.max() <= 2e-3 and (rb["T"], rb["N"], rb["M"]) == (box["T"], box["N"], box["M"])))
+        result["cpu_baseline"] = cpu_baseline(reps)
     print(json.dumps(result), flush=True)
 
 
