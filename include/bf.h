@@ -88,6 +88,19 @@ typedef enum {
                                   Toeplitz variants only; BF_BLUR_AUTO picks among them. */
 } bf_spatial;
 
+/* Range kernel of SHIFTABLE-BF (Section 1.2).  Both tend to the Gaussian of
+ * sigma_r (Section 1.3). */
+typedef enum {
+  BF_RANGE_RAISED_COSINE = 0,  /* eq. (RC): cos^N(s / (sqrt(N) sigma_r)), N from T (Table 1
+                                  rule), truncated by Algorithm 2 step 4                  */
+  BF_RANGE_POLYNOMIAL = 1      /* eq. (RPconv): (1 - s^2 / (2 N sigma_r^2))^N with the
+                                  smallest N >= 0.5 (T/sigma_r)^2, expanded in Chebyshev
+                                  polynomials of the intensity over [0, value_range]; the
+                                  orders whose summed coefficient bound is <= eps dropped.
+                                  8-bit input and global T only; plans whose FP32 sums
+                                  would cancel (T far below value_range) are refused.    */
+} bf_range_kernel;
+
 typedef struct {
   int32_t height, width;   /* >= 1                                                   */
   int64_t in_pitch;        /* elements between input rows; 0 => width               */
@@ -104,6 +117,20 @@ typedef struct {
                               the sigma_r bands (given in 8-bit units) of step 4. */
   bf_blur blur;
   bf_spatial spatial;
+  bf_range_kernel range_kernel;
+  /* Non-local means (the paper's closing section, eqs. (NL1), (NL2)): with
+   * patch_size p >= 2 the range kernel compares the patches u_1 = (0, 0),
+   * u_k = (patch_dy[k-1], patch_dx[k-1]) (k = 2..p, |offsets| <= 2) of the
+   * output pixel and of each neighbour: the product of p raised cosines of
+   * sigma_r, each of order N and truncation M from T as for the bilateral
+   * filter, expanded into one term per multi-index of kept frequencies.
+   * Patch samples outside the image take the nearest pixel.  8-bit input,
+   * the raised-cosine kernel and the Toeplitz split variants only
+   * (BF_BLUR_TOEPLITZ_F16X2 / BF16X2; the box spatial filter gives eq. (NL1)
+   * as written).  0 or 1: the bilateral filter.  patch_dy[0], patch_dx[0]
+   * must be 0. */
+  int32_t patch_size;
+  int32_t patch_dy[4], patch_dx[4];
 } bf_params;
 
 /* Per-image result summary (filled only when requested; requesting it makes
@@ -111,9 +138,12 @@ typedef struct {
 typedef struct {
   double T;          /* dynamic range used (raw maximum for float input)      */
   int32_t T_used;    /* integer T indexing the order table (ceil for floats)   */
-  int32_t N, M;      /* order and truncation                                   */
-  int32_t kept;      /* kept terms N - 2M + 1                                  */
-  int32_t pairs;     /* frequency pairs blurred (with the zero frequency)      */
+  int32_t N, M;      /* order and truncation (polynomial kernel: M = highest
+                        kept Chebyshev order J)                                */
+  int32_t kept;      /* kept terms N - 2M + 1 (polynomial kernel: J + 1; per
+                        patch sample for non-local means)                      */
+  int32_t pairs;     /* frequency pairs blurred (with the zero frequency; for
+                        non-local means the folded multi-indices)              */
   int32_t variant;   /* bf_blur actually run                                   */
   int32_t flags;     /* bit0 non-finite input, bit1 T above value_range        */
   int64_t q_nonpos;  /* pixels whose denominator (f2) was <= 0 (output = input) */

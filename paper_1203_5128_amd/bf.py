@@ -48,7 +48,8 @@ class bf_params(ctypes.Structure):
                 ("sigma_r", ctypes.c_double), ("eps", ctypes.c_double),
                 ("radius", ctypes.c_int32), ("t_mode", ctypes.c_int),
                 ("t_value", ctypes.c_double), ("value_range", ctypes.c_double),
-                ("blur", ctypes.c_int), ("spatial", ctypes.c_int)]
+                ("blur", ctypes.c_int), ("spatial", ctypes.c_int), ("range_kernel", ctypes.c_int),
+                ("patch_size", ctypes.c_int32), ("patch_dy", ctypes.c_int32 * 4), ("patch_dx", ctypes.c_int32 * 4)]
 
 
 class bf_report(ctypes.Structure):
@@ -120,11 +121,14 @@ def _check(status: int):
 
 
 SPATIALS = {"gaussian": 0, "box": 1, "gaussian_fir": 2}
+RANGE_KERNELS = {"raised_cosine": 0, "polynomial": 1}
 
 
 def make_params(H, W, dtype="u8", sigma_s=3.0, sigma_r=30.0, eps=1e-3, radius=0, t_mode="local",
                 t_value=0.0, value_range=0.0, blur="iir_f32", in_pitch=0, out_pitch=0,
-                spatial="gaussian") -> bf_params:
+                spatial="gaussian", range_kernel="raised_cosine", patch=None) -> bf_params:
+    """patch: None for the bilateral filter, or the non-local-means patch as
+    a list of (dy, dx) offsets starting with (0, 0)."""
     p = bf_params()
     p.height, p.width = int(H), int(W)
     p.in_pitch, p.out_pitch = int(in_pitch), int(out_pitch)
@@ -135,6 +139,11 @@ def make_params(H, W, dtype="u8", sigma_s=3.0, sigma_r=30.0, eps=1e-3, radius=0,
     p.t_value, p.value_range = float(t_value), float(value_range)
     p.blur = BLURS[blur] if isinstance(blur, str) else int(blur)
     p.spatial = SPATIALS[spatial] if isinstance(spatial, str) else int(spatial)
+    p.range_kernel = RANGE_KERNELS[range_kernel] if isinstance(range_kernel, str) else int(range_kernel)
+    if patch:
+        p.patch_size = len(patch)
+        for k, (dy, dx) in enumerate(patch[:4]):
+            p.patch_dy[k], p.patch_dx[k] = int(dy), int(dx)
     return p
 
 

@@ -54,6 +54,13 @@ struct ImagePlan {
   float *d_pc = nullptr;
   float *d_iir = nullptr;
   float *d_taps = nullptr;  // Toeplitz path: FIR taps
+  // polynomial range kernel: basis values and coefficients per pair slot and
+  // intensity (NULL for the raised cosine)
+  bool poly = false;
+  float2 *d_rgen = nullptr, *d_rcomb = nullptr;
+  // non-local means: patch samples per pixel (p >= 2), packed per pixel into
+  // the workspace's patch image before the blur
+  bool nlm = false;
   ToepCfg tc{};
   size_t z_per_pair = 0;    // workspace bytes of the smoothed images of one pair
   void *d_state = nullptr;  // T_used, flags, T_raw, q_nonpos
@@ -64,7 +71,7 @@ struct ImagePlan {
     Geom g{};
     ToepCfg tc{};
     int KC = 0;
-    size_t rowmax = 0, lut = 0, pq = 0, z = 0, end = 0;
+    size_t patch = 0, rowmax = 0, lut = 0, pq = 0, z = 0, end = 0;
   } na;
 };
 
@@ -97,6 +104,11 @@ bool toeplitz_shape(int variant, int R, int H, int lds_kb, ToepCfg &tc) {
 
 size_t elem_size(bf_dtype d) { return d == BF_U8 ? 1 : (d == BF_U16 ? 2 : 4); }
 
+// Largest sum of absolute Chebyshev coefficients (over the kept orders, worst
+// intensity) a polynomial-kernel plan accepts: the FP32 sums of the smoothed
+// images lose about that factor against their result.
+constexpr double kRpKappaMax = 16.0;
+
 // Size of the static working memory of bf_filter_noalloc (per device).
 constexpr size_t kScratchBytes = (size_t)256 << 20;
 
@@ -110,7 +122,8 @@ struct bf_plan_s {
   float4 *d_Z = nullptr;
   float2 *d_PQ = nullptr;
   float2 *d_lut = nullptr;  // cos/sin tables of the pairs in flight (8-bit inputs)
-  size_t rowmax_bytes = 0, Z_bytes = 0, PQ_bytes = 0, lut_bytes = 0;
+  void *d_patch = nullptr;  // non-local means: the patch image
+  size_t rowmax_bytes = 0, Z_bytes = 0, PQ_bytes = 0, lut_bytes = 0, patch_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // stage timing (bf_profile)
   bool prof = false;
@@ -171,6 +184,8 @@ DevTables tables_of(const ImagePlan &ip) {
   t.pm = ip.d_pm;
   t.pc = ip.d_pc;
   t.T_cap = ip.T_cap;
+  t.lut_gen = ip.d_rgen;
+  t.lut_comb = ip.d_rcomb;
   return t;
 }
 
@@ -193,6 +208,25 @@ bf_status check_params(const bf_params &p) {
   if (p.blur < BF_BLUR_AUTO || p.blur > BF_BLUR_TOEPLITZ_BF16X2) return fail(BF_ERR_INVALID_ARG, "unknown blur");
   if (p.spatial != BF_SPATIAL_GAUSSIAN && p.spatial != BF_SPATIAL_BOX && p.spatial != BF_SPATIAL_GAUSSIAN_FIR)
     return fail(BF_ERR_INVALID_ARG, "unknown spatial kernel");
+  if (p.range_kernel != BF_RANGE_RAISED_COSINE && p.range_kernel != BF_RANGE_POLYNOMIAL)
+    return fail(BF_ERR_INVALID_ARG, "unknown range kernel");
+  if (p.range_kernel == BF_RANGE_POLYNOMIAL && p.dtype != BF_U8)
+    return fail(BF_ERR_UNSUPPORTED, "the polynomial range kernel takes 8-bit images");
+  if (p.range_kernel == BF_RANGE_POLYNOMIAL && p.t_mode != BF_T_GLOBAL)
+    return fail(BF_ERR_UNSUPPORTED, "the polynomial range kernel needs a global T");
+  if (p.patch_size < 0 || p.patch_size > kNlmMaxPatch) return fail(BF_ERR_INVALID_ARG, "patch_size outside 0..4");
+  if (p.patch_size >= 2) {
+    if (p.patch_dy[0] != 0 || p.patch_dx[0] != 0)
+      return fail(BF_ERR_INVALID_ARG, "the first patch sample must be the pixel itself (offset 0, 0)");
+    for (int k = 1; k < p.patch_size; k++)
+      if (std::abs(p.patch_dy[k]) > kNlmMaxOffset || std::abs(p.patch_dx[k]) > kNlmMaxOffset)
+        return fail(BF_ERR_INVALID_ARG, "patch offsets must lie within +-2");
+    if (p.dtype != BF_U8) return fail(BF_ERR_UNSUPPORTED, "non-local means takes 8-bit images");
+    if (p.range_kernel != BF_RANGE_RAISED_COSINE)
+      return fail(BF_ERR_UNSUPPORTED, "non-local means uses the raised-cosine range kernel");
+    if (p.blur != BF_BLUR_TOEPLITZ_F16X2 && p.blur != BF_BLUR_TOEPLITZ_BF16X2)
+      return fail(BF_ERR_UNSUPPORTED, "non-local means runs on the split Toeplitz blur variants");
+  }
   if (p.spatial == BF_SPATIAL_BOX && p.blur == BF_BLUR_IIR_F32)
     return fail(BF_ERR_UNSUPPORTED, "the box spatial filter runs on the Toeplitz blur variants");
   if (p.spatial == BF_SPATIAL_GAUSSIAN_FIR && p.blur == BF_BLUR_IIR_F32)
@@ -299,17 +333,19 @@ void noalloc_shape(ImagePlan &ip) {
   const size_t state = align256(kStateBytes);
   const size_t rowmax =
       (ip.p.t_mode == BF_T_LOCAL && !range_tile_ok(ip.R, ip.p.dtype)) ? align256(px * elem_size(ip.p.dtype)) : 0;
+  const size_t patch = ip.nlm ? align256(px * sizeof(Patch8x4)) : 0;
   ImagePlan::NoAlloc na;
   auto fits = [&](int kc) {
     set_chunk(ip, kc);
-    na.rowmax = state;
+    na.patch = state;
+    na.rowmax = na.patch + patch;
     na.lut = na.rowmax + rowmax;
     na.pq = na.lut + (toep ? 0 : align256((size_t)kc * 256 * sizeof(float2)));
     na.z = na.pq + align256((size_t)(toep ? ip.tc.groups : ip.g.hgroups) * px * sizeof(float2));
     na.end = na.z + align256((size_t)kc * ip.z_per_pair);
     return na.end <= kScratchBytes;
   };
-  const size_t fixed = state + rowmax + align256(px * sizeof(float2));
+  const size_t fixed = state + patch + rowmax + align256(px * sizeof(float2));
   int kc = fixed >= kScratchBytes ? 1
                                   : (int)std::max<size_t>(1, std::min<size_t>((size_t)ip.tab.K_max,
                                                                               (kScratchBytes - fixed) / ip.z_per_pair));
@@ -351,7 +387,36 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   if (is_toeplitz(variant) && !toeplitz_shape(variant, ip.R, p.height, kn.lds_kb, ip.tc))
     return fail(BF_ERR_UNSUPPORTED, "radius above 120 for the Toeplitz blur");
   std::string err;
-  if (!build_order_table(p.sigma_r, p.eps, ip.range, ip.T_cap, ip.tab, err)) return fail(BF_ERR_UNSUPPORTED, err);
+  RpTable rt;
+  ip.poly = p.range_kernel == BF_RANGE_POLYNOMIAL;
+  if (ip.poly) {
+    // one entry for the plan's global T: pair slots of two Chebyshev orders,
+    // unit weights (the coefficients sit in the per-intensity table)
+    if (!build_rp_table(p.sigma_r, p.eps, ip.range, Tg, rt, err)) return fail(BF_ERR_UNSUPPORTED, err);
+    if (rt.kappa > kRpKappaMax)
+      return fail(BF_ERR_UNSUPPORTED, "polynomial kernel: the Chebyshev coefficients sum to " +
+                                          std::to_string(rt.kappa) + " (T far below value_range), FP32 sums would cancel");
+    OrderTable &t = ip.tab;
+    t = OrderTable();
+    t.T_cap = ip.T_cap;
+    t.idx_of_T.assign((size_t)ip.T_cap + 1, 0);
+    OrderEntry oe{};
+    oe.N = rt.N;
+    oe.M = rt.J;
+    oe.K = rt.K;
+    oe.off = 0;
+    t.ent.push_back(oe);
+    t.pm.assign(rt.K, 0);
+    t.pc.assign(rt.K, 1.0f);
+    t.K_max = rt.K;
+    t.N_max = rt.N;
+  } else if (p.patch_size >= 2) {
+    ip.nlm = true;
+    if (!build_nlm_table(p.sigma_r, p.eps, ip.range, ip.T_cap, p.patch_size, ip.tab, err))
+      return fail(BF_ERR_UNSUPPORTED, err);
+  } else if (!build_order_table(p.sigma_r, p.eps, ip.range, ip.T_cap, ip.tab, err)) {
+    return fail(BF_ERR_UNSUPPORTED, err);
+  }
   std::vector<float> iir, taps;
   if (is_toeplitz(variant)) {
     std::vector<double> t;
@@ -401,6 +466,10 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   if ((st = upload((void **)&ip.d_pc, ip.tab.pc.data(), ip.tab.pc.size() * 4))) return st;
   if ((st = upload((void **)&ip.d_iir, iir.data(), iir.size() * 4))) return st;
   if ((st = upload((void **)&ip.d_taps, taps.data(), taps.size() * 4))) return st;
+  if (ip.poly) {
+    if ((st = upload((void **)&ip.d_rgen, rt.gen.data(), rt.gen.size() * 4))) return st;
+    if ((st = upload((void **)&ip.d_rcomb, rt.comb.data(), rt.comb.size() * 4))) return st;
+  }
   ip.tc.taps = ip.d_taps;
   {
     // the range accumulator and counter must start at zero
@@ -431,6 +500,8 @@ void free_image(ImagePlan &ip) {
   (void)hipFree(ip.d_pc);
   (void)hipFree(ip.d_iir);
   (void)hipFree(ip.d_taps);
+  (void)hipFree(ip.d_rgen);
+  (void)hipFree(ip.d_rcomb);
   (void)hipFree(ip.d_state);
 }
 
@@ -482,6 +553,7 @@ struct Workspace {
   float4 *Z;
   float2 *PQ;
   float2 *lut;
+  void *patch;  // non-local means: H x W packed patch samples
 };
 // Launch shape of one image: geometry, Toeplitz configuration, pairs per
 // launch and the device state (T, flags, range accumulators) it runs with.
@@ -494,7 +566,7 @@ struct Shape {
 bf_status run_image_ws(const Workspace &ws, const StageRec &rec, const ImagePlan &ip, const Shape &sh,
                        const void *d_in, float *d_out, hipStream_t s);
 bf_status run_image(bf_plan_s *pl, ImagePlan &ip, const void *d_in, float *d_out, hipStream_t s) {
-  return run_image_ws(Workspace{pl->d_rowmax, pl->d_Z, pl->d_PQ, pl->d_lut}, pl->rec, ip,
+  return run_image_ws(Workspace{pl->d_rowmax, pl->d_Z, pl->d_PQ, pl->d_lut, pl->d_patch}, pl->rec, ip,
                       Shape{&ip.g, &ip.tc, ip.KC, ip.d_state}, d_in, d_out, s);
 }
 
@@ -551,6 +623,26 @@ bf_status run_image_ws(const Workspace &ws, const StageRec &rec, const ImagePlan
     if (e != hipSuccess) return dev_fail(e, "reset");
   }
   const int Kmax = ip.tab.K_max;
+  if (ip.nlm) {
+    // the patch samples of every pixel, then the blur of the multi-index
+    // terms reads the packed words in place of the image
+    PatchArgs pa{(const uint8_t *)d_in, g.pitch, g.H, g.W, ip.p.patch_size, {}, {}, (Patch8x4 *)ws.patch};
+    for (int k = 0; k < kNlmMaxPatch; k++) {
+      pa.dy[k] = k < ip.p.patch_size ? ip.p.patch_dy[k] : 0;
+      pa.dx[k] = k < ip.p.patch_size ? ip.p.patch_dx[k] : 0;
+    }
+    e = launch_patch_pack(s, pa);
+    if (e != hipSuccess) return dev_fail(e, "patch samples");
+    Geom gp = g;
+    gp.pitch = g.W;
+    for (int k0 = 0; k0 < Kmax; k0 += KC) {
+      const int kcount = std::min(KC, Kmax - k0);
+      e = launch_toeplitz_chunk(s, kDtPatch, ip.variant, ws.patch, d_out, gp, tab, st, *sh.tc, k0, kcount, ws.Z,
+                                ws.PQ, k0 == 0, k0 + KC >= Kmax, rec);
+      if (e != hipSuccess) return dev_fail(e, "Toeplitz blur (non-local means)");
+    }
+    return BF_OK;
+  }
   if (is_toeplitz(ip.variant)) {
     for (int k0 = 0; k0 < Kmax; k0 += KC) {
       const int kcount = std::min(KC, Kmax - k0);
@@ -571,7 +663,7 @@ bf_status run_image_ws(const Workspace &ws, const StageRec &rec, const ImagePlan
 
 // Whether an image of the plan runs inside the grouped launches of a batch
 // (all its pairs in one launch).
-bool in_group(const bf_plan_s *pl, const ImagePlan &ip) { return pl->grouped && ip.KC == ip.tab.K_max; }
+bool in_group(const bf_plan_s *pl, const ImagePlan &ip) { return pl->grouped && ip.KC == ip.tab.K_max && !ip.nlm; }
 
 // Host image of the argument arrays of one batch, packed for one upload.
 struct ArgPack {
@@ -902,7 +994,7 @@ bf_status fill_report(const ImagePlan &ip, const void *d_state, bf_report *rep, 
   rep->T_used = Tu;
   rep->N = oe.N;
   rep->M = oe.M;
-  rep->kept = oe.N - 2 * oe.M + 1;
+  rep->kept = ip.poly ? oe.M + 1 : oe.N - 2 * oe.M + 1;
   rep->pairs = oe.K;
   rep->variant = ip.variant;
   rep->flags = flags;
@@ -944,7 +1036,7 @@ static bf_status create_plan(const bf_params *params, int32_t n_images, const Kn
   bf_plan_s *pl = new bf_plan_s();
   (void)hipGetDevice(&pl->device);
   pl->im.resize(n_images);
-  size_t rowmax = 0, Z = 0, PQ = 0, lut = 0;
+  size_t rowmax = 0, Z = 0, PQ = 0, lut = 0, patch = 0;
   for (int i = 0; i < n_images; i++) {
     bf_status s = prepare_image(params[i], pl->im[i], knobs ? knobs[i] : Knobs());
     if (s) {
@@ -959,11 +1051,13 @@ static bf_status create_plan(const bf_params *params, int32_t n_images, const Kn
     }
     Z = std::max(Z, (size_t)ip.KC * ip.z_per_pair);
     PQ = std::max(PQ, (size_t)(is_toeplitz(ip.variant) ? ip.tc.groups : g.hgroups) * g.H * g.W * sizeof(float2));
+    if (ip.nlm) patch = std::max(patch, (size_t)g.H * g.W * sizeof(Patch8x4));
   }
   bf_status s;
   if ((s = ensure(&pl->d_rowmax, pl->rowmax_bytes, rowmax)) ||
       (s = ensure((void **)&pl->d_Z, pl->Z_bytes, Z)) || (s = ensure((void **)&pl->d_PQ, pl->PQ_bytes, PQ)) ||
-      (s = ensure((void **)&pl->d_lut, pl->lut_bytes, lut))) {
+      (s = ensure((void **)&pl->d_lut, pl->lut_bytes, lut)) ||
+      (patch && (s = ensure(&pl->d_patch, pl->patch_bytes, patch)))) {
     bf_plan_destroy(pl);
     return s;
   }
@@ -1081,6 +1175,7 @@ void bf_plan_destroy(bf_plan_t pl) {
   (void)hipFree(pl->d_Z);
   (void)hipFree(pl->d_PQ);
   (void)hipFree(pl->d_lut);
+  (void)hipFree(pl->d_patch);
   if (pl->ev0) (void)hipEventDestroy(pl->ev0);
   if (pl->ev1) (void)hipEventDestroy(pl->ev1);
   delete pl;
@@ -1156,7 +1251,8 @@ bf_status bf_filter_noalloc(bf_plan_t pl, const void *d_in, float *d_out, void *
   e = launch_zero(s, base, align256(kStateBytes));
   if (e != hipSuccess) return dev_fail(e, "clear state");
   const ImagePlan::NoAlloc &na = ip.na;
-  const Workspace ws{base + na.rowmax, (float4 *)(base + na.z), (float2 *)(base + na.pq), (float2 *)(base + na.lut)};
+  const Workspace ws{base + na.rowmax, (float4 *)(base + na.z), (float2 *)(base + na.pq), (float2 *)(base + na.lut),
+                     base + na.patch};
   st = run_image_ws(ws, StageRec(), ip, Shape{&na.g, &na.tc, na.KC, base}, d_in, d_out, s);
   if (st) return st;
   if (!rep) return BF_OK;

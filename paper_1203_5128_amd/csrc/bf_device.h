@@ -10,10 +10,20 @@
 
 namespace bfi {
 
+// Non-local means: the 8-bit samples f(x + u_k) of a pixel's patch packed
+// into one word (sample k in byte k, u_1 = 0 in byte 0), the element type the
+// Toeplitz kernels read in place of the image.  Internal dtype code kDtPatch.
+struct Patch8x4 {
+  uint32_t v;
+};
+constexpr bf_dtype kDtPatch = (bf_dtype)3;
+
 // bf_dtype of an element type
 template <typename Tin>
 constexpr bf_dtype dtype_of() {
-  return std::is_same<Tin, uint8_t>::value ? BF_U8 : (std::is_same<Tin, uint16_t>::value ? BF_U16 : BF_F32);
+  return std::is_same<Tin, Patch8x4>::value
+             ? kDtPatch
+             : (std::is_same<Tin, uint8_t>::value ? BF_U8 : (std::is_same<Tin, uint16_t>::value ? BF_U16 : BF_F32));
 }
 
 // Order table on the device (uploaded copy of OrderTable).
@@ -23,6 +33,11 @@ struct DevTables {
   const int32_t *pm;
   const float *pc;
   int32_t T_cap;
+  // polynomial range kernel (8-bit input): per pair slot and intensity the
+  // basis values of the smoothed images and the coefficients of the combine,
+  // which take the place of cos/sin of the raised cosine (NULL otherwise)
+  const float2 *lut_gen;
+  const float2 *lut_comb;
 };
 
 // Per-image scalars written by the range stage and read by every later stage.
@@ -233,6 +248,16 @@ hipError_t launch_fill_checker(hipStream_t s, bf_dtype dt, void *f, int H, int W
 hipError_t launch_reset(hipStream_t s, DevState st, int32_t T_used, double T_raw);
 // Zero fill of `bytes` (a multiple of 4) at p, as a kernel.
 hipError_t launch_zero(hipStream_t s, void *p, size_t bytes);
+// Non-local means: the patch image (H x W words, row pitch W) of an 8-bit
+// image, sample k at (clamp(y + dy[k]), clamp(x + dx[k])), k < p.
+struct PatchArgs {
+  const uint8_t *f;
+  int64_t pitch;
+  int H, W, p;
+  int dy[4], dx[4];
+  Patch8x4 *out;
+};
+hipError_t launch_patch_pack(hipStream_t s, const PatchArgs &a);
 // Algorithm 1 for one image, with the state reset it needs (the one-launch
 // tile kernel when range_tile_ok(R, dt), else reset + row pass + column pass).
 hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,

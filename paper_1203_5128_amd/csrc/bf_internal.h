@@ -52,9 +52,28 @@ struct OrderTable {
 };
 
 int order_N(double T, double sigma_r);
+// Non-local means: p patch samples share N and M; each pair is a folded
+// multi-index (m_1..m_p) (first non-zero component negative, or all zero),
+// packed as p signed bytes in pm, with weight 2 prod c (1 for all zero).
+constexpr int kNlmMaxPatch = 4;
+constexpr int kNlmMaxOffset = 2;
+bool build_nlm_table(double sigma_r, double eps, double value_range, int32_t T_cap, int p, OrderTable &out,
+                     std::string &err);
 int trunc_M(int N, double sigma_r8, double eps);
 bool build_order_table(double sigma_r, double eps, double value_range, int32_t T_cap,
                        OrderTable &out, std::string &err);
+
+// ------------------------------------- polynomial range kernel (eq. (RP))
+// Order N, highest kept Chebyshev order J, slots of two orders K = ceil((J+1)/2),
+// and per slot k and 8-bit intensity v (float pairs, [k][v][2]): the basis
+// values (T_2k, T_2k+1)(x(v)) and the coefficients (c_2k, c_2k+1)(v).
+// kappa = max_v sum_j |c_j(v)|, the cancellation factor of the FP32 sums.
+struct RpTable {
+  int N = 0, J = 0, K = 0;
+  double kappa = 0.0;
+  std::vector<float> gen, comb;
+};
+bool build_rp_table(double sigma_r, double eps, double L, double T, RpTable &out, std::string &err);
 
 // ------------------------------------------- recursive Gaussian constants
 // State of one direction of the cascade after element n: (s[n], w[n], d[n])

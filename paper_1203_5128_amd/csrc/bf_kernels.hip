@@ -1022,10 +1022,18 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
     float2 *lt = lut + (it & 1) * 257;
     if constexpr (kLut) {
       // the other buffer was last read before the previous pair's barrier
-      build_lut(lt, m, e.qfix, e.alpha_turn, tid, kHThreads);
+      if (tab.lut_gen) {
+        // polynomial kernel: basis values per intensity from the table; the
+        // horizontal pass combines with the coefficients instead
+        const size_t row = (size_t)(e.off + k0 + kl) * 256 + tid;
+        lt[tid] = tab.lut_gen[row];
+        if (cbx == 0) glut[(size_t)kl * 256 + tid] = tab.lut_comb[row];
+      } else {
+        build_lut(lt, m, e.qfix, e.alpha_turn, tid, kHThreads);
+        // one workgroup per pair also leaves the table for the horizontal pass
+        if (cbx == 0) glut[(size_t)kl * 256 + tid] = lt[tid];
+      }
       if (tid == 0) lt[256] = make_float2(0.f, 0.f);
-      // one workgroup per pair also leaves the table for the horizontal pass
-      if (cbx == 0) glut[(size_t)kl * 256 + tid] = lt[tid];
       __syncthreads();
     } else if (it == 0) {
       __syncthreads();  // the filter constants
@@ -1343,6 +1351,29 @@ hipError_t launch_fill_checker(hipStream_t s, bf_dtype dt, void *f, int H, int W
   return hipGetLastError();
 }
 
+// Non-local means: each pixel's patch samples f(x + u_k), k < p, clamped
+// into the image, packed into one word (byte k), one thread per pixel.
+__global__ __launch_bounds__(256) void k_patch_pack(PatchArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)a.H * a.W) return;
+  const int y = (int)(i / a.W), x = (int)(i % a.W);
+  uint32_t v = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    if (k < a.p) {
+      const int yy = min(max(y + a.dy[k], 0), a.H - 1), xx = min(max(x + a.dx[k], 0), a.W - 1);
+      v |= (uint32_t)a.f[(int64_t)yy * a.pitch + xx] << (8 * k);
+    }
+  }
+  a.out[i] = Patch8x4{v};
+}
+hipError_t launch_patch_pack(hipStream_t s, const PatchArgs &a) {
+  const int64_t n = (int64_t)a.H * a.W;
+  if (n <= 0 || a.p < 1 || a.p > 4) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_patch_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 // Zero fill of n 32-bit words (a kernel, so that it can sit in a captured
 // graph where a memset node could not).
 __global__ __launch_bounds__(256) void k_zero_words(uint32_t *__restrict__ p, int64_t n) {
@@ -1494,6 +1525,10 @@ hipError_t launch_finish(hipStream_t s, bf_dtype dt, const FinishArgs *one, cons
     case BF_U16:
       if (one) hipLaunchKernelGGL(k_finish<uint16_t>, dim3(one->gg.gx), dim3(256), 0, s, *one);
       else if (total > 0) hipLaunchKernelGGL(k_finish_grp<uint16_t>, dim3(total), dim3(256), 0, s, arr, start, n);
+      break;
+    case kDtPatch:  // non-local means: single images only
+      if (one) hipLaunchKernelGGL(k_finish<Patch8x4>, dim3(one->gg.gx), dim3(256), 0, s, *one);
+      else if (total > 0) return hipErrorInvalidValue;
       break;
     default:
       if (one) hipLaunchKernelGGL(k_finish<float>, dim3(one->gg.gx), dim3(256), 0, s, *one);

@@ -16,6 +16,11 @@ template <typename Tin>
 __device__ __forceinline__ float fval(Tin v) {
   return (float)v;
 }
+// a patch word stands for its centre sample (u_1 = 0)
+template <>
+__device__ __forceinline__ float fval<Patch8x4>(Patch8x4 v) {
+  return (float)(v.v & 0xFFu);
+}
 
 __device__ __forceinline__ const OrderEntry &lookup(const DevTables &tab, const int32_t *Tu) {
   int T = *Tu;
@@ -68,9 +73,11 @@ __device__ __forceinline__ UEntry uniform_entry(const DevTables &tab, const int3
 struct Freq {
   uint64_t qm;
   double mat;
+  uint64_t q;  // non-local means: frac(alpha/2pi) 2^64 and the packed
+  int32_t mp;  // multi-index (p signed bytes)
 };
 __device__ __forceinline__ Freq make_freq(int32_t m, uint64_t q, double at) {
-  return Freq{(uint64_t)(int64_t)m * q, (double)m * at};
+  return Freq{(uint64_t)(int64_t)m * q, (double)m * at, q, m};
 }
 template <typename Tin>
 __device__ __forceinline__ uint32_t phase_turn(Tin v, const Freq &fq) {
@@ -85,6 +92,16 @@ __device__ __forceinline__ uint32_t phase_turn(Tin v, const Freq &fq) {
   } else {
     return (uint32_t)(((uint64_t)(uint32_t)v * fq.qm) >> 32);
   }
+}
+// Non-local means: the phase alpha sum_k m_k f(x + u_k) of a multi-index;
+// sum_k m_k f_k is an exact integer (|m_k| <= 127, f_k <= 255, p <= 4),
+// reduced like a single frequency's m f.
+template <>
+__device__ __forceinline__ uint32_t phase_turn<Patch8x4>(Patch8x4 v, const Freq &fq) {
+  int32_t u = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) u += (int32_t)(int8_t)(fq.mp >> (8 * k)) * (int32_t)((v.v >> (8 * k)) & 0xFFu);
+  return (uint32_t)(((uint64_t)(int64_t)u * fq.q) >> 32);
 }
 template <typename Tin>
 __device__ __forceinline__ uint32_t phase_turn(int32_t m, Tin v, uint64_t q, double at) {

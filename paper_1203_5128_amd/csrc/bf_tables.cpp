@@ -6,6 +6,7 @@
 // the sigma_r band: none above 40, eq. (trunc) in (10, 40], eq. (Chernoff) at
 // or below 10, sigma_r in 8-bit units), eq. (approx) for the kept terms and
 // eq. (expansion) for their weights and frequencies.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -97,6 +98,146 @@ bool build_order_table(double sigma_r, double eps, double value_range, int32_t T
     if (e.K > out.K_max) out.K_max = e.K;
     if (N > out.N_max) out.N_max = N;
   }
+  return true;
+}
+
+// ---------------------------------------------------- non-local means ---
+// The product over the p patch samples of the truncated raised cosine of
+// eq. (approx): prod_k sum_{n_k} c_{n_k} cos(m_k alpha s_k) with m = 2n - N,
+// alpha = 1 / (sqrt(N) sigma_r).  Expanding the product of cosines gives one
+// cosine of alpha sum_k m_k s_k per multi-index; m and -m give the same term,
+// so each conjugate pair is kept once with twice the weight.
+bool build_nlm_table(double sigma_r, double eps, double value_range, int32_t T_cap, int p, OrderTable &out,
+                     std::string &err) {
+  out = OrderTable();
+  if (p < 2 || p > kNlmMaxPatch) { err = "patch size outside 2..4"; return false; }
+  out.T_cap = T_cap;
+  out.idx_of_T.resize((size_t)T_cap + 1);
+  const double sigma_r8 = sigma_r * 255.0 / value_range;
+  std::map<int, int> seen;
+  const long double two_pi = 6.283185307179586476925286766559L;
+  for (int32_t T = 0; T <= T_cap; T++) {
+    const int N = order_N((double)T, sigma_r);
+    auto it = seen.find(N);
+    if (it != seen.end()) { out.idx_of_T[T] = it->second; continue; }
+    const int M = trunc_M(N, sigma_r8, eps);
+    if (N - 2 * M > 127) { err = "non-local means: kept frequencies above 127 (sigma_r too small)"; return false; }
+    const int L = N - 2 * M + 1;
+    double total = 1.0;
+    for (int k = 0; k < p; k++) total *= L;
+    if (out.pm.size() + total / 2 + 1 > (double)(4 << 20)) {
+      err = "non-local means: more than 4M frequency multi-indices (sigma_r too small for the patch size)";
+      return false;
+    }
+    std::vector<double> w(L);
+    for (int i = 0; i < L; i++) w[i] = std::exp(log_binom_weight(N, M + i));
+    OrderEntry e;
+    e.N = N;
+    e.M = M;
+    e.off = (int32_t)out.pm.size();
+    std::vector<int> idx(p, 0);  // kept-term index per sample, sample 0 slowest
+    for (;;) {
+      int first = 0;  // first non-zero m
+      double c = 1.0;
+      uint32_t packed = 0;
+      for (int k = 0; k < p; k++) {
+        const int m = 2 * (M + idx[k]) - N;
+        if (!first && m) first = m;
+        c *= w[idx[k]];
+        packed |= (uint32_t)(uint8_t)(int8_t)m << (8 * k);
+      }
+      if (first <= 0) {
+        out.pm.push_back((int32_t)packed);
+        out.pc.push_back((float)(first ? 2.0 * c : c));
+      }
+      int k = p - 1;
+      while (k >= 0 && ++idx[k] == L) idx[k--] = 0;
+      if (k < 0) break;
+    }
+    e.K = (int32_t)out.pm.size() - e.off;
+    long double at = 1.0L / (two_pi * std::sqrt((long double)N) * (long double)sigma_r);
+    long double fr = at - std::floor(at);
+    long double sc = fr * 18446744073709551616.0L;
+    e.qfix = sc >= 18446744073709551615.0L ? ~0ull : (uint64_t)sc;
+    e.alpha_turn = (double)at;
+    out.idx_of_T[T] = (int32_t)out.ent.size();
+    seen[N] = (int32_t)out.ent.size();
+    out.ent.push_back(e);
+    if (e.K > out.K_max) out.K_max = e.K;
+    if (N > out.N_max) out.N_max = N;
+  }
+  return true;
+}
+
+// ----------------------------------------------- polynomial range kernel ---
+// Eq. (RPconv) of Section 1.3: phi(s) = (1 - s^2 / (2 N sigma_r^2))^N with the
+// smallest N >= N0 = 0.5 (T/sigma_r)^2 (non-negative and monotone on
+// [-T, T]).  As a polynomial of degree 2N in the neighbour's intensity a,
+// phi(a - b) = sum_j c_j(b) T_j(x(a)) in the Chebyshev basis of
+// x(a) = (a - L/2) / (L/2) on [0, L]: the shiftable form of Section 1.2 with
+// basis functions T_j and coefficients c_j(b), one table row per integer
+// intensity b.  Coefficients from the values at the 2N+1 Chebyshev points
+// (the discrete cosine transform that is exact for degree <= 2N), long
+// double.  Orders above J are dropped, J the smallest order with
+// sum_{j > J} max_b |c_j(b)| <= eps, so that the kernel moves by at most eps
+// anywhere on [0, L]^2 (|T_j| <= 1).
+bool build_rp_table(double sigma_r, double eps, double L, double T, RpTable &out, std::string &err) {
+  out = RpTable();
+  const double n0 = 0.5 * (T / sigma_r) * (T / sigma_r);
+  if (!(n0 <= 2048.0)) { err = "polynomial kernel order above 2048 (sigma_r too small for T)"; return false; }
+  const int N = std::max(1, (int)std::ceil(n0));
+  const int n = 2 * N + 1;  // nodes = coefficients
+  const int nv = (int)L + 1;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  const long double K2 = 2.0L * N * (long double)sigma_r * (long double)sigma_r;
+  const long double h = 0.5L * (long double)L;
+  // cos(j theta_k), theta_k = pi (k + 1/2) / n, by k-major rows
+  std::vector<long double> ct((size_t)n * n);
+  for (int k = 0; k < n; k++)
+    for (int j = 0; j < n; j++) ct[(size_t)k * n + j] = std::cos(pi * (long double)j * (k + 0.5L) / n);
+  std::vector<double> c((size_t)nv * n);
+  std::vector<long double> acc(n);
+  for (int b = 0; b < nv; b++) {
+    std::fill(acc.begin(), acc.end(), 0.0L);
+    for (int k = 0; k < n; k++) {
+      const long double a = h + h * ct[(size_t)k * n + 1];  // x_k = cos theta_k
+      const long double d = a - (long double)b;
+      const long double v = std::pow(1.0L - d * d / K2, (long double)N);
+      const long double *row = &ct[(size_t)k * n];
+      for (int j = 0; j < n; j++) acc[j] += v * row[j];
+    }
+    for (int j = 0; j < n; j++) c[(size_t)b * n + j] = (double)(acc[j] * (j ? 2.0L : 1.0L) / n);
+  }
+  std::vector<double> sup(n, 0.0);
+  for (int b = 0; b < nv; b++)
+    for (int j = 0; j < n; j++) sup[j] = std::max(sup[j], std::fabs(c[(size_t)b * n + j]));
+  int J = n - 1;
+  double tail = 0.0;
+  while (J > 0 && tail + sup[J] <= eps) tail += sup[J--];
+  out.N = N;
+  out.J = J;
+  out.K = (J + 2) / 2;  // slots of two orders: (2k, 2k+1)
+  out.kappa = 0.0;
+  for (int b = 0; b < nv; b++) {
+    double sa = 0.0;
+    for (int j = 0; j <= J; j++) sa += std::fabs(c[(size_t)b * n + j]);
+    out.kappa = std::max(out.kappa, sa);
+  }
+  // per slot and intensity v (256 entries, v > L unused): the basis values
+  // (T_2k, T_2k+1)(x(v)) and the coefficients (c_2k, c_2k+1)(v)
+  out.gen.assign((size_t)out.K * 512, 0.f);
+  out.comb.assign((size_t)out.K * 512, 0.f);
+  for (int k = 0; k < out.K; k++)
+    for (int v = 0; v < 256; v++) {
+      const long double x = std::min(1.0L, std::max(-1.0L, ((long double)std::min(v, nv - 1) - h) / h));
+      const long double th = std::acos(x);
+      for (int u = 0; u < 2; u++) {
+        const int j = 2 * k + u;
+        const size_t o = ((size_t)k * 256 + v) * 2 + u;
+        out.gen[o] = (float)std::cos((long double)j * th);
+        out.comb[o] = (j <= J && v < nv) ? (float)c[(size_t)v * n + j] : 0.f;
+      }
+    }
   return true;
 }
 

@@ -167,7 +167,8 @@ __device__ __forceinline__ void toep_v_body(const ToepVArgs &a, const Blk b) {
   const float inv = 1.f / g.center;
   build_tap_frags<BF, SPLIT>(tfh, tfl, taps, R, nks, tid);  // read after the staging barrier
   if constexpr (PhaseLut<Tin>::kOn) {
-    build_lut(lut, m, q, at, tid, 256);
+    if (tab.lut_gen) lut[tid] = tab.lut_gen[(size_t)(e.off + k) * 256 + tid];  // polynomial kernel
+    else build_lut(lut, m, q, at, tid, 256);
     __syncthreads();
   }
   // staging: one work item = 8 consecutive rows of one column.  The eight
@@ -366,7 +367,10 @@ __device__ __forceinline__ void toep_h_body(const ToepHArgs &a, const Blk b) {
     const float cp = tab.pc[e.off + k];
     const Freq fq = make_freq(m, q, at);
     __syncthreads();  // the previous pair's tile and table are consumed
-    if constexpr (PhaseLut<Tin>::kOn) build_lut(lut, m, q, at, tid, 256);
+    if constexpr (PhaseLut<Tin>::kOn) {
+      if (tab.lut_comb) lut[tid] = tab.lut_comb[(size_t)(e.off + k) * 256 + tid];  // polynomial kernel
+      else build_lut(lut, m, q, at, tid, 256);
+    }
     const ZT *Zk = Zb + (size_t)kl * 4 * zplane;
     constexpr int kRU = 4;  // instructions in flight per lane
     for (int j0 = 0; j0 < ninst; j0 += kRU) {
@@ -634,6 +638,11 @@ static hipError_t allow_lds_dt() {
 }
 hipError_t toeplitz_setup() {
   hipError_t e;
+  // non-local means: single-image kernels of the split variants
+  if ((e = allow_one((const void *)k_toep_v<Patch8x4, false, true>)) != hipSuccess) return e;
+  if ((e = allow_one((const void *)k_toep_h<Patch8x4, false, true>)) != hipSuccess) return e;
+  if ((e = allow_one((const void *)k_toep_v<Patch8x4, true, true>)) != hipSuccess) return e;
+  if ((e = allow_one((const void *)k_toep_h<Patch8x4, true, true>)) != hipSuccess) return e;
   if ((e = allow_lds_dt<uint8_t>()) != hipSuccess) return e;
   if ((e = allow_lds_dt<uint16_t>()) != hipSuccess) return e;
   return allow_lds_dt<float>();
@@ -661,6 +670,14 @@ hipError_t launch_toeplitz_chunk(hipStream_t s, bf_dtype dt, int variant, const 
                                  DevTables tab, DevState st, const ToepCfg &tc, int k0, int kcount, void *Z,
                                  float2 *PQ, bool first, bool last, const StageRec &rec) {
   switch (dt) {
+    case kDtPatch:  // non-local means: the patch image, split variants only
+      if (variant == BF_BLUR_TOEPLITZ_F16X2)
+        return toep_t<Patch8x4, false, true>(s, (const Patch8x4 *)f, out, g, tab, st, tc, k0, kcount, Z, PQ, first,
+                                             last, rec);
+      if (variant == BF_BLUR_TOEPLITZ_BF16X2)
+        return toep_t<Patch8x4, true, true>(s, (const Patch8x4 *)f, out, g, tab, st, tc, k0, kcount, Z, PQ, first,
+                                            last, rec);
+      return hipErrorInvalidValue;
     case BF_U8:
       return toep_dt<uint8_t>(s, variant, (const uint8_t *)f, out, g, tab, st, tc, k0, kcount, Z, PQ, first, last,
                               rec);

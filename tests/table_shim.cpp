@@ -20,6 +20,19 @@ int shim_table_entry(double sigma_r, double eps, double range, int T_cap, int T,
   for (int k = 0; k < e.K && k < cap; k++) { pm[k] = t.pm[e.off + k]; pc[k] = t.pc[e.off + k]; }
   return t.K_max;
 }
+// Polynomial range kernel table: N, J, K, kappa and the per-slot basis values
+// and coefficients ([K][256][2] floats each, at most cap floats copied).
+int shim_rp_table(double sigma_r, double eps, double L, double T, int *N, int *J, int *K, double *kappa,
+                  float *gen, float *comb, int cap) {
+  bfi::RpTable t;
+  std::string err;
+  if (!bfi::build_rp_table(sigma_r, eps, L, T, t, err)) return -1;
+  *N = t.N; *J = t.J; *K = t.K; *kappa = t.kappa;
+  const int n = (int)t.gen.size() < cap ? (int)t.gen.size() : cap;
+  std::memcpy(gen, t.gen.data(), sizeof(float) * n);
+  std::memcpy(comb, t.comb.data(), sizeof(float) * n);
+  return n;
+}
 int shim_iir_consts(double sigma, float *out, int n) {
   std::vector<float> v;
   std::string err;

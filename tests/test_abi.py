@@ -151,3 +151,48 @@ def test_operator_and_variant_must_agree(spatial, blur):
     h = ctypes.c_void_p(123)
     st = bf.lib().bf_plan(ctypes.byref(p), 1, ctypes.byref(h))
     assert st == bf.BF_ERR_UNSUPPORTED and h.value is None
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(dtype="u16", t_mode="global"), bf.BF_ERR_UNSUPPORTED),      # 8-bit input only
+    (dict(dtype="u8", t_mode="local"), bf.BF_ERR_UNSUPPORTED),        # global T only
+    (dict(dtype="u8", t_mode="global", t_value=60.0), bf.BF_ERR_UNSUPPORTED),  # T far below the range
+    (dict(dtype="u8", t_mode="global", sigma_r=2.0), bf.BF_ERR_UNSUPPORTED),   # order above 2048
+    (dict(range_kernel=7), bf.BF_ERR_INVALID_ARG),
+])
+def test_polynomial_kernel_limits_rejected_without_device(kw, status):
+    """The polynomial range kernel's limits are checked on the host before
+    any device work: 8-bit input, a global T, Chebyshev sums that do not
+    cancel in FP32, an order the table builder accepts."""
+    args = dict(H=16, W=16, dtype="u8", sigma_s=2.0, sigma_r=30.0, eps=1e-3, t_mode="global",
+                range_kernel="polynomial")
+    args.update(kw)
+    p = bf.make_params(**args)
+    h = ctypes.c_void_p(123)
+    assert bf.lib().bf_plan(ctypes.byref(p), 1, ctypes.byref(h)) == status
+    assert h.value is None
+    assert bf.bf_last_error_detail()
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(patch=[(0, 0), (0, 1), (1, 0), (1, 1), (2, 2)]), bf.BF_ERR_INVALID_ARG),  # at most 4 samples
+    (dict(patch=[(0, 0), (0, 3)]), bf.BF_ERR_INVALID_ARG),                          # offsets within +-2
+    (dict(patch=[(1, 0), (0, 1)]), bf.BF_ERR_INVALID_ARG),                          # u_1 = 0
+    (dict(patch=[(0, 0), (0, 1)], dtype="u16"), bf.BF_ERR_UNSUPPORTED),             # 8-bit only
+    (dict(patch=[(0, 0), (0, 1)], blur="iir_f32"), bf.BF_ERR_UNSUPPORTED),          # Toeplitz split only
+    (dict(patch=[(0, 0), (0, 1)], blur="toeplitz_f16"), bf.BF_ERR_UNSUPPORTED),
+    (dict(patch=[(0, 0), (0, 1)], range_kernel="polynomial", t_mode="global"), bf.BF_ERR_UNSUPPORTED),
+    (dict(patch=[(0, 0), (0, 1), (1, 0), (1, 1)], sigma_r=8.0), bf.BF_ERR_UNSUPPORTED),  # too many terms
+])
+def test_nlm_limits_rejected_without_device(kw, status):
+    """Non-local means parameters are checked on the host before any device
+    work: patch size and offsets, input type, blur variant, range kernel,
+    and the size of the multi-index table."""
+    args = dict(H=16, W=16, dtype="u8", sigma_s=1.0, sigma_r=40.0, eps=1e-3, radius=3,
+                blur="toeplitz_f16x2", spatial="box")
+    args.update(kw)
+    p = bf.make_params(**args)
+    h = ctypes.c_void_p(123)
+    assert bf.lib().bf_plan(ctypes.byref(p), 1, ctypes.byref(h)) == status
+    assert h.value is None
+    assert bf.bf_last_error_detail()

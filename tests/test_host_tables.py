@@ -32,6 +32,8 @@ def shim():
     L.shim_table_entry.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int, P, P, P, P, P, P, P, ctypes.c_int]
     L.shim_iir_consts.argtypes = [ctypes.c_double, P, ctypes.c_int]
+    L.shim_rp_table.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                P, P, P, P, P, P, ctypes.c_int]
     L.shim_layout.argtypes = [ctypes.c_int, P]
     return L
 
@@ -264,3 +266,35 @@ def test_blocked_model_matches_oracle(shim, c, sigma, n):
     for off in (0, 32, 48):  # where the row group sits in its wave
         got = model_blocked(x, C, off) * C["g1"] ** 2
         assert np.abs(got - ref).max() < 2e-5 * max(1.0, np.abs(ref).max()), off
+
+
+# ------------------------------------------------- polynomial range kernel
+@pytest.mark.parametrize("sr,eps,T", [(30.0, 1e-3, 255.0), (10.0, 1e-3, 255.0), (20.0, 1e-2, 255.0),
+                                      (60.0, 1e-4, 255.0), (25.0, 1e-3, 220.0), (5.0, 1e-3, 255.0)])
+def test_polynomial_table_matches_oracle(shim, sr, eps, T):
+    """The library's Chebyshev table (its own DCT in long double) against the
+    oracle's (numpy interpolation in FP64): same order N and kept order J,
+    basis values T_j(x(v)) and coefficients c_j(v) to FP32 rounding."""
+    from oracle import poly as rp
+    cap = 2 * 256 * 2048
+    N, J, K = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    kap = ctypes.c_double()
+    gen = (ctypes.c_float * cap)()
+    comb = (ctypes.c_float * cap)()
+    n = shim.shim_rp_table(sr, eps, 255.0, T, ctypes.byref(N), ctypes.byref(J), ctypes.byref(K), ctypes.byref(kap),
+                           gen, comb, cap)
+    assert n == K.value * 512
+    tab = rp.rp_table(sr, eps, 255.0, T)
+    assert (N.value, J.value) == (tab["N"], tab["J"])
+    assert K.value == (J.value + 2) // 2
+    g = np.array(gen[:n]).reshape(K.value, 256, 2)
+    c = np.array(comb[:n]).reshape(K.value, 256, 2)
+    x = rp.to_unit(np.arange(256.0), 255.0)
+    for j in range(J.value + 1):
+        Tj = np.cos(j * np.arccos(x))
+        assert np.abs(g[j // 2, :, j % 2] - Tj).max() <= 2e-7
+        ref = tab["C"][:, j]
+        assert np.abs(c[j // 2, :, j % 2] - ref).max() <= 1e-7 * max(1.0, np.abs(ref).max()) + 1e-9
+    if J.value % 2 == 0:  # the unused half of the last slot carries no coefficient
+        assert np.all(c[-1, :, 1] == 0.0)
+    assert abs(kap.value - np.abs(tab["C"]).sum(1).max()) < 1e-6
