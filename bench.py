@@ -15,7 +15,9 @@ the FP64 oracle: the 256x256 rectangles image with global T = 255; the
 512x512 gradient image (recursive blur, split-FP16 Toeplitz blur, and the
 constant spatial filter of Section 4); the 2048x2048 16-bit polygons image;
 the 4096x4096 float mosaic on the recursive blur and on the four Toeplitz
-variants (split FP16, split BF16, FP16, BF16 operands).  `batched` holds the
+variants (split FP16, split BF16, FP16, BF16 operands); and the 256x256
+image with the polynomial range kernel (eq. (RPconv)) and with non-local
+means (three-sample patch, 11x11 window, eqs. (NL1), (NL2)).  `batched` holds the
 batch on the recursive and on the split-FP16 path alone and the 64 images
 filtered one after another by single-image plans.
 
@@ -167,14 +169,15 @@ def sample_pixels(H, W, n, seed):
 
 # ------------------------------------------------------- single-image lines
 def single_line(idx, blur, steps, warmup, spatial="gaussian", sigma_s=None, radius=None, sigma_r=None,
-                eps=None, label=None):
+                eps=None, label=None, range_kernel="raised_cosine", patch=None, t_mode=None, t_value=None):
     """One workload on one blur variant: timed graph replays, stage profile,
     roofline; returns (line, output on the host, report)."""
     import torch
     from bfsynth import CONFIGS, config_image
     from paper_1203_5128_amd import Plan, make_params
     c = dict(CONFIGS[idx])
-    for k, v in (("sigma_s", sigma_s), ("radius", radius), ("sigma_r", sigma_r), ("eps", eps)):
+    for k, v in (("sigma_s", sigma_s), ("radius", radius), ("sigma_r", sigma_r), ("eps", eps), ("t_mode", t_mode),
+                 ("t_value", t_value)):
         if v is not None:
             c[k] = v
     img = config_image(idx)
@@ -182,7 +185,8 @@ def single_line(idx, blur, steps, warmup, spatial="gaussian", sigma_s=None, radi
     x = torch.from_numpy(img).to("cuda:0")
     out = torch.empty((H, W), dtype=torch.float32, device=x.device)
     plan = Plan.create(make_params(H, W, c["dtype"], c["sigma_s"], c["sigma_r"], c["eps"], c["radius"],
-                                   c["t_mode"], t_value=c["t_value"], blur=blur, spatial=spatial))
+                                   c["t_mode"], t_value=c["t_value"], blur=blur, spatial=spatial,
+                                   range_kernel=range_kernel, patch=patch))
     print(f"[bench] {label or c['name']} {blur} {spatial}", file=sys.stderr, flush=True)
     _, rep = plan.filter(x, out, report=True)
     sec = time_steps(lambda: plan.filter(x, out, report=False), steps, warmup)
@@ -190,7 +194,7 @@ def single_line(idx, blur, steps, warmup, spatial="gaussian", sigma_s=None, radi
     plan.close()
     workload = label or c["name"]
     imgs = [(H * W, rep["pairs"], B_IN[c["dtype"]], blur, c["radius"])]
-    line = dict(workload=workload, blur=blur, spatial=spatial, H=H, W=W, input=c["dtype"],
+    line = dict(workload=workload, blur=blur, spatial=spatial, range_kernel=range_kernel, H=H, W=W, input=c["dtype"],
                 sigma_s=c["sigma_s"], radius=c["radius"], sigma_r=c["sigma_r"], eps=c["eps"], t_mode=c["t_mode"],
                 value=round(H * W / sec / 1e6, 3), unit="megapixels/sec", ms_per_step=round(sec * 1e3, 5),
                 steps=steps, T=rep["T"], N=rep["N"], M=rep["M"], pairs=rep["pairs"], stages=stages,
@@ -384,6 +388,28 @@ def config_lines(steps, warmup, which):
         line["err_checked"] = "154 sampled pixels against eq. (BF) evaluated directly with the box"
         sub["box_toeplitz_f16x2"] = line
         res["grad512_u8_local"] = sub
+    if "poly" in which:  # the polynomial range kernel (eq. (RPconv)) on the 256x256 image, global T = 255
+        from oracle import poly
+        sub = {}
+        for blur, op in (("iir_f32", "iir"), ("toeplitz_f16x2", "fir")):
+            line, out, c, img = single_line(1, blur, steps, warmup, range_kernel="polynomial",
+                                            label="rect256_u8_global_poly")
+            ref = poly.rp_shiftable_bf(img, op, c["sigma_s"], c["radius"], c["sigma_r"], c["eps"], 255.0)
+            line.update(err_stats(out, ref["out"], TOL["u8"]))
+            line["err_ok"] = line["err_ok"] and (ref["N"], ref["J"]) == (line["N"], line["M"])
+            sub[blur] = line
+        res["rect256_u8_global_poly"] = sub
+    if "nlm" in which:  # non-local means: patch (0,0),(0,1),(1,0), 11x11 box window, sigma_r 40
+        from oracle import nlm
+        patch = [(0, 0), (0, 1), (1, 0)]
+        line, out, c, img = single_line(1, "toeplitz_f16x2", max(5, steps // 10), 2, spatial="box", sigma_s=5.0,
+                                        radius=5, sigma_r=40.0, eps=1e-3, patch=patch, t_mode="local",
+                                        t_value=0.0, label="rect256_u8_nlm3")
+        ref = nlm.nlm_algorithm(img, patch, "box", 5.0, 5, 40.0, 1e-3, 255.0, True)
+        line.update(err_stats(out, ref["out"], TOL["u8"]))
+        line["err_ok"] = line["err_ok"] and (ref["N"], ref["M"], ref["pairs"]) == (line["N"], line["M"], line["pairs"])
+        line["patch"] = patch
+        res["rect256_u8_nlm3"] = line
     if "cfg3" in which:  # 2048x2048 u16
         line, out, c, img = single_line(3, "iir_f32", big, 2)
         ref = oracle.algorithm2(img.astype(np.float64), "iir", c["sigma_s"], c["radius"], c["sigma_r"], c["eps"],
@@ -418,8 +444,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--lines", default="cfg1,cfg2,cfg3,cfg4,batch",
-                    help="sub-lines besides the headline batch: any of cfg1..cfg4, batch (empty: none)")
+    ap.add_argument("--lines", default="cfg1,cfg2,cfg3,cfg4,poly,nlm,batch",
+                    help="sub-lines besides the headline batch: any of cfg1..cfg4, poly, nlm, batch (empty: none)")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle checks (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB mebibytes (a kernel of known "
