@@ -1066,7 +1066,7 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
       }
     }
     group_blur<SV, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
-    if (col) {  // padding positions past the last column are never read
+    if (inpos) {
       // y0 is a multiple of the tile height: row y0 + i sits at the thread's
       // first row plus an offset that is the same in every lane
       // rows y0 .. y0+kC-1 by tiles of 2^ZL rows: consecutive elements
@@ -1161,35 +1161,12 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   Tin fv[kC];
 #pragma unroll
   for (int i = 0; i < kC; i++) fv[i] = frow[min(x0 + i, g.W - 1)];
-  // This thread's columns x0 .. x0 + kC - 1: nz of them lie inside the
-  // image.  The smoothed images hold nothing past the last column (the
-  // vertical pass writes no padding).  A thread wholly past the end reads
-  // the row's last column kC times (one element the cache holds: no memory
-  // traffic); the row's one partial thread reads its own unwritten tail.
-  // Those samples are then replaced by the zeros of the zero extension, with
-  // integer masks (compares would be hoisted into scalar lane masks).
-  const int nz = min(max(g.W - x0, 0), kC);
-  const size_t zstride = nz > 0 ? (size_t)S * qs : 0;
-  const size_t zfirst = nz > 0 ? z_index(g, y, t) : z_index(g, y, ((g.W - 1) % kC) * S + (g.W - 1) / kC);
   float4 zv[kC];
-  auto load_row = [&](const float4 *__restrict__ zb) {
-    const float4 *q = zb + zfirst;
-#pragma unroll
-    for (int i = 0; i < kC; i++, q += zstride) zv[i] = *q;
-    if (nz < kC) {
-#pragma unroll
-      for (int i = 0; i < kC; i++) {
-        const int keep = (i - nz) >> 31;  // all ones for a column inside the image
-        zv[i] = make_float4(__int_as_float(__float_as_int(zv[i].x) & keep),
-                            __int_as_float(__float_as_int(zv[i].y) & keep),
-                            __int_as_float(__float_as_int(zv[i].z) & keep),
-                            __int_as_float(__float_as_int(zv[i].w) & keep));
-      }
-    }
-  };
   {
     const int kl = kb + grp;
-    load_row(Z + (size_t)(kl < kend ? kl : 0) * g.Hz * g.Spos);
+    const float4 *q = Z + (size_t)(kl < kend ? kl : 0) * g.Hz * g.Spos + z_index(g, y, t);
+#pragma unroll
+    for (int i = 0; i < kC; i++, q += (size_t)S * qs) zv[i] = *q;
   }
   store_iir_lds(L, tr, tid);
   __syncthreads();
@@ -1206,7 +1183,11 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
         for (int i = t; i < 256; i += S) slut[grp * 256 + i] = glut[(size_t)kl * 256 + i];
       __syncthreads();
     }
-    if (it > 0) load_row(Z + (size_t)(act ? kl : 0) * g.Hz * g.Spos);
+    if (it > 0) {
+      const float4 *q = Z + (size_t)(act ? kl : 0) * g.Hz * g.Spos + z_index(g, y, t);
+#pragma unroll
+      for (int i = 0; i < kC; i++, q += (size_t)S * qs) zv[i] = *q;
+    }
     group_blur<S, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
     // eqs. (f1), (f2): weight by the phase at the output pixel
     if (act) {
