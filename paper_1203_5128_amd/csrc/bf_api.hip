@@ -298,16 +298,24 @@ void set_chunk(ImagePlan &ip, int KC) {
     const int groups = std::max(1, std::min(KC, (target + gx - 1) / gx));
     g.vppw = (KC + groups - 1) / groups;
   }
+  g.hrows = 1;
   if (!is_toeplitz(ip.variant)) {
-    // horizontal pass: split the pairs of a launch over enough rows of
-    // workgroups to fill the GPU, each group a whole number of the NG pairs a
-    // workgroup handles at once
+    // horizontal pass: a workgroup's NG = 256/S row groups take pw pairs at a
+    // time on each of NG/pw rows; pw is the largest power of two whose last
+    // round leaves at most 1/8 of the slots idle at the full-range pair count
+    // (few pairs: several rows per workgroup instead of idle groups)
     const int ng = kHThreads / g.S;
-    const int slots = (KC + ng - 1) / ng;
+    int pw = ng;
+    while (pw > 1 && 8 * KC < 7 * ((KC + pw - 1) / pw * pw)) pw >>= 1;
+    g.hrows = ng / pw;
+    // then split the pairs of a launch over enough rows of workgroups to
+    // fill the GPU (as many groups as with one row per workgroup), each
+    // group a whole number of the pw pairs in flight
+    const int slots = (KC + pw - 1) / pw;
     int target = kHWorkgroups;
     if (const char *w = std::getenv("BF_H_WG")) target = std::max(1, std::atoi(w));
-    const int groups = std::max(1, std::min(slots, (target + g.H - 1) / g.H));
-    g.hkpg = (slots + groups - 1) / groups * ng;
+    const int groups = std::max(1, std::min((KC + ng - 1) / ng, (target + g.H - 1) / g.H));
+    g.hkpg = (slots + groups - 1) / groups * pw;
     g.hgroups = (KC + g.hkpg - 1) / g.hkpg;
   } else {
     // split the pairs of a launch over enough horizontal workgroups to fill the GPU

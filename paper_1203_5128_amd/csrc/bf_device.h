@@ -71,8 +71,10 @@ struct Geom {
   // the vertical writes.)
   int Hz, zlog;
   // horizontal pass: the pairs of a launch are split into hgroups groups of
-  // hkpg pairs, each a row of workgroups with its own partial sums
-  int hgroups, hkpg;
+  // hkpg pairs, each a row of workgroups with its own partial sums; a
+  // workgroup takes hrows image rows (a power of two <= 256/S), each with
+  // 256/(S hrows) pairs in flight
+  int hgroups, hkpg, hrows;
   float center;       // intensity subtracted from f in the f*cos, f*sin images
   // Toeplitz path: smoothed images stored with a left pad of padl elements
   // (padl = R mod 8) and a row pitch of zpitch elements (multiple of 8)

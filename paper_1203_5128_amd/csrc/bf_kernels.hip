@@ -1115,11 +1115,13 @@ __global__ __launch_bounds__(kHThreads, 2) void k_iir_v_grp(const IirArgs *__res
 }
 
 // ------------------------------------ horizontal pass + accumulate (a4, a5)
-// One workgroup per (image row, pair group); S threads per row group, NG =
-// 256/S groups each taking every NG-th frequency of the pair group.  Each
-// group smooths its pair's four images along the row and combines them at
-// once into the numerator and the denominator (eqs. (f1), (f2)) with the
-// phases regenerated at each pixel.
+// One workgroup per (hrows image rows, pair group); S threads per row group,
+// NG = 256/S groups: hrows rows of PW = NG/hrows groups each, the PW groups
+// of a row taking every PW-th frequency of the pair group (hrows > 1 when a
+// pair group holds too few pairs to keep NG groups busy).  Each group
+// smooths its pair's four images along its row and combines them at once
+// into the numerator and the denominator (eqs. (f1), (f2)) with the phases
+// regenerated at each pixel.
 template <typename Tin, int S, int kC>
 __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, float *__restrict__ out, const Geom &g, const DevTables &tab, const DevState &st, const float *__restrict__ iir, int k0, int kcount, const float4 *__restrict__ Z, float2 *__restrict__ PQ, int first, int last, const float2 *__restrict__ glut, const Blk b) {
 
@@ -1130,24 +1132,31 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   // LDS when that still leaves room for two workgroups per CU
   constexpr bool kLutLds = PhaseLut<Tin>::kOn && NG <= 8 && NG * PAD * 8 + NG * 2048 <= 80 * 1024;
   // (P, Q) per group and pixel; slot (grp, t, i) belongs to one thread until the
-  // groups are summed at the end
+  // groups of a row are summed at the end
   __shared__ float2 spq[NG * PAD];
   __shared__ float4 xw[NG][NW][3];
   __shared__ float2 slut[kLutLds ? NG * 256 : 1];
   __shared__ IirLds L;
-  // rows in XCD order: the workgroups of consecutive rows (which share the
-  // cache lines of tiled smoothed images) run on one XCD
-  const int per = (g.H + 7) / 8;
-  const int y = (b.x & 7) * per + (b.x >> 3);
-  if (y >= g.H) return;  // the whole workgroup: past the last row
+  const int hrows = g.hrows;      // rows per workgroup (a power of two <= NG)
+  const int PW = NG / hrows;      // pairs in flight per row
+  // row blocks in XCD order: the workgroups of consecutive rows (which share
+  // the cache lines of tiled smoothed images) run on one XCD
+  const int nrb = (g.H + hrows - 1) / hrows;
+  const int per = (nrb + 7) / 8;
+  const int rb = (b.x & 7) * per + (b.x >> 3);
+  if (rb >= nrb) return;  // the whole workgroup: past the last row
   const int pg = b.y;  // pair group: launch-local pairs [kb, kb + hkpg)
   const int tid = threadIdx.x;
   const int t = tid % S;
   const int grp = tid / S;
+  const int rsub = grp / PW, plane = grp % PW;
+  // rows past the image (last block only) smooth a copy of the last row and
+  // store nothing; they still take part in the group's barriers
+  const int y = min(rb * hrows + rsub, g.H - 1);
   const UEntry e = uniform_entry(tab, st.T_used);
   const int kb = pg * g.hkpg;
   const int kend = min(min(kb + g.hkpg, kcount), e.K - k0);
-  const int niter = kend > kb ? (kend - kb + NG - 1) / NG : 0;
+  const int niter = kend > kb ? (kend - kb + PW - 1) / PW : 0;
   const bool finish = last && g.hgroups == 1;
   if (niter == 0 && !first && !finish) return;  // no pairs here: partial sums unchanged
   const float a1 = iir[kIirCoef + 0], g2 = iir[kIirCoef + 1], c2 = iir[kIirCoef + 2];
@@ -1163,7 +1172,7 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   for (int i = 0; i < kC; i++) fv[i] = frow[min(x0 + i, g.W - 1)];
   float4 zv[kC];
   {
-    const int kl = kb + grp;
+    const int kl = kb + plane;
     const float4 *q = Z + (size_t)(kl < kend ? kl : 0) * g.Hz * g.Spos + z_index(g, y, t);
 #pragma unroll
     for (int i = 0; i < kC; i++, q += (size_t)S * qs) zv[i] = *q;
@@ -1175,12 +1184,12 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   for (int i = 0; i < kC; i++) mypq[i] = make_float2(0.f, 0.f);
 
   for (int it = 0; it < niter; it++) {
-    const int kl = kb + it * NG + grp;
+    const int kl = kb + it * PW + plane;
     const bool act = kl < kend;
     if constexpr (kLutLds) {
       __syncthreads();  // the previous pairs' tables are no longer read
-      if (act)
-        for (int i = t; i < 256; i += S) slut[grp * 256 + i] = glut[(size_t)kl * 256 + i];
+      if (act && rsub == 0)  // one copy per pair in flight, shared by the rows
+        for (int i = t; i < 256; i += S) slut[plane * 256 + i] = glut[(size_t)kl * 256 + i];
       __syncthreads();
     }
     if (it > 0) {
@@ -1206,7 +1215,7 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
         if (i < nx) {
           float c, sn;
           if constexpr (PhaseLut<Tin>::kOn) {
-            const float2 cs = kLutLds ? slut[grp * 256 + (int)fv[i]] : lk[(int)fv[i]];
+            const float2 cs = kLutLds ? slut[plane * 256 + (int)fv[i]] : lk[(int)fv[i]];
             c = cs.x;
             sn = cs.y;
           } else {
@@ -1220,35 +1229,37 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
       }
     }
   }
-  // sum the groups in a fixed order
+  // sum the groups of each row in a fixed order
   __syncthreads();
   float2 *PQg = PQ + (size_t)pg * g.H * g.W;
   unsigned long long nbad = 0;
-  for (int x = tid; x < g.W; x += kHThreads) {
+  const int nrow = min(hrows, g.H - rb * hrows);
+  for (int idx = tid; idx < nrow * g.W; idx += kHThreads) {
+    const int r = idx / g.W, x = idx - r * g.W;
+    const int yr = rb * hrows + r;
     const int o = (x / kC) * (kC + 1) + (x % kC);
     float P = 0.f, Q = 0.f;
-#pragma unroll
-    for (int gg = 0; gg < NG; gg++) {
-      const float2 pq = spq[gg * PAD + o];
+    for (int pl = 0; pl < PW; pl++) {
+      const float2 pq = spq[(r * PW + pl) * PAD + o];
       P += pq.x;
       Q += pq.y;
     }
-    const size_t pix = (size_t)y * g.W + x;
+    const size_t pix = (size_t)yr * g.W + x;
     if (!first) {
       float2 pq = PQg[pix];
       P += pq.x;
       Q += pq.y;
     }
     if (finish) {
-      float r = P / Q;
+      float rr = P / Q;
       float v;
-      if (Q > 0.f && isfinite(r)) {
-        v = g.center + r;
+      if (Q > 0.f && isfinite(rr)) {
+        v = g.center + rr;
       } else {
-        v = fval(frow[x]);
+        v = fval(f[(int64_t)yr * g.pitch + x]);
         nbad++;
       }
-      out[(int64_t)y * g.opitch + x] = v;
+      out[(int64_t)yr * g.opitch + x] = v;
     } else {
       PQg[pix] = make_float2(P, Q);
     }
@@ -1509,7 +1520,8 @@ void iir_args(const void *f, float *out, const Geom &g, DevTables tab, DevState 
   const int ng = kHThreads / g.vS;  // columns per vertical workgroup
   const int per = ((g.Spos + ng - 1) / ng + 7) / 8;
   a[0].gg = GroupGrid{8 * per, (kcount + g.vppw - 1) / g.vppw, 1};  // vertical (column blocks in XCD order)
-  a[1].gg = GroupGrid{8 * ((g.H + 7) / 8), g.hgroups, 1};  // horizontal + combine (rows in XCD order)
+  const int nrb = (g.H + g.hrows - 1) / g.hrows;
+  a[1].gg = GroupGrid{8 * ((nrb + 7) / 8), g.hgroups, 1};  // horizontal + combine (row blocks in XCD order)
   const int64_t npx = (int64_t)g.H * g.W;
   const int nfin = (last && g.hgroups > 1) ? (int)((npx + 255) / 256) : 0;
   fa = FinishArgs{GroupGrid{nfin > 0 ? nfin : 1, 1, 1}, f, out, g, st, (const float2 *)PQ, g.hgroups, 1.0f};
@@ -1598,6 +1610,7 @@ static bool launch_v_any(hipStream_t s, int S, int cV, const IirArgs *one, const
 
 static bool iir_geom_ok(const Geom &g, int kcount) {
   return g.hgroups >= 1 && g.hgroups <= 65535 && g.vppw >= 1 && g.hkpg >= 1 && (int64_t)g.hgroups * g.hkpg >= kcount &&
+         g.hrows >= 1 && (kHThreads / g.S) % g.hrows == 0 && g.hkpg % (kHThreads / g.S / g.hrows) == 0 &&
          kcount >= 1 && kcount <= 65535 && g.vS >= 1 && g.vS <= kHThreads && (int64_t)g.vS * g.vC >= g.H &&
          (int64_t)g.S * g.cC >= g.W && g.Spos == g.S * g.cC && g.zlog >= 0 && g.zlog <= 3 && g.Hz >= g.H && g.Hz % (1 << g.zlog) == 0 &&
          ((kHThreads / g.vS) << g.zlog) >= z_tile_words(g.vS) && (g.zlog == 0 || ((kHThreads / g.vS) << g.zlog) == z_tile_words(g.vS));
