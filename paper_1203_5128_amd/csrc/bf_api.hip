@@ -46,6 +46,7 @@ struct ImagePlan {
   Geom g{};
   OrderTable tab;
   int KC = 0;              // frequency pairs per launch of the blur passes
+  int hpw = 0;             // term-group width knob of the recursive horizontal pass
   int variant = BF_BLUR_IIR_F32;
   // device memory
   int32_t *d_idx = nullptr;
@@ -279,6 +280,9 @@ struct Knobs {
   int variant = 0;  // bf_blur other than AUTO
   int hchunk = 0;   // pixels per thread of the recursive horizontal pass (16 or 32)
   int lds_kb = 0;   // preferred LDS of a Toeplitz vertical tile
+  int hpw = 0;      // term-group width of the recursive horizontal pass (pairs in
+                    // flight per row): 0 the single-image rule, -1 the rule for a
+                    // shared grouped launch, > 0 that width
 };
 
 // Launch shape of the blur passes for KC pairs per launch: the vertical
@@ -301,20 +305,38 @@ void set_chunk(ImagePlan &ip, int KC) {
   g.hrows = 1;
   if (!is_toeplitz(ip.variant)) {
     // horizontal pass: a workgroup's NG = 256/S row groups take pw pairs at a
-    // time on each of NG/pw rows; pw is the largest power of two whose last
-    // round leaves at most 1/8 of the slots idle at the full-range pair count
-    // (few pairs: several rows per workgroup instead of idle groups)
+    // time on each of NG/pw rows (few pairs: several rows per workgroup
+    // instead of idle groups).  The pairs of a launch are split over enough
+    // groups of workgroups to fill the GPU (as many as with one row per
+    // workgroup), each group a whole number of the pw pairs in flight.
     const int ng = kHThreads / g.S;
-    int pw = ng;
-    while (pw > 1 && 8 * KC < 7 * ((KC + pw - 1) / pw * pw)) pw >>= 1;
-    g.hrows = ng / pw;
-    // then split the pairs of a launch over enough rows of workgroups to
-    // fill the GPU (as many groups as with one row per workgroup), each
-    // group a whole number of the pw pairs in flight
-    const int slots = (KC + pw - 1) / pw;
     int target = kHWorkgroups;
     if (const char *w = std::getenv("BF_H_WG")) target = std::max(1, std::atoi(w));
     const int groups = std::max(1, std::min((KC + ng - 1) / ng, (target + g.H - 1) / g.H));
+    int pw = ng;
+    if (ip.hpw > 0) {
+      while (pw > ip.hpw) pw >>= 1;
+    } else if (ip.hpw < 0) {
+      // in a launch shared with other images, which fill the GPU: the
+      // largest width whose last round leaves at most 1/8 of the slots idle
+      while (pw > 1 && 8 * KC < 7 * ((KC + pw - 1) / pw * pw)) pw >>= 1;
+    } else {
+      // alone: the smallest rounds x waves of workgroups (resident: the
+      // workgroups all CUs hold at once), so that fewer idle slots do not cost occupancy
+      const int resident = 256 * (g.cC == kCSmall ? (ip.p.dtype == BF_F32 ? 2 : 3) : 1);
+      long best = -1;
+      for (int w = ng; w >= 1; w >>= 1) {
+        const long nrb = (g.H + ng / w - 1) / (ng / w);
+        const long rounds = (((KC + w - 1) / w) + groups - 1) / groups;
+        const long t = rounds * ((nrb * groups + resident - 1) / resident);
+        if (best < 0 || t < best) {
+          best = t;
+          pw = w;
+        }
+      }
+    }
+    g.hrows = ng / pw;
+    const int slots = (KC + pw - 1) / pw;
     g.hkpg = (slots + groups - 1) / groups * pw;
     g.hgroups = (KC + g.hkpg - 1) / g.hkpg;
   } else {
@@ -370,6 +392,7 @@ void noalloc_shape(ImagePlan &ip) {
 
 bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   ip.p = p;
+  ip.hpw = kn.hpw;
   const double full = p.dtype == BF_U16 ? 65535.0 : 255.0;
   ip.range = p.value_range > 0.0 ? p.value_range : full;
   if (p.dtype == BF_U8 && ip.range > 255.0) return fail(BF_ERR_INVALID_ARG, "value_range above 255 for u8");
@@ -452,8 +475,18 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   g.logS = logS;
   g.cC = cC;
   g.Spos = S * cC;
-  // vertical pass: one row group per column, kCLarge rows per thread
-  g.vC = kCLarge;
+  // vertical pass: one row group per column, kCLarge rows per thread; float
+  // input (whose phases are computed per sample, not read from a table)
+  // kCSmall up to 4096 rows: half the registers, three waves per SIMD
+  // instead of two to hide the sine/cosine and scan latencies (4096² float:
+  // 2.05 -> 1.40 ms; for 8- and 16-bit input the extra scan level costs more
+  // than the waves gain: 512² 53 -> 58 µs, 2048² 3.79 -> 4.63 ms).
+  // BF_VCHUNK=16/32 overrides.
+  g.vC = (p.dtype == BF_F32 && g.H <= kCSmall * kHThreads) ? kCSmall : kCLarge;
+  if (const char *c = std::getenv("BF_VCHUNK")) {
+    if (std::atoi(c) == kCSmall && g.H <= kCSmall * kHThreads) g.vC = kCSmall;
+    if (std::atoi(c) == kCLarge) g.vC = kCLarge;
+  }
   g.vS = 1;
   while (g.vS * g.vC < g.H) g.vS <<= 1;
   // a vertical workgroup covers 256 / vS columns; the smoothed images are
@@ -1520,6 +1553,12 @@ double time_batch(const bf_params *params, int n, const std::vector<Knobs> &kn, 
 }
 
 void autotune_batch(const bf_params *params, int n, std::vector<Knobs> &kn) {
+  // The tuned recursive images take the term-group width for a launch they
+  // share with the other images (which fill the GPU between them): fewer
+  // idle pair slots rather than more workgroups.  (The proxy input keeps
+  // every pair, so timing it could not tell the widths apart on real T.)
+  for (int i = 0; i < n; i++)
+    if (params[i].blur == BF_BLUR_AUTO && kn[i].variant == BF_BLUR_IIR_F32) kn[i].hpw = -1;
   // candidates: the per-image choice, and every tuned image on the default
   // implementation of its own operator (one set of grouped launches each)
   std::vector<std::vector<Knobs>> cand(1, kn);
@@ -1529,7 +1568,7 @@ void autotune_batch(const bf_params *params, int n, std::vector<Knobs> &kn) {
     for (int i = 0; i < n; i++) {
       if (params[i].blur != BF_BLUR_AUTO) continue;
       const Knobs d = fir_operator(params[i]) ? Knobs{BF_BLUR_TOEPLITZ_F16X2, 0, kToepLdsMax / 2048 - 2}
-                                              : Knobs{BF_BLUR_IIR_F32, kCSmall, 0};
+                                              : Knobs{BF_BLUR_IIR_F32, kCSmall, 0, -1};
       if (d.variant != kn[i].variant || d.hchunk != kn[i].hchunk || d.lds_kb != kn[i].lds_kb) differs = true;
       alt[i] = d;
     }
@@ -1559,8 +1598,7 @@ void autotune_batch(const bf_params *params, int n, std::vector<Knobs> &kn) {
     for (size_t c = 0; c < cand.size(); c++) {
       const double t = time_batch(params, n, cand[c], ins, outs, s, a, b);
       if (std::getenv("BF_TUNE_LOG"))
-        std::fprintf(stderr, "[bf tune] batch of %d, assignment %zu (%s): %.3f ms\n", n, c,
-                     c == 0 ? "per-image choice" : "default implementation per operator", t);
+        std::fprintf(stderr, "[bf tune] batch of %d, assignment %zu: %.3f ms\n", n, c, t);
       if (t > 0.0 && (best < 0.0 || t < best)) {
         best = t;
         pick = c;

@@ -64,8 +64,10 @@ struct Geom {
   // = z_tile_words(vS), zth at least 1 (row-major): 16 elements (256 bytes)
   // for workgroups of 4 and 8 columns, so that each writes 256 contiguous
   // bytes per tile while the horizontal workgroups of neighbouring rows
-  // share each line; 8 (one line) for the 1- and 2-column workgroups of
-  // images taller than 2048, whose horizontal workgroups hold one row.
+  // share each line; 8 (one line) for the 2-column workgroups of images
+  // taller than 2048 (32 rows per thread) and 4 for the 1-column workgroups
+  // (taller than 4096, or 16 rows per thread above 2048), whose
+  // horizontal workgroups hold one row each.
   // (Taller tiles make the vertical writes longer but leave each horizontal
   // workgroup a smaller share of the lines it reads; shorter ones scatter
   // the vertical writes.)
@@ -132,7 +134,7 @@ __device__ __forceinline__ Blk group_blk(const GroupGrid &gg, int local) {
 }
 
 // Offset of element (y, p) of one pair's smoothed images (recursive path).
-__host__ __device__ constexpr int z_tile_words(int vS) { return vS >= 128 ? 8 : 16; }
+__host__ __device__ constexpr int z_tile_words(int vS) { return vS >= 256 ? 4 : (vS >= 128 ? 8 : 16); }
 __host__ __device__ inline size_t z_index(const Geom &g, int y, int p) {
   return (((size_t)(y >> g.zlog) * g.Spos + p) << g.zlog) + (y & ((1 << g.zlog) - 1));
 }

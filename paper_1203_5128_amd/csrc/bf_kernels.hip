@@ -965,7 +965,7 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
   constexpr bool kLut = PhaseLut<Tin>::kOn;
   // tile height of the smoothed images (2^ZL rows, the host's zlog for this
   // column group size)
-  constexpr int ZL = NG >= 16 ? 0 : (NG == 8 ? 1 : (NG == 1 ? 3 : 2));
+  constexpr int ZL = NG >= 16 ? 0 : (NG == 8 ? 1 : 2);
   __shared__ float4 xw[NG][NW][3];
   __shared__ IirLds L;
   // 8-bit inputs: cos/sin per intensity and a zero entry for the samples
@@ -1102,12 +1102,19 @@ __device__ __forceinline__ void iir_v_body(const IirArgs &a, const Blk b) {
   const DevState st = a.st;
   iir_v_impl<Tin, SV, kC>((const Tin *)a.f, g, tab, st, a.iir, a.k0, a.kcount, a.Z, a.glut, b);
 }
+// Workgroups per CU the vertical kernel is compiled for: 32 rows per thread
+// hold 128 VGPRs of samples (two waves per SIMD), 16 rows half that (three
+// waves fit 168 VGPRs without spills).
+template <int kC>
+constexpr int v_blocks_per_cu() {
+  return kC == kCSmall ? 3 : 2;
+}
 template <typename Tin, int SV, int kC>
-__global__ __launch_bounds__(kHThreads, 2) void k_iir_v(IirArgs a) {
+__global__ __launch_bounds__(kHThreads, v_blocks_per_cu<kC>()) void k_iir_v(IirArgs a) {
   iir_v_body<Tin, SV, kC>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
 }
 template <typename Tin, int SV, int kC>
-__global__ __launch_bounds__(kHThreads, 2) void k_iir_v_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
+__global__ __launch_bounds__(kHThreads, v_blocks_per_cu<kC>()) void k_iir_v_grp(const IirArgs *__restrict__ a, const int *__restrict__ start,
                                                      int n) {
   const int i = group_find(start, n, blockIdx.x);
   const IirArgs ai = a[i];
@@ -1588,24 +1595,29 @@ static bool launch_h_any(hipStream_t s, int S, int cC, const IirArgs *one, const
   return cC == kCSmall ? launch_h_S<Tin, kCSmall>(s, S, one, arr, start, n, total)
                        : launch_h_S<Tin, kCLarge>(s, S, one, arr, start, n, total);
 }
-// The vertical pass always runs kCLarge rows per thread (half the scan work
-// per pixel of the short chunk).
+// The vertical pass runs kCLarge or kCSmall rows per thread.
+template <typename Tin, int C>
+static bool launch_v_S(hipStream_t s, int S, const IirArgs *one, const IirArgs *arr, const int *start, int n,
+                       int total) {
+  switch (S) {
+    case 1: launch_v<Tin, 1, C>(s, one, arr, start, n, total); return true;
+    case 2: launch_v<Tin, 2, C>(s, one, arr, start, n, total); return true;
+    case 4: launch_v<Tin, 4, C>(s, one, arr, start, n, total); return true;
+    case 8: launch_v<Tin, 8, C>(s, one, arr, start, n, total); return true;
+    case 16: launch_v<Tin, 16, C>(s, one, arr, start, n, total); return true;
+    case 32: launch_v<Tin, 32, C>(s, one, arr, start, n, total); return true;
+    case 64: launch_v<Tin, 64, C>(s, one, arr, start, n, total); return true;
+    case 128: launch_v<Tin, 128, C>(s, one, arr, start, n, total); return true;
+    case 256: launch_v<Tin, 256, C>(s, one, arr, start, n, total); return true;
+    default: return false;
+  }
+}
 template <typename Tin>
 static bool launch_v_any(hipStream_t s, int S, int cV, const IirArgs *one, const IirArgs *arr, const int *start,
                          int n, int total) {
-  if (cV != kCLarge) return false;
-  switch (S) {
-    case 1: launch_v<Tin, 1, kCLarge>(s, one, arr, start, n, total); return true;
-    case 2: launch_v<Tin, 2, kCLarge>(s, one, arr, start, n, total); return true;
-    case 4: launch_v<Tin, 4, kCLarge>(s, one, arr, start, n, total); return true;
-    case 8: launch_v<Tin, 8, kCLarge>(s, one, arr, start, n, total); return true;
-    case 16: launch_v<Tin, 16, kCLarge>(s, one, arr, start, n, total); return true;
-    case 32: launch_v<Tin, 32, kCLarge>(s, one, arr, start, n, total); return true;
-    case 64: launch_v<Tin, 64, kCLarge>(s, one, arr, start, n, total); return true;
-    case 128: launch_v<Tin, 128, kCLarge>(s, one, arr, start, n, total); return true;
-    case 256: launch_v<Tin, 256, kCLarge>(s, one, arr, start, n, total); return true;
-    default: return false;
-  }
+  if (cV == kCLarge) return launch_v_S<Tin, kCLarge>(s, S, one, arr, start, n, total);
+  if (cV == kCSmall) return launch_v_S<Tin, kCSmall>(s, S, one, arr, start, n, total);
+  return false;
 }
 
 static bool iir_geom_ok(const Geom &g, int kcount) {

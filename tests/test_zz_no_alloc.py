@@ -102,3 +102,33 @@ def test_noalloc_rejects_images_beyond_the_array():
     assert bool((out == 7.0).all())
     assert bf.lib().bf_filter_noalloc(None, img.data_ptr(), out.data_ptr(), None, None) == bf.BF_ERR_INVALID_ARG
     p.close()
+
+
+def test_noalloc_polynomial_kernel_and_nlm():
+    """The polynomial-kernel tables and the non-local-means patch words go
+    through the same static working memory.  The polynomial plans fit one
+    launch (equal to bf_filter bit for bit); the non-local-means plan's up to
+    1372 multi-index pairs need about 460 MB of smoothed images, so the
+    static array runs them in two launches and only the order of the pair
+    sums differs (within the 2e-3 bar)."""
+    torch = _cuda()
+    from paper_1203_5128_amd import Plan, make_params
+    img = gen_random(91, 120, 170, "u8", "mixed")
+    cases = [
+        ("poly iir", make_params(120, 170, "u8", sigma_s=3.0, sigma_r=25.0, eps=1e-3, radius=9, t_mode="global",
+                                 blur="iir_f32", range_kernel="polynomial")),
+        ("poly toeplitz", make_params(120, 170, "u8", sigma_s=3.0, sigma_r=25.0, eps=1e-3, radius=9,
+                                      t_mode="global", blur="toeplitz_f16x2", range_kernel="polynomial")),
+        ("nlm", make_params(120, 170, "u8", sigma_s=1.0, sigma_r=45.0, eps=1e-3, radius=3, t_mode="local",
+                            blur="toeplitz_f16x2", spatial="box", patch=[(0, 0), (0, 1), (1, 0)])),
+    ]
+    for name, p in cases:
+        plan = Plan.create(p)
+        print(f"[noalloc] {name}", flush=True)
+        ref, rep_ref, got, rep = _both(plan, img, torch)
+        plan.close()
+        _same_report(rep_ref, rep)
+        if name == "nlm":
+            assert np.abs(got.astype(np.float64) - ref).max() <= 2e-3
+        else:
+            assert np.array_equal(got, ref), name
