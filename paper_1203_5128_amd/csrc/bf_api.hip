@@ -169,11 +169,12 @@ DevState state_at(void *d_state) {
   return st;
 }
 // d_state: the published state (24 bytes), then the range accumulators
-// (top slot at 32, kRangeSubs slots from 48).
-constexpr size_t kStateBytes = 48 + kRangeSubs * sizeof(RangeAccSlot);
+// (top slot at 32, kRangeSubs slots from 48, then kRangeSubs lower bounds).
+constexpr size_t kAccLbOff = 48 + kRangeSubs * sizeof(RangeAccSlot);
+constexpr size_t kStateBytes = kAccLbOff + kRangeSubs * sizeof(unsigned long long);
 RangeAcc acc_at(void *d_state) {
   char *b = (char *)d_state;
-  return RangeAcc{(RangeAccSlot *)(b + 32), (RangeAccSlot *)(b + 48)};
+  return RangeAcc{(RangeAccSlot *)(b + 32), (RangeAccSlot *)(b + 48), (unsigned long long *)(b + kAccLbOff)};
 }
 DevState state_of(const ImagePlan &ip) { return state_at(ip.d_state); }
 RangeAcc acc_of(const ImagePlan &ip) { return acc_at(ip.d_state); }
@@ -350,6 +351,18 @@ void set_chunk(ImagePlan &ip, int KC) {
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// Device bytes of an image's range-stage workspace: the tile statistics of
+// the one-launch kernel (one int2 per 32 x 32 tile), or the row maxima of the
+// two passes (R > 48); none with a global T.
+size_t range_ws_bytes(const ImagePlan &ip) {
+  if (ip.p.t_mode != BF_T_LOCAL) return 0;
+  if (range_tile_ok(ip.R, ip.p.dtype)) {
+    const GroupGrid gt = range_tile_grid(ip.g);
+    return (size_t)gt.gx * gt.gy * sizeof(int2);
+  }
+  return (size_t)ip.g.H * ip.g.W * elem_size(ip.p.dtype);
+}
+
 // Shape of bf_filter_noalloc for an image: the most pairs per launch whose
 // working memory (device state, row maxima of the two-pass range stage,
 // 8-bit cos/sin tables, partial sums, smoothed images) fits kScratchBytes.
@@ -361,8 +374,7 @@ void noalloc_shape(ImagePlan &ip) {
   const size_t px = (size_t)g0.H * g0.W;
   const bool toep = is_toeplitz(ip.variant);
   const size_t state = align256(kStateBytes);
-  const size_t rowmax =
-      (ip.p.t_mode == BF_T_LOCAL && !range_tile_ok(ip.R, ip.p.dtype)) ? align256(px * elem_size(ip.p.dtype)) : 0;
+  const size_t rowmax = align256(range_ws_bytes(ip));
   const size_t patch = ip.nlm ? align256(px * sizeof(Patch8x4)) : 0;
   ImagePlan::NoAlloc na;
   auto fits = [&](int kc) {
@@ -729,7 +741,7 @@ std::vector<int> starts_of(const std::vector<int> &blocks) {
 // packed buffer, block totals and LDS sizes.
 struct GLaunch {
   int kind;  // 0 reset, 1 range, 2 Toeplitz stages, 3 recursive vertical, 4 recursive horizontal,
-            // 5 one-launch range
+            // 5 one-launch range, 6 its tile statistics
   bf_dtype dt;
   int variant;
   int S, cC;
@@ -771,33 +783,64 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
       bp.launches.push_back(L);
     }
   }
-  for (bf_dtype dt : {BF_U8, BF_U16, BF_F32})
-    for (int kr : {32, 48}) {
-      std::vector<RangeTileArgs> ta;
-      std::vector<int> tb;
-      size_t lds = 0;
+  for (bf_dtype dt : {BF_U8, BF_U16, BF_F32}) {
+    // the tile statistics of every tile-kernel image of this dtype (one
+    // workgroup per strip of tiles), then one tile launch per staged-block size
+    auto tile_args = [&](int kr, std::vector<RangeTileArgs> &ta, size_t *lds) {
       for (int i : gidx) {
         const ImagePlan &ip = pl->im[i];
-        if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || !range_tile_ok(ip.R, dt) || range_tile_kr(ip.R) != kr)
+        if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || !range_tile_ok(ip.R, dt) ||
+            (kr && range_tile_kr(ip.R) != kr))
           continue;
-        const GroupGrid gt = range_tile_grid(ip.g);
-        ta.push_back(RangeTileArgs{gt, d_in[i], ip.g.pitch, ip.g.H, ip.g.W, ip.R, state_of(ip), acc_of(ip), ip.T_cap});
-        tb.push_back(gt.gx * gt.gy);
-        lds = std::max(lds, range_tile_lds(ip.R, dt));
+        ta.push_back(RangeTileArgs{range_tile_grid(ip.g), d_in[i], ip.g.pitch, ip.g.H, ip.g.W, ip.R, state_of(ip),
+                                   acc_of(ip), ip.T_cap, (int2 *)((char *)pl->d_bws + pl->rowmax_off[i]), 0});
+        if (lds) *lds = std::max(*lds, range_tile_lds(ip.R, dt));
       }
+    };
+    std::vector<RangeTileArgs> sa;
+    tile_args(0, sa, nullptr);
+    if (sa.empty()) continue;
+    {
+      std::vector<int> sb;
+      for (const RangeTileArgs &t : sa) {
+        const GroupGrid gs = range_stats_grid(t.gg);
+        sb.push_back(gs.gx * gs.gy);
+      }
+      const std::vector<int> ss = starts_of(sb);
+      GLaunch L{};
+      L.kind = 6;
+      L.dt = dt;
+      L.cnt = (int)sa.size();
+      L.o[0] = bp.pack.add(sa);
+      L.o[1] = bp.pack.add(ss);
+      L.t[0] = ss.back();
+      bp.launches.push_back(L);
+    }
+    for (int kr : {32, 48}) {
+      std::vector<RangeTileArgs> ta;
+      size_t lds = 0;
+      tile_args(kr, ta, &lds);
       if (ta.empty()) continue;
-      const std::vector<int> ts = starts_of(tb);
+      long long total = 0;
+      for (const RangeTileArgs &t : ta) total += t.gg.gx * t.gg.gy;
+      std::vector<int> wb;
+      for (RangeTileArgs &t : ta) {
+        t.nwg = range_tile_wgs(t.gg.gx * t.gg.gy, total);
+        wb.push_back(t.nwg);
+      }
+      const std::vector<int> ws = starts_of(wb);
       GLaunch L{};
       L.kind = 5;
       L.dt = dt;
       L.S = kr;
       L.cnt = (int)ta.size();
       L.o[0] = bp.pack.add(ta);
-      L.o[1] = bp.pack.add(ts);
-      L.t[0] = ts.back();
+      L.o[1] = bp.pack.add(ws);
+      L.t[0] = ws.back();
       L.lds[0] = lds;
       bp.launches.push_back(L);
     }
+  }
   for (bf_dtype dt : {BF_U8, BF_U16, BF_F32}) {
     std::vector<RowmaxArgs> ra;
     std::vector<ColmaxArgs> ca;
@@ -922,6 +965,11 @@ bf_status enqueue_batch(bf_plan_s *pl, int n, const void *const *d_in, float *co
     hipError_t e;
     if (L.kind == 0) {
       e = launch_reset_group(s, (const ResetArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]), L.t[0], L.cnt);
+    } else if (L.kind == 6) {
+      pl->rec.begin(BF_STAGE_RANGE, s);
+      e = launch_range_stats_group(s, L.dt, (const RangeTileArgs *)(d_args + L.o[0]), (const int *)(d_args + L.o[1]),
+                                   L.t[0], L.cnt);
+      pl->rec.end(BF_STAGE_RANGE, s);
     } else if (L.kind == 5) {
       pl->rec.begin(BF_STAGE_RANGE, s);
       e = launch_range_tile_group(s, L.dt, L.S, (const RangeTileArgs *)(d_args + L.o[0]),
@@ -1086,7 +1134,7 @@ static bf_status create_plan(const bf_params *params, int32_t n_images, const Kn
     }
     const ImagePlan &ip = pl->im[i];
     const Geom &g = ip.g;
-    rowmax = std::max(rowmax, (size_t)g.H * g.W * elem_size(ip.p.dtype));
+    rowmax = std::max(rowmax, std::max<size_t>(range_ws_bytes(ip), 256));
     if (!is_toeplitz(ip.variant)) {
       lut = std::max(lut, (size_t)ip.KC * 256 * sizeof(float2));
     }
@@ -1118,7 +1166,7 @@ static bf_status create_plan(const bf_params *params, int32_t n_images, const Kn
       const size_t K = (size_t)ip.tab.K_max;
       const size_t zb = K * ip.z_per_pair;
       zsum += zb;
-      pl->rowmax_off.push_back(take((size_t)g.H * g.W * elem_size(ip.p.dtype)));
+      pl->rowmax_off.push_back(take(range_ws_bytes(ip)));
       pl->z_off.push_back(take(zb));
       pl->pq_off.push_back(take((size_t)(t ? ip.tc.groups : g.hgroups) * g.H * g.W * sizeof(float2)));
       pl->glut_off.push_back(take(t ? 0 : K * 256 * sizeof(float2)));

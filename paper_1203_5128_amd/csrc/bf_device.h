@@ -175,7 +175,9 @@ struct RangeAccSlot {
 };
 struct RangeAcc {
   RangeAccSlot *top;
-  RangeAccSlot *sub;  // [kRangeSubs]
+  RangeAccSlot *sub;       // [kRangeSubs]
+  unsigned long long *lb;  // [kRangeSubs] lower bounds of T from the tile statistics
+                           // (double bit patterns, merged by tile index mod kRangeSubs)
 };
 struct RangeTileArgs {
   GroupGrid gg;
@@ -185,7 +187,26 @@ struct RangeTileArgs {
   DevState st;
   RangeAcc acc;
   int32_t T_cap;
+  int2 *tstats;  // per 32 x 32 tile: (max key, min key) of f, written by the statistics
+                 // pass; null: no statistics, every tile is computed
+  int nwg;       // workgroups of the tile kernel for this image (tile t: workgroup t mod nwg)
 };
+// Workgroups of the tile kernel for an image of `tiles` tiles when a launch
+// covers `total` tiles: about kRangeTileWgs in all, each image's tiles
+// spread over its share.
+constexpr int kRangeTileWgs = 2048;
+__host__ __device__ inline int range_tile_wgs(int tiles, long long total) {
+  const long long per = total > kRangeTileWgs ? total / kRangeTileWgs : 1;
+  return (int)((tiles + per - 1) / per);
+}
+// Single images with fewer tiles run the tile kernel without statistics.
+constexpr int kRangeStatsMinTiles = 1024;
+// Grid of the statistics pass over a tile grid gt: (tile columns, strips of
+// kStatTiles tiles).
+constexpr int kStatTiles = 4;
+__host__ __device__ inline GroupGrid range_stats_grid(const GroupGrid &gt) {
+  return GroupGrid{gt.gx, (gt.gy + kStatTiles - 1) / kStatTiles, 1};
+}
 
 struct ToepVArgs {  // vertical pass: blocks (launch tile index, pair)
   GroupGrid gg;
@@ -262,8 +283,10 @@ struct PatchArgs {
   Patch8x4 *out;
 };
 hipError_t launch_patch_pack(hipStream_t s, const PatchArgs &a);
-// Algorithm 1 for one image, with the state reset it needs (the one-launch
-// tile kernel when range_tile_ok(R, dt), else reset + row pass + column pass).
+// Algorithm 1 for one image, with the state reset it needs (tile statistics
+// and the one-launch tile kernel when range_tile_ok(R, dt), rowmax then
+// holding the statistics; else reset + row pass + column pass, rowmax
+// holding the row maxima).
 hipError_t launch_range(hipStream_t s, bf_dtype dt, const void *f, const Geom &g, int R, void *rowmax,
                         DevState st, RangeAcc acc, int32_t T_cap, const StageRec &rec);
 // Grids of the two-pass range stage for one image (R > 48), and the
@@ -276,6 +299,10 @@ GroupGrid range_tile_grid(const Geom &g);
 size_t range_tile_lds(int R, bf_dtype dt);
 hipError_t launch_range_tile_group(hipStream_t s, bf_dtype dt, int kr, const RangeTileArgs *a, const int *start,
                                    int total, int n, size_t lds);
+// Tile statistics of the one-launch kernel's images (same grid), which must
+// precede it: a.tstats and a.acc.lb are written.
+hipError_t launch_range_stats_group(hipStream_t s, bf_dtype dt, const RangeTileArgs *a, const int *start, int total,
+                                    int n);
 // Grouped launches over n images (device argument arrays and block starts).
 hipError_t launch_reset_group(hipStream_t s, const ResetArgs *a, const int *start, int total, int n);
 hipError_t launch_range_group(hipStream_t s, bf_dtype dt, const RowmaxArgs *ra, const int *rstart, int rtotal,

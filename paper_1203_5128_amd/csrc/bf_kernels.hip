@@ -464,8 +464,9 @@ __device__ __forceinline__ int line_max(int a, int b, int c) {
 // the last arrival reads the slot (by exchange) only after its own increment
 // returned: every merged value is seen without L2 writeback fences.
 __device__ __forceinline__ bool acc_merge(RangeAccSlot *c, unsigned long long &t, int32_t &fl, uint32_t n) {
-  const unsigned long long om = atomicMax(&c->T, t);
-  const int32_t of = atomicOr(&c->flags, fl);
+  // (zero is both merges' identity: an arrival with nothing to merge only counts)
+  const unsigned long long om = t ? atomicMax(&c->T, t) : 0ull;
+  const int32_t of = fl ? atomicOr(&c->flags, fl) : 0;
   uint32_t one = 1u;
   asm volatile("" : "+v"(one) : "v"(om), "v"(of));
   const uint32_t done = atomicAdd(&c->count, one);
@@ -479,13 +480,177 @@ __device__ __forceinline__ bool acc_merge(RangeAccSlot *c, unsigned long long &t
   return true;
 }
 
+// Tile statistics.  T = max over x of (max of f over the window of x) -
+// f(x) is a maximum over the pixels, so the tile kernel may skip a block of
+// outputs none of which can exceed a value T is known to reach; the result
+// is unchanged.  Per 32 x 32 output tile this pass records the maximum and
+// the minimum of f (as keys), and a lower bound of T: the largest
+// (maximum - minimum) over the b x b sub-blocks of the tiles, b the largest
+// power of two <= min(R + 1, 32) -- two samples of such a sub-block lie in
+// each other's window, so T reaches their difference.  Tiles of a strip with
+// a non-finite sample record (INT_MAX, INT_MIN), which no bound lets skip.
+// One workgroup of 256 threads per strip of kStatTiles tiles down a column
+// of tiles (all loads issued at once); thread (g, c) holds rows 4g..4g+3 of
+// column c of each tile.
+constexpr int kStatThreads = 256;
+template <typename Tin>
+__device__ __forceinline__ double key_diff(int mx, int mn) {
+  return mx >= mn ? (double)tile_unkey<Tin>(mx) - (double)tile_unkey<Tin>(mn) : 0.0;
+}
+template <typename Tin>
+__device__ __forceinline__ void range_stats_body(const RangeTileArgs &a, const Blk b) {
+  constexpr int NT = kStatTiles;
+  __shared__ int smx[NT][8][kTileW], smn[NT][8][kTileW];
+  __shared__ double wlb[kStatThreads / 64];
+  const Tin *__restrict__ f = (const Tin *)a.f;
+  const int tid = threadIdx.x, c = tid & 31, g = tid >> 5, lane = tid & 63;
+  const int x = b.x * kTileW + c, xc = min(x, a.W - 1);
+  const int by0 = b.y * NT;
+  float v[NT][4];
+#pragma unroll
+  for (int k = 0; k < NT; k++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int y = (by0 + k) * kTileH + 4 * g + i;
+      v[k][i] = fval(f[(int64_t)min(y, a.H - 1) * a.pitch + xc]);
+    }
+  // sub-block size: a power of two <= min(R + 1, 32)
+  int sb = 1;
+  while (2 * sb <= min(a.R + 1, kTileW)) sb *= 2;
+  bool bad = false;
+  double lb = 0.0;
+#pragma unroll
+  for (int k = 0; k < NT; k++) {
+    int kx[4], kn[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int y = (by0 + k) * kTileH + 4 * g + i;
+      const bool in = x < a.W && y < a.H;
+      const bool fin = isfinite(v[k][i]);
+      if (in && !fin) bad = true;
+      kx[i] = (in && fin) ? tile_key<Tin>(v[k][i]) : INT_MIN;
+      kn[i] = (in && fin) ? tile_key<Tin>(v[k][i]) : INT_MAX;
+    }
+    if (sb == 2 || sb == 4) {  // sub-blocks inside the thread's four rows
+      int m0 = sb == 2 ? max(kx[0], kx[1]) : max(max(kx[0], kx[1]), max(kx[2], kx[3]));
+      int n0 = sb == 2 ? min(kn[0], kn[1]) : min(min(kn[0], kn[1]), min(kn[2], kn[3]));
+      int m1 = sb == 2 ? max(kx[2], kx[3]) : INT_MIN;
+      int n1 = sb == 2 ? min(kn[2], kn[3]) : INT_MAX;
+      for (int o = 1; o < sb; o <<= 1) {
+        m0 = max(m0, __shfl_xor(m0, o, 64));
+        n0 = min(n0, __shfl_xor(n0, o, 64));
+        m1 = max(m1, __shfl_xor(m1, o, 64));
+        n1 = min(n1, __shfl_xor(n1, o, 64));
+      }
+      lb = fmax(lb, fmax(key_diff<Tin>(m0, n0), key_diff<Tin>(m1, n1)));
+    }
+    smx[k][g][c] = max(max(kx[0], kx[1]), max(kx[2], kx[3]));
+    smn[k][g][c] = min(min(kn[0], kn[1]), min(kn[2], kn[3]));
+  }
+  bad = __syncthreads_or(bad) != 0;
+  if (sb >= 8) {  // sub-blocks of sb / 4 row groups: segment g mod (32 / sb)
+    const int rows = sb / 4, seg = g % (kTileW / sb);
+#pragma unroll
+    for (int k = 0; k < NT; k++) {
+      int m = INT_MIN, n = INT_MAX;
+      for (int r = 0; r < rows; r++) {
+        m = max(m, smx[k][seg * rows + r][c]);
+        n = min(n, smn[k][seg * rows + r][c]);
+      }
+      for (int o = 1; o < sb; o <<= 1) {
+        m = max(m, __shfl_xor(m, o, 64));
+        n = min(n, __shfl_xor(n, o, 64));
+      }
+      lb = fmax(lb, key_diff<Tin>(m, n));
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) lb = fmax(lb, __shfl_xor(lb, o, 64));
+  if (lane == 0) wlb[tid >> 6] = lb;
+  // tile k's maximum and minimum: wave k, one column per lane
+  const int k = tid >> 6;
+  if (k < NT && by0 + k < a.gg.gy) {
+    int m = INT_MIN, n = INT_MAX;
+#pragma unroll
+    for (int r = 0; r < 8; r++) {
+      m = max(m, smx[k][r][c]);
+      n = min(n, smn[k][r][c]);
+    }
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+      m = max(m, __shfl_xor(m, o, 64));
+      n = min(n, __shfl_xor(n, o, 64));
+    }
+    if (lane == 0) a.tstats[(by0 + k) * a.gg.gx + b.x] = bad ? make_int2(INT_MAX, INT_MIN) : make_int2(m, n);
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int w = 1; w < kStatThreads / 64; w++) lb = fmax(lb, wlb[w]);
+    const int bl = b.y * a.gg.gx + b.x;
+    if (!bad && lb > 0.0)
+      atomicMax(a.acc.lb + bl % kRangeSubs, (unsigned long long)__double_as_longlong(lb));
+  }
+}
+template <typename Tin>
+__global__ __launch_bounds__(kStatThreads) void k_range_stats(RangeTileArgs a) {
+  range_stats_body<Tin>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
+}
+template <typename Tin>
+__global__ __launch_bounds__(kStatThreads) void k_range_stats_grp(const RangeTileArgs *__restrict__ a,
+                                                                   const int *__restrict__ start, int n) {
+  const int i = group_find(start, n, blockIdx.x);
+  range_stats_body<Tin>(a[i], group_blk(range_stats_grid(a[i].gg), blockIdx.x - start[i]));
+}
+
+// The largest lower bound of T merged by the statistics pass (0 without
+// one), in every lane.
+__device__ __forceinline__ double tile_lower_bound(const RangeTileArgs &a, int lane) {
+  double l = (a.tstats && lane < kRangeSubs) ? __longlong_as_double((long long)a.acc.lb[lane]) : 0.0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) l = fmax(l, __shfl_xor(l, o, 64));
+  return l;
+}
+// Tiles c0 + j nwg (j < 64) of the image that must be computed, as a lane
+// mask: those inside the image whose bound -- the largest maximum of the
+// tiles the windows of its outputs reach (R <= 48: at most two tiles away)
+// minus its own minimum -- exceeds the lower bound lb.  Without statistics
+// every tile inside the image.
+template <typename Tin>
+__device__ __forceinline__ unsigned long long tiles_to_compute(const RangeTileArgs &a, int c0, int nwg, int ntiles,
+                                                               int lane, double lb) {
+  const int t = c0 + lane * nwg;
+  bool keep = t < ntiles;
+  if (a.tstats) {
+    const int gx = a.gg.gx, gy = a.gg.gy, tc = min(t, ntiles - 1);
+    const int by = tc / gx, bx = tc - by * gx;
+    const int rt = (a.R + kTileW - 1) / kTileW;
+    int nmax = INT_MIN;
+#pragma unroll
+    for (int dy = -2; dy <= 2; dy++)
+#pragma unroll
+      for (int dx = -2; dx <= 2; dx++) {
+        const int ty = by + dy, tx = bx + dx;
+        const bool in = abs(dy) <= rt && abs(dx) <= rt && ty >= 0 && ty < gy && tx >= 0 && tx < gx;
+        const int v = a.tstats[min(max(ty, 0), gy - 1) * gx + min(max(tx, 0), gx - 1)].x;
+        nmax = in ? max(nmax, v) : nmax;
+      }
+    const double ub = (double)tile_unkey<Tin>(nmax) - (double)tile_unkey<Tin>(a.tstats[tc].y);
+    keep = keep && !(ub <= lb);
+  }
+  return __ballot(keep);
+}
+
+// One output tile (bx, by) of the tile kernel: stages, filters, and folds
+// its outputs' (window maximum - f) into tmax and its non-finite samples
+// into bad.  Starts with a barrier (the previous tile's readers of LDS).
 template <typename Tin, int KR>
-__device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Blk b) {
+__device__ __forceinline__ void range_tile_one(const RangeTileArgs &a, int bx, int by, bool &bad_out,
+                                               double &tmax) {
   using KeyT = typename TileKey<Tin>::T;
   constexpr int RS = tile_rs<KR>();
   constexpr bool kFloat = std::is_same<Tin, float>::value;
   extern __shared__ float tlds[];
-  __shared__ double wmax[kTileWaves];
   const Tin *__restrict__ f = (const Tin *)a.f;
   const int64_t pitch = a.pitch;
   const int H = a.H, W = a.W, R = a.R;
@@ -498,13 +663,14 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
   float *fc = (float *)(rm + L * kTileMS);
   const int tid = threadIdx.x, lane = tid & 63, j = lane & 31, half = lane >> 5;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int x0 = b.x * kTileW, y0 = b.y * kTileH;
+  const int x0 = bx * kTileW, y0 = by * kTileH;
   const float pad = kFloat ? -INFINITY : 0.f;
+  bool bad = false;
+  __syncthreads();
 
   // stage: staged row e = wv + kTileWaves k, columns lane and lane + 64; every
   // lane loads from a clamped in-image address (no branch around the load,
   // so all loads stay in flight) and masks afterwards
-  bool bad = false;
   if constexpr (kGlob) {
     // only the centre samples: rows tid / 32 and tid / 32 + 16, column tid % 32
 #pragma unroll
@@ -546,6 +712,7 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
     }
   }
   bad = __syncthreads_or(bad) != 0;
+  bad_out = bad_out || bad;
 
   // row pass: staged row e = 2 it + half, four row pairs per wave in flight
   const int n1 = nc - 1, n2 = nc - 33, n3 = nc - 65;
@@ -609,7 +776,6 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
   __syncthreads();
 
   // column pass: output column cc = 2 it + half, it = wv + kTileWaves u
-  double tmax = 0.0;
   {
     constexpr int UC = kTileW / 2 / kTileWaves;
     int mv[UC];
@@ -643,24 +809,61 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
       tmax = (y0 + j < H && x0 + cc < W && d > tmax) ? d : tmax;
     }
   }
+}
+
+// Workgroup wg of nwg takes the image's tiles wg, wg + nwg, ...: per round of
+// 64 of them, wave 0 finds those that must be computed (the others cannot
+// raise T above the statistics pass's lower bound lb), then the workgroup
+// computes them one after another.  T = max(lb, the computed tiles'
+// maxima), merged once per workgroup.
+template <typename Tin, int KR>
+__device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const int wg) {
+  __shared__ double wmax[kTileWaves];
+  __shared__ unsigned long long todo_s[2];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nwg = a.nwg, ntiles = a.gg.gx * a.gg.gy;
+  const double lb = tile_lower_bound(a, lane);
+  bool bad = false;
+  double tmax = 0.0;
+  for (int c0 = wg, r = 0; c0 < ntiles; c0 += 64 * nwg, r ^= 1) {
+    if (wv == 0) {
+      const unsigned long long m = tiles_to_compute<Tin>(a, c0, nwg, ntiles, lane, lb);
+      if (lane == 0) todo_s[r] = m;
+    }
+    __syncthreads();  // (double-buffered: wave 0 writes the other slot next round)
+    unsigned long long todo = todo_s[r];
+    todo = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(todo >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)todo);
+    while (todo) {
+      const int jt = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int t = c0 + jt * nwg, by = t / a.gg.gx;
+      range_tile_one<Tin, KR>(a, t - by * a.gg.gx, by, bad, tmax);
+    }
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     const double o = __shfl_xor(tmax, off, 64);
     tmax = o > tmax ? o : tmax;
   }
   if (lane == 0) wmax[wv] = tmax;
+  // also orders every wave's read of the lower bounds before the arrival
+  // below (the last arrival clears them)
   __syncthreads();
 
   if (tid == 0) {
     tmax = wmax[0];
 #pragma unroll
     for (int w = 1; w < kTileWaves; w++) tmax = fmax(tmax, wmax[w]);
-    const int nb = a.gg.gx * a.gg.gy, bl = b.y * a.gg.gx + b.x;
-    const int sub = bl % kRangeSubs, nsub = min(nb, kRangeSubs);
+    const int sub = wg % kRangeSubs, nsub = min(nwg, kRangeSubs);
+    // the computed tiles' maximum only (non-negative: the bit patterns order
+    // as the values); the lower bound joins at the publication
     unsigned long long t = (unsigned long long)__double_as_longlong(tmax);
     int32_t fl = bad ? 1 : 0;
-    if (acc_merge(a.acc.sub + sub, t, fl, (uint32_t)((nb - sub + kRangeSubs - 1) / kRangeSubs)) &&
+    if (acc_merge(a.acc.sub + sub, t, fl, (uint32_t)((nwg - sub + kRangeSubs - 1) / kRangeSubs)) &&
         acc_merge(a.acc.top, t, fl, (uint32_t)nsub)) {
+      t = (unsigned long long)__double_as_longlong(fmax(__longlong_as_double((long long)t), lb));
       const double tc = ceil(__longlong_as_double((long long)t));
       const int32_t ti = tc > 2147483647.0 ? 2147483647 : (int32_t)tc;
       const DevState st = a.st;
@@ -668,18 +871,22 @@ __device__ __forceinline__ void range_tile_body(const RangeTileArgs &a, const Bl
       *st.T_used = ti;
       *st.flags = fl | (ti > a.T_cap ? 2 : 0);
       *st.q_nonpos = 0ull;
+      if (a.tstats) {
+#pragma unroll 4
+        for (int k = 0; k < kRangeSubs; k++) atomicExch(a.acc.lb + k, 0ull);
+      }
     }
   }
 }
 template <typename Tin, int KR>
 __global__ __launch_bounds__(kTileThreads) void k_range_tile(RangeTileArgs a) {
-  range_tile_body<Tin, KR>(a, Blk{(int)blockIdx.x, (int)blockIdx.y, 0});
+  range_tile_body<Tin, KR>(a, (int)blockIdx.x);
 }
 template <typename Tin, int KR>
 __global__ __launch_bounds__(kTileThreads) void k_range_tile_grp(const RangeTileArgs *__restrict__ a,
                                                                  const int *__restrict__ start, int n) {
   const int i = group_find(start, n, blockIdx.x);
-  range_tile_body<Tin, KR>(a[i], group_blk(a[i].gg, blockIdx.x - start[i]));
+  range_tile_body<Tin, KR>(a[i], __builtin_amdgcn_readfirstlane((int)blockIdx.x - start[i]));
 }
 
 // --------------------------------------------- blocked recursive Gaussian
@@ -1442,12 +1649,17 @@ static hipError_t range_t(hipStream_t s, const Tin *f, const Geom &g, int R, Tin
   if (range_tile_ok(R, dtype_of<Tin>())) {
     rec.begin(BF_STAGE_RANGE, s);
     const GroupGrid gt = range_tile_grid(g);
-    RangeTileArgs ta{gt, f, g.pitch, g.H, g.W, R, st, acc, T_cap};
+    const int tiles = gt.gx * gt.gy;
+    const bool stats = tiles >= kRangeStatsMinTiles;
+    RangeTileArgs ta{gt, f, g.pitch, g.H, g.W, R, st, acc, T_cap, stats ? (int2 *)rowmax : nullptr,
+                     range_tile_wgs(tiles, tiles)};
+    const GroupGrid gs = range_stats_grid(gt);
+    if (stats) hipLaunchKernelGGL(k_range_stats<Tin>, dim3(gs.gx, gs.gy), dim3(kStatThreads), 0, s, ta);
     const size_t lds = range_tile_lds(R, dtype_of<Tin>());
     if (range_tile_kr(R) == 32)
-      hipLaunchKernelGGL((k_range_tile<Tin, 32>), dim3(gt.gx, gt.gy), dim3(kTileThreads), lds, s, ta);
+      hipLaunchKernelGGL((k_range_tile<Tin, 32>), dim3(ta.nwg), dim3(kTileThreads), lds, s, ta);
     else
-      hipLaunchKernelGGL((k_range_tile<Tin, 48>), dim3(gt.gx, gt.gy), dim3(kTileThreads), lds, s, ta);
+      hipLaunchKernelGGL((k_range_tile<Tin, 48>), dim3(ta.nwg), dim3(kTileThreads), lds, s, ta);
     rec.end(BF_STAGE_RANGE, s);
     return hipGetLastError();
   }
@@ -1490,6 +1702,19 @@ static hipError_t range_tile_group_t(hipStream_t s, int kr, const RangeTileArgs 
       hipLaunchKernelGGL((k_range_tile_grp<Tin, 48>), dim3(total), dim3(kTileThreads), lds, s, a, start, n);
   }
   return hipGetLastError();
+}
+template <typename Tin>
+static hipError_t range_stats_group_t(hipStream_t s, const RangeTileArgs *a, const int *start, int total, int n) {
+  if (total > 0) hipLaunchKernelGGL(k_range_stats_grp<Tin>, dim3(total), dim3(kStatThreads), 0, s, a, start, n);
+  return hipGetLastError();
+}
+hipError_t launch_range_stats_group(hipStream_t s, bf_dtype dt, const RangeTileArgs *a, const int *start, int total,
+                                    int n) {
+  switch (dt) {
+    case BF_U8: return range_stats_group_t<uint8_t>(s, a, start, total, n);
+    case BF_U16: return range_stats_group_t<uint16_t>(s, a, start, total, n);
+    default: return range_stats_group_t<float>(s, a, start, total, n);
+  }
 }
 hipError_t launch_range_tile_group(hipStream_t s, bf_dtype dt, int kr, const RangeTileArgs *a, const int *start,
                                    int total, int n, size_t lds) {
