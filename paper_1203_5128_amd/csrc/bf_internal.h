@@ -78,9 +78,9 @@ bool build_rp_table(double sigma_r, double eps, double L, double T, RpTable &out
 // ------------------------------------------- recursive Gaussian constants
 // State of one direction of the cascade after element n: (s[n], w[n], d[n])
 // with s the first-order section, w the second-order section output and
-// d[n] = w[n] - w[n-1].  Carrying the difference instead of w[n-1] keeps the
-// FP32 rounding of the second-order section from being fed back through its
-// poles, which sit close to z = 1 for wide Gaussians.
+// d[n] = (w[n] - w[n-1]) / g2.  Carrying the (scaled) increment instead of
+// w[n-1] keeps the FP32 rounding of the second-order section from being fed
+// back through its poles, which sit close to z = 1 for wide Gaussians.
 // Rows and columns are padded with zeros to whole chunks and the
 // zero-extension boundary is applied at the padded end: the causal outputs in
 // the padding are exactly the continuation of the zero-extended signal, so the

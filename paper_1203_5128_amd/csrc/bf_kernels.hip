@@ -63,13 +63,13 @@ __device__ __forceinline__ void apow_mul(const float *__restrict__ M, const floa
 // first-order section s = a1 s + x (a1 = 1 - g1; the input gain g1 is left
 // out, a constant factor per pass common to all smoothed images, which
 // cancels in P / Q), then the second-order section carried as
-// w[n] = w[n-1] + d[n], d[n] = g2 (s - w[n-1]) - c2 d[n-1].
+// d[n] = (s - w[n-1]) - c2 d[n-1], w[n] = w[n-1] + g2 d[n] (d is the
+// increment of w divided by g2): four operations per sample and image.
 __device__ __forceinline__ void casc_step(float a1, float g2, float c2, float4 x, float4 &s, float4 &w,
                                           float4 &d) {
   s = fma4(a1, s, x);
-  float4 nd = fma4(-c2, d, make_float4(g2 * (s.x - w.x), g2 * (s.y - w.y), g2 * (s.z - w.z), g2 * (s.w - w.w)));
-  w = add4(w, nd);
-  d = nd;
+  d = fma4(-c2, d, sub4(s, w));
+  w = fma4(g2, d, w);
 }
 
 // ---- segmented running maxima across a wave (Appendix MAX-FILTER) --------

@@ -295,14 +295,15 @@ M3 mpow(const M3 &x, long e) {
 }
 struct Casc {
   double g1, g2, c2;
-  // one step of the cascade on state (s, w, d) with input x, d = w[n] - w[n-1].
-  // The first-order section runs without its input gain g1 (s = (1-g1) s + x):
-  // each pass then scales its output by 1/g1, a constant shared by every
-  // smoothed image that cancels in the ratio of eqs. (f1), (f2).
+  // one step of the cascade on state (s, w, d) with input x,
+  // d = (w[n] - w[n-1]) / g2.  The first-order section runs without its input
+  // gain g1 (s = (1-g1) s + x): each pass then scales its output by 1/g1, a
+  // constant shared by every smoothed image that cancels in the ratio of
+  // eqs. (f1), (f2).
   void step(double st[3], double x) const {
     double s = (1.0 - g1) * st[0] + x;
-    double d = g2 * (s - st[1]) - c2 * st[2];
-    st[1] = st[1] + d;
+    double d = (s - st[1]) - c2 * st[2];
+    st[1] = st[1] + g2 * d;
     st[2] = d;
     st[0] = s;
   }
@@ -323,8 +324,8 @@ bool build_iir_consts(double sigma_s, std::vector<float> &out, std::string &err)
   // zero-input step of Casc as a matrix on (s, w, d)
   M3 A{};
   A.a[0] = 1.0 - g1;
-  A.a[3] = g2 * (1.0 - g1); A.a[4] = 1.0 - g2; A.a[5] = -c2;
-  A.a[6] = g2 * (1.0 - g1); A.a[7] = -g2;      A.a[8] = -c2;
+  A.a[3] = g2 * (1.0 - g1); A.a[4] = 1.0 - g2; A.a[5] = -g2 * c2;
+  A.a[6] = 1.0 - g1;        A.a[7] = -1.0;     A.a[8] = -c2;
   // zero-extension boundary: continue the causal recursion with zero input
   // past the end, run the anticausal recursion back from far away
   long L = (long)std::ceil(40.0 * sigma_s) + 64;

@@ -119,8 +119,8 @@ def _sweep(x, st, a1, g2, c2, rev=False):
     idx = range(len(x) - 1, -1, -1) if rev else range(len(x))
     for i in idx:
         s = a1 * s + x[i]
-        d = g2 * (s - w) - c2 * d
-        w = w + d
+        d = (s - w) - c2 * d
+        w = w + g2 * d
         out[i] = w
     return out, np.array([s, w, d])
 
