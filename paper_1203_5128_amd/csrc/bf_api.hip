@@ -486,7 +486,11 @@ bf_status prepare_image(const bf_params &p, ImagePlan &ip, const Knobs &kn) {
   g.S = S;
   g.logS = logS;
   g.cC = cC;
-  g.Spos = S * cC;
+  // positions: whole chunks only; the row group's remaining threads (a
+  // power of two in all) hold no positions and smooth zeros, so neither the
+  // vertical pass nor the smoothed images carry the padding of the group
+  g.Seff = (g.W + cC - 1) / cC;
+  g.Spos = g.Seff * cC;
   // vertical pass: one row group per column, kCLarge rows per thread; float
   // input (whose phases are computed per sample, not read from a table)
   // kCSmall up to 4096 rows: half the registers, three waves per SIMD

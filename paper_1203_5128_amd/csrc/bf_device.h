@@ -53,9 +53,11 @@ struct Geom {
   int H, W;
   int64_t pitch;      // input pitch (elements)
   int64_t opitch;     // output pitch (elements)
-  int S, logS;        // threads per row in the horizontal pass (power of two)
+  int S, logS;        // threads per row group in the horizontal pass (power of two)
   int cC;             // pixels per thread in the horizontal pass (kCSmall or kCLarge)
-  int Spos;           // S * cC positions per padded row
+  int Seff;           // threads of a row group that hold positions: ceil(W / cC) <= S;
+                      // the others smooth zeros (the row's zero extension)
+  int Spos;           // Seff * cC positions per padded row
   int vS, vC;         // vertical pass: threads per column (power of two), rows per thread
   int vppw;           // vertical pass: pairs per workgroup (one after another)
   // smoothed images of the recursive path, stored in tiles of zth = 2^zlog

@@ -900,7 +900,8 @@ __global__ __launch_bounds__(kTileThreads) void k_range_tile_grp(const RangeTile
 // zero-extension boundary.
 //
 // Positions p index the padded row in an interleaved order: p -> column
-// x = (p mod S) * c + p / S, so that the horizontal pass, where thread t owns
+// x = (p mod Seff) * c + p / Seff (Seff = ceil(W / c) threads of the row
+// group hold positions), so that the horizontal pass, where thread t owns
 // columns [t c, t c + c), reads consecutive addresses.
 
 // Lane moves inside a wave through DPP (VALU only, no LDS round trip).  Lanes
@@ -1200,7 +1201,7 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
   if (kb >= kend) return;  // the whole workgroup: no pair kept for this image's T
   const int p = cbx * NG + grp;
   const bool inpos = p < g.Spos;
-  const int x = inpos ? (p & (g.S - 1)) * g.cC + (p >> g.logS) : 0;
+  const int x = inpos ? (p % g.Seff) * g.cC + p / g.Seff : 0;
   const bool col = inpos && x < g.W;  // a column of the image (else zeros)
   const int y0 = t * kC;
   const int xc = min(x, g.W - 1);
@@ -1384,12 +1385,17 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   Tin fv[kC];
 #pragma unroll
   for (int i = 0; i < kC; i++) fv[i] = frow[min(x0 + i, g.W - 1)];
+  // threads past the row's positions (t >= Seff) load from position 0 and
+  // smooth zeros
+  const bool tin = t < g.Seff;
+  const int tq = tin ? t : 0;
+  const size_t qstep = (size_t)g.Seff * qs;
   float4 zv[kC];
   {
     const int kl = kb + plane;
-    const float4 *q = Z + (size_t)(kl < kend ? kl : 0) * g.Hz * g.Spos + z_index(g, y, t);
+    const float4 *q = Z + (size_t)(kl < kend ? kl : 0) * g.Hz * g.Spos + z_index(g, y, tq);
 #pragma unroll
-    for (int i = 0; i < kC; i++, q += (size_t)S * qs) zv[i] = *q;
+    for (int i = 0; i < kC; i++, q += qstep) zv[i] = keep4(tin, *q);
   }
   store_iir_lds(L, tr, tid);
   __syncthreads();
@@ -1407,9 +1413,9 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
       __syncthreads();
     }
     if (it > 0) {
-      const float4 *q = Z + (size_t)(act ? kl : 0) * g.Hz * g.Spos + z_index(g, y, t);
+      const float4 *q = Z + (size_t)(act ? kl : 0) * g.Hz * g.Spos + z_index(g, y, tq);
 #pragma unroll
-      for (int i = 0; i < kC; i++, q += (size_t)S * qs) zv[i] = *q;
+      for (int i = 0; i < kC; i++, q += qstep) zv[i] = keep4(tin, *q);
     }
     group_blur<S, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
     // eqs. (f1), (f2): weight by the phase at the output pixel
@@ -1849,7 +1855,7 @@ static bool iir_geom_ok(const Geom &g, int kcount) {
   return g.hgroups >= 1 && g.hgroups <= 65535 && g.vppw >= 1 && g.hkpg >= 1 && (int64_t)g.hgroups * g.hkpg >= kcount &&
          g.hrows >= 1 && (kHThreads / g.S) % g.hrows == 0 && g.hkpg % (kHThreads / g.S / g.hrows) == 0 &&
          kcount >= 1 && kcount <= 65535 && g.vS >= 1 && g.vS <= kHThreads && (int64_t)g.vS * g.vC >= g.H &&
-         (int64_t)g.S * g.cC >= g.W && g.Spos == g.S * g.cC && g.zlog >= 0 && g.zlog <= 3 && g.Hz >= g.H && g.Hz % (1 << g.zlog) == 0 &&
+         g.Seff >= 1 && g.Seff <= g.S && (int64_t)g.Seff * g.cC >= g.W && g.Spos == g.Seff * g.cC && g.zlog >= 0 && g.zlog <= 3 && g.Hz >= g.H && g.Hz % (1 << g.zlog) == 0 &&
          ((kHThreads / g.vS) << g.zlog) >= z_tile_words(g.vS) && (g.zlog == 0 || ((kHThreads / g.vS) << g.zlog) == z_tile_words(g.vS));
 }
 
