@@ -820,11 +820,21 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
       L.t[0] = ss.back();
       bp.launches.push_back(L);
     }
+    // 8- and 16-bit input: one tile launch for all of them, staged for the
+    // largest block size among them (few tiles are computed once the
+    // statistics let the rest be skipped, so the larger staging of the
+    // R <= 32 images costs less than a second launch).  Float input: one
+    // launch per block size (its R > 32 kernel reads the rows from memory
+    // and assumes R > 32).
+    int kr_all = 32;
+    for (const RangeTileArgs &t : sa) kr_all = std::max(kr_all, range_tile_kr(t.R));
     for (int kr : {32, 48}) {
+      if (dt != BF_F32 && kr != kr_all) continue;
       std::vector<RangeTileArgs> ta;
-      size_t lds = 0;
-      tile_args(kr, ta, &lds);
+      tile_args(dt == BF_F32 ? kr : 0, ta, nullptr);
       if (ta.empty()) continue;
+      size_t lds = 0;
+      for (const RangeTileArgs &t : ta) lds = std::max(lds, range_tile_lds(t.R, dt, kr));
       long long total = 0;
       for (const RangeTileArgs &t : ta) total += t.gg.gx * t.gg.gy;
       std::vector<int> wb;

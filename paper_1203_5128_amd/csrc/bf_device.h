@@ -195,8 +195,10 @@ struct RangeTileArgs {
 };
 // Workgroups of the tile kernel for an image of `tiles` tiles when a launch
 // covers `total` tiles: about kRangeTileWgs in all, each image's tiles
-// spread over its share.
-constexpr int kRangeTileWgs = 2048;
+// spread over its share.  (Range stage of the 64-image batch with about
+// 256 / 512 / 1024 / 2048 / 4096 workgroups per launch: 148 / 118 / 110 /
+// 125 / 163 us; one tile per workgroup: 272 us.)
+constexpr int kRangeTileWgs = 1024;
 __host__ __device__ inline int range_tile_wgs(int tiles, long long total) {
   const long long per = total > kRangeTileWgs ? total / kRangeTileWgs : 1;
   return (int)((tiles + per - 1) / per);
@@ -298,7 +300,8 @@ GroupGrid range_col_grid(const Geom &g);
 bool range_tile_ok(int R, bf_dtype dt);
 int range_tile_kr(int R);  // staged-block size class (32 or 48) of a tile-kernel image
 GroupGrid range_tile_grid(const Geom &g);
-size_t range_tile_lds(int R, bf_dtype dt);
+// LDS of the tile kernel for radius R staged as block size kr (0: R's own)
+size_t range_tile_lds(int R, bf_dtype dt, int kr = 0);
 hipError_t launch_range_tile_group(hipStream_t s, bf_dtype dt, int kr, const RangeTileArgs *a, const int *start,
                                    int total, int n, size_t lds);
 // Tile statistics of the one-launch kernel's images (same grid), which must

@@ -1638,14 +1638,15 @@ bool range_tile_ok(int R, bf_dtype dt) {
 int range_tile_kr(int R) { return R <= 32 ? 32 : 48; }
 GroupGrid range_tile_grid(const Geom &g) { return GroupGrid{(g.W + kTileW - 1) / kTileW, (g.H + kTileH - 1) / kTileH, 1}; }
 template <typename Tin>
-static size_t tile_lds_t(int R) {
-  return range_tile_kr(R) == 32 ? tile_lds_bytes<Tin, 32>(R) : tile_lds_bytes<Tin, 48>(R);
+static size_t tile_lds_t(int R, int kr) {
+  return kr == 32 ? tile_lds_bytes<Tin, 32>(R) : tile_lds_bytes<Tin, 48>(R);
 }
-size_t range_tile_lds(int R, bf_dtype dt) {
+size_t range_tile_lds(int R, bf_dtype dt, int kr) {
+  if (kr == 0) kr = range_tile_kr(R);
   switch (dt) {
-    case BF_U8: return tile_lds_t<uint8_t>(R);
-    case BF_U16: return tile_lds_t<uint16_t>(R);
-    default: return tile_lds_t<float>(R);
+    case BF_U8: return tile_lds_t<uint8_t>(R, kr);
+    case BF_U16: return tile_lds_t<uint16_t>(R, kr);
+    default: return tile_lds_t<float>(R, kr);
   }
 }
 
