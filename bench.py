@@ -452,7 +452,7 @@ def main():
                          "traffic against which the HBM byte counters are scaled)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (--gpus {args.gpus} requested); "
+        print(f"bench.py: the filter runs on exactly one GPU (--gpus {args.gpus} requested); "
               "multi-GPU sharding is a design note only", file=sys.stderr)
         sys.exit(2)
 

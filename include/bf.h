@@ -43,7 +43,7 @@ extern "C" {
 typedef enum {
   BF_OK = 0,
   BF_ERR_INVALID_ARG = 1,   /* a parameter is out of its documented range     */
-  BF_ERR_UNSUPPORTED = 2,   /* valid but beyond this build's limits           */
+  BF_ERR_UNSUPPORTED = 2,   /* valid but beyond the library's limits          */
   BF_ERR_OUT_OF_MEMORY = 3, /* a device or host allocation failed             */
   BF_ERR_DEVICE = 4,        /* a HIP call failed (see bf_last_error_detail)   */
   BF_ERR_NOT_FINITE = 5,    /* float input held NaN or Inf (report requested) */

@@ -12,7 +12,7 @@
  * paper's order.  OpenMP only splits loops over independent rows/columns/
  * pixels; no sum is reordered, so results do not depend on the thread count.
  *
- * Readings of passages the paper leaves open (each also listed in the design doc):
+ * Readings of passages the paper leaves open:
  *  - Sec. 2, Prop. 2.1 and Algorithm 1 step 4 print "f(x) - max f(x-y)", which
  *    is never positive.  The proof (|t| = max(t,-t) and the symmetry of the
  *    window) gives T = max_x [max_{y} f(x-y) - f(x)]; that is what is computed.
