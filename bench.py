@@ -89,10 +89,10 @@ def mfma_flops(stage: str, px: int, pairs: int, R: int) -> float:
     return 0.0
 
 
-def measured_traffic(stage: str, workload: str):
-    """HBM bytes per step of `stage` from the committed rocprofv3 counter
-    summary of `workload`, or None when a kernel source changed since it was
-    taken."""
+def measured_counters(stage: str, workload: str):
+    """The committed rocprofv3 counter summary of `stage` on `workload` (HBM
+    bytes per step, VALU fraction), or None when a kernel source changed
+    since it was taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{stage}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -102,7 +102,14 @@ def measured_traffic(stage: str, workload: str):
         with open(os.path.join(ROOT, src), "rb") as fh:
             if not hashlib.sha256(fh.read()).hexdigest().startswith(pre):
                 return None
-    return rec["traffic_bytes_per_step"]
+    return rec
+
+
+def measured_traffic(stage: str, workload: str):
+    """HBM bytes per step of `stage` on `workload` from the committed counter
+    summary, or None (see measured_counters)."""
+    rec = measured_counters(stage, workload)
+    return None if rec is None else rec["traffic_bytes_per_step"]
 
 
 # ------------------------------------------------------------------- timing
@@ -143,6 +150,11 @@ def roofline(stages, images, workload):
     roof = dict(bound="hbm", kernel=dom, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(ach / HBM_PEAK_GBS, 4), avg_launch_ms=round(ms / max(launches, 1), 5),
                 launches_per_step=launches, bytes_per_step=nb, traffic=measured_traffic(dom, workload))
+    rec = measured_counters(dom, workload)
+    if rec is not None and rec.get("valu_fraction") is not None:
+        # SQ_INSTS_VALU x 4 cycles / (GPU-active cycles x 1024 SIMDs), time-weighted over the
+        # stage's launches: the stage's share of the vector-ALU issue limit
+        roof["valu_fraction"] = rec["valu_fraction"]
     mf = {}
     for s in ("v_toeplitz", "h_combine"):
         fl = sum(mfma_flops(s, px, pr, R) for px, pr, _, bl, R in images if bl.startswith("toeplitz"))
