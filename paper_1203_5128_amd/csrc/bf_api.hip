@@ -47,6 +47,10 @@ struct ImagePlan {
   OrderTable tab;
   int KC = 0;              // frequency pairs per launch of the blur passes
   int hpw = 0;             // term-group width knob of the recursive horizontal pass
+  // workgroups the recursive vertical pass aims for (pairs per workgroup
+  // follow): kVWorkgroups alone, kVWorkgroupsBatch in a batch, whose grouped
+  // launch the other images fill
+  int v_target = kVWorkgroups;
   int variant = BF_BLUR_IIR_F32;
   // device memory
   int32_t *d_idx = nullptr;
@@ -298,7 +302,7 @@ void set_chunk(ImagePlan &ip, int KC) {
     // vertical pass: pairs per workgroup for about one round of workgroups
     const int ncb = (g.Spos + kHThreads / g.vS - 1) / (kHThreads / g.vS);
     const int gx = 8 * ((ncb + 7) / 8);
-    int target = kVWorkgroups;
+    int target = ip.v_target;
     if (const char *w = std::getenv("BF_V_WG")) target = std::max(1, std::atoi(w));
     const int groups = std::max(1, std::min(KC, (target + gx - 1) / gx));
     g.vppw = (KC + groups - 1) / groups;
@@ -1141,6 +1145,7 @@ static bf_status create_plan(const bf_params *params, int32_t n_images, const Kn
   pl->im.resize(n_images);
   size_t rowmax = 0, Z = 0, PQ = 0, lut = 0, patch = 0;
   for (int i = 0; i < n_images; i++) {
+    pl->im[i].v_target = n_images > 1 ? kVWorkgroupsBatch : kVWorkgroups;
     bf_status s = prepare_image(params[i], pl->im[i], knobs ? knobs[i] : Knobs());
     if (s) {
       bf_plan_destroy(pl);
