@@ -794,7 +794,7 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
   for (bf_dtype dt : {BF_U8, BF_U16, BF_F32}) {
     // the tile statistics of every tile-kernel image of this dtype (one
     // workgroup per strip of tiles), then one tile launch per staged-block size
-    auto tile_args = [&](int kr, std::vector<RangeTileArgs> &ta, size_t *lds) {
+    auto tile_args = [&](int kr, std::vector<RangeTileArgs> &ta) {
       for (int i : gidx) {
         const ImagePlan &ip = pl->im[i];
         if (ip.p.t_mode != BF_T_LOCAL || ip.p.dtype != dt || !range_tile_ok(ip.R, dt) ||
@@ -802,11 +802,10 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
           continue;
         ta.push_back(RangeTileArgs{range_tile_grid(ip.g), d_in[i], ip.g.pitch, ip.g.H, ip.g.W, ip.R, state_of(ip),
                                    acc_of(ip), ip.T_cap, (int2 *)((char *)pl->d_bws + pl->rowmax_off[i]), 0});
-        if (lds) *lds = std::max(*lds, range_tile_lds(ip.R, dt));
       }
     };
     std::vector<RangeTileArgs> sa;
-    tile_args(0, sa, nullptr);
+    tile_args(0, sa);
     if (sa.empty()) continue;
     {
       std::vector<int> sb;
@@ -835,7 +834,7 @@ void build_batch(bf_plan_s *pl, int n, const void *const *d_in, float *const *d_
     for (int kr : {32, 48}) {
       if (dt != BF_F32 && kr != kr_all) continue;
       std::vector<RangeTileArgs> ta;
-      tile_args(dt == BF_F32 ? kr : 0, ta, nullptr);
+      tile_args(dt == BF_F32 ? kr : 0, ta);
       if (ta.empty()) continue;
       size_t lds = 0;
       for (const RangeTileArgs &t : ta) lds = std::max(lds, range_tile_lds(t.R, dt, kr));
