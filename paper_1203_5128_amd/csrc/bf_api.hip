@@ -47,10 +47,11 @@ struct ImagePlan {
   OrderTable tab;
   int KC = 0;              // frequency pairs per launch of the blur passes
   int hpw = 0;             // term-group width knob of the recursive horizontal pass
-  // workgroups the recursive vertical pass aims for (pairs per workgroup
-  // follow): kVWorkgroups alone, kVWorkgroupsBatch in a batch, whose grouped
-  // launch the other images fill
+  // workgroups the recursive vertical and horizontal passes aim for (pairs
+  // per workgroup follow): kVWorkgroups / kHWorkgroups alone, the *Batch
+  // values in a batch, whose grouped launches the other images fill
   int v_target = kVWorkgroups;
+  int h_target = kHWorkgroups;
   int variant = BF_BLUR_IIR_F32;
   // device memory
   int32_t *d_idx = nullptr;
@@ -315,7 +316,7 @@ void set_chunk(ImagePlan &ip, int KC) {
     // groups of workgroups to fill the GPU (as many as with one row per
     // workgroup), each group a whole number of the pw pairs in flight.
     const int ng = kHThreads / g.S;
-    int target = kHWorkgroups;
+    int target = ip.h_target;
     if (const char *w = std::getenv("BF_H_WG")) target = std::max(1, std::atoi(w));
     const int groups = std::max(1, std::min((KC + ng - 1) / ng, (target + g.H - 1) / g.H));
     int pw = ng;
@@ -1145,6 +1146,7 @@ static bf_status create_plan(const bf_params *params, int32_t n_images, const Kn
   size_t rowmax = 0, Z = 0, PQ = 0, lut = 0, patch = 0;
   for (int i = 0; i < n_images; i++) {
     pl->im[i].v_target = n_images > 1 ? kVWorkgroupsBatch : kVWorkgroups;
+    pl->im[i].h_target = n_images > 1 ? kHWorkgroupsBatch : kHWorkgroups;
     bf_status s = prepare_image(params[i], pl->im[i], knobs ? knobs[i] : Knobs());
     if (s) {
       bf_plan_destroy(pl);
