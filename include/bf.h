@@ -30,6 +30,23 @@
  *    the input.
  *  - A plan is not re-entrant: one stream at a time per plan.  Separate plans
  *    on separate streams are independent.
+ *
+ * Environment (read at plan creation; results stay within the same error
+ * bar, only launch shapes and timing change):
+ *  - BF_TUNE_CACHE=<file>: the autotuner's choices are read from and
+ *    appended to this file (one JSON object per line); BF_TUNE_LOG prints
+ *    them to stderr.
+ *  - BF_GRAPH=0: launch the kernels directly instead of replaying a captured
+ *    HIP graph.
+ *  - BF_Z_BUDGET_MB=<n>: device memory for the smoothed images of a launch
+ *    (default 64 GiB); a smaller budget runs the pairs in several launches,
+ *    and a batch whose images need more runs them one after another.
+ *  - Shape overrides for measurement: BF_HCHUNK / BF_VCHUNK (16 or 32
+ *    samples per thread of the recursive passes), BF_H_WG / BF_V_WG
+ *    (workgroups the recursive passes aim for), BF_TOEP_LDS_KB (LDS of a
+ *    Toeplitz workgroup).
+ *  - BF_FAIL_ALLOC: every device allocation fails with BF_ERR_OUT_OF_MEMORY
+ *    (a test hook for that path).
  */
 #ifndef BF_H_
 #define BF_H_
