@@ -1229,17 +1229,27 @@ __device__ __forceinline__ void iir_v_impl(const Tin *__restrict__ f, const Geom
     const int it = kl - kb;
     float2 *lt = lut + (it & 1) * 257;
     if constexpr (kLut) {
-      // the other buffer was last read before the previous pair's barrier
+      // the other buffer was last read before the previous pair's barrier.
+      // One workgroup per pair also leaves the table for the horizontal
+      // pass, times the pair's weight (eqs. (f1), (f2)), which the
+      // horizontal pass then need not apply per pixel
       if (tab.lut_gen) {
         // polynomial kernel: basis values per intensity from the table; the
         // horizontal pass combines with the coefficients instead
         const size_t row = (size_t)(e.off + k0 + kl) * 256 + tid;
         lt[tid] = tab.lut_gen[row];
-        if (cbx == 0) glut[(size_t)kl * 256 + tid] = tab.lut_comb[row];
+        if (cbx == 0) {
+          const float w = const_load(tab.pc + e.off + k0 + kl);
+          const float2 cc = tab.lut_comb[row];
+          glut[(size_t)kl * 256 + tid] = make_float2(w * cc.x, w * cc.y);
+        }
       } else {
         build_lut(lt, m, e.qfix, e.alpha_turn, tid, kHThreads);
-        // one workgroup per pair also leaves the table for the horizontal pass
-        if (cbx == 0) glut[(size_t)kl * 256 + tid] = lt[tid];
+        if (cbx == 0) {
+          const float w = const_load(tab.pc + e.off + k0 + kl);
+          const float2 cs = lt[tid];
+          glut[(size_t)kl * 256 + tid] = make_float2(w * cs.x, w * cs.y);
+        }
       }
       if (tid == 0) lt[256] = make_float2(0.f, 0.f);
       __syncthreads();
@@ -1433,17 +1443,18 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
 #pragma unroll
       for (int i = 0; i < kC; i++) {
         if (i < nx) {
-          float c, sn;
-          if constexpr (PhaseLut<Tin>::kOn) {
-            const float2 cs = kLutLds ? slut[plane * 256 + (int)fv[i]] : lk[(int)fv[i]];
-            c = cs.x;
-            sn = cs.y;
-          } else {
-            turn_sincos(phase_turn<Tin>(m, fv[i], q, at), c, sn);
-          }
           float2 pq = mypq[i];
-          pq.x = fmaf(cp, fmaf(c, zv[i].x, sn * zv[i].y), pq.x);
-          pq.y = fmaf(cp, fmaf(c, zv[i].z, sn * zv[i].w), pq.y);
+          if constexpr (PhaseLut<Tin>::kOn) {
+            // the table holds the pair's weight times cos and sin
+            const float2 cs = kLutLds ? slut[plane * 256 + (int)fv[i]] : lk[(int)fv[i]];
+            pq.x = fmaf(cs.x, zv[i].x, fmaf(cs.y, zv[i].y, pq.x));
+            pq.y = fmaf(cs.x, zv[i].z, fmaf(cs.y, zv[i].w, pq.y));
+          } else {
+            float c, sn;
+            turn_sincos(phase_turn<Tin>(m, fv[i], q, at), c, sn);
+            pq.x = fmaf(cp, fmaf(c, zv[i].x, sn * zv[i].y), pq.x);
+            pq.y = fmaf(cp, fmaf(c, zv[i].z, sn * zv[i].w), pq.y);
+          }
           mypq[i] = pq;
         }
       }
