@@ -1436,27 +1436,25 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
       const uint64_t q = e.qfix;
       const double at = e.alpha_turn;
       const float2 *lk = glut + (size_t)kl * 256;
-      // columns of this thread inside the image, kept in the loop (hoisted,
-      // the kC tests would hold lane masks in scalar registers)
-      int nx = min(max(g.W - x0, 0), kC);
-      asm volatile("" : "+v"(nx));
+      // every slot of the thread, also those of columns past the image (its
+      // samples there repeat the last column's, so the values stay finite):
+      // they are in the thread's own LDS range and never read back, and no
+      // per-column test is needed
 #pragma unroll
       for (int i = 0; i < kC; i++) {
-        if (i < nx) {
-          float2 pq = mypq[i];
-          if constexpr (PhaseLut<Tin>::kOn) {
-            // the table holds the pair's weight times cos and sin
-            const float2 cs = kLutLds ? slut[plane * 256 + (int)fv[i]] : lk[(int)fv[i]];
-            pq.x = fmaf(cs.x, zv[i].x, fmaf(cs.y, zv[i].y, pq.x));
-            pq.y = fmaf(cs.x, zv[i].z, fmaf(cs.y, zv[i].w, pq.y));
-          } else {
-            float c, sn;
-            turn_sincos(phase_turn<Tin>(m, fv[i], q, at), c, sn);
-            pq.x = fmaf(cp, fmaf(c, zv[i].x, sn * zv[i].y), pq.x);
-            pq.y = fmaf(cp, fmaf(c, zv[i].z, sn * zv[i].w), pq.y);
-          }
-          mypq[i] = pq;
+        float2 pq = mypq[i];
+        if constexpr (PhaseLut<Tin>::kOn) {
+          // the table holds the pair's weight times cos and sin
+          const float2 cs = kLutLds ? slut[plane * 256 + (int)fv[i]] : lk[(int)fv[i]];
+          pq.x = fmaf(cs.x, zv[i].x, fmaf(cs.y, zv[i].y, pq.x));
+          pq.y = fmaf(cs.x, zv[i].z, fmaf(cs.y, zv[i].w, pq.y));
+        } else {
+          float c, sn;
+          turn_sincos(phase_turn<Tin>(m, fv[i], q, at), c, sn);
+          pq.x = fmaf(cp, fmaf(c, zv[i].x, sn * zv[i].y), pq.x);
+          pq.y = fmaf(cp, fmaf(c, zv[i].z, sn * zv[i].w), pq.y);
         }
+        mypq[i] = pq;
       }
     }
   }
