@@ -1436,12 +1436,7 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
       const uint64_t q = e.qfix;
       const double at = e.alpha_turn;
       const float2 *lk = glut + (size_t)kl * 256;
-      // every slot of the thread, also those of columns past the image (its
-      // samples there repeat the last column's, so the values stay finite):
-      // they are in the thread's own LDS range and never read back, and no
-      // per-column test is needed
-#pragma unroll
-      for (int i = 0; i < kC; i++) {
+      auto combine = [&](int i) {
         float2 pq = mypq[i];
         if constexpr (PhaseLut<Tin>::kOn) {
           // the table holds the pair's weight times cos and sin
@@ -1455,6 +1450,23 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
           pq.y = fmaf(cp, fmaf(c, zv[i].z, sn * zv[i].w), pq.y);
         }
         mypq[i] = pq;
+      };
+      if constexpr (PhaseLut<Tin>::kOn && !kLutLds) {
+        // table reads from memory: none for the columns past the image
+        // (the test kept in the loop: hoisted, the kC tests would hold lane
+        // masks in scalar registers)
+        int nx = min(max(g.W - x0, 0), kC);
+        asm volatile("" : "+v"(nx));
+#pragma unroll
+        for (int i = 0; i < kC; i++)
+          if (i < nx) combine(i);
+      } else {
+        // every slot of the thread, also those of columns past the image (its
+        // samples there repeat the last column's, so the values stay finite):
+        // they are in the thread's own LDS range and never read back, and no
+        // per-column test is needed
+#pragma unroll
+        for (int i = 0; i < kC; i++) combine(i);
       }
     }
   }
