@@ -1048,10 +1048,12 @@ __device__ __forceinline__ void store_iir_lds(IirLds &L, const IirLdsRegs &r, in
 // The causal and anticausal cascade over one line held by a row group of S
 // threads (zv: this thread's kC samples, in place).  xw: this group's LDS
 // slots for the wave carries (S > 64); every thread of the workgroup calls it
-// (it holds barriers when S > 64).
+// (it holds barriers when S > 64).  The line ends with thread tlast's chunk:
+// the zero extension starts there, and the threads after it (whatever their
+// samples) pass nothing to the others and their outputs are not defined.
 template <int S, int kC>
 __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, float c2, const IirLds &L,
-                                           cfloat_p Apow, float4 (*xw)[3], int t, int lane) {
+                                           cfloat_p Apow, float4 (*xw)[3], int t, int lane, int tlast = S - 1) {
   constexpr int SW = S < 64 ? S : 64;
   constexpr int NW = S > 64 ? S / 64 : 1;
   const int ls = t % SW;
@@ -1085,7 +1087,7 @@ __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, fl
     }
     __syncthreads();
     apow_acc(sA + 9 * ls, Kc, exc);
-    if (t == S - 1) apow_acc(waveM, Kc, inc);
+    if (t == tlast) apow_acc(waveM, Kc, inc);
   }
   // true causal outputs.  In blocks of 16 samples: block b takes the carry
   // A^(16 b) exc, so that only the w rows of A^1..A^16 and A^16 itself are
@@ -1104,9 +1106,9 @@ __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, fl
       for (int j = 0; j < (kC < 16 ? kC : 16); j++) row1_acc(Apow + 9 * (j + 1), cb, zv[b0 + j]);
     }
   }
-  // zero extension beyond the padded end
+  // zero extension beyond the line's end
   float4 Eb[3] = {f4(0.f), f4(0.f), f4(0.f)};
-  if (t == S - 1) matvec3(L.Mts, inc, Eb);
+  if (t == tlast) matvec3(L.Mts, inc, Eb);
   // anticausal sweep from rest
   s = f4(0.f);
   w = f4(0.f);
@@ -1116,8 +1118,8 @@ __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, fl
     casc_step(a1, g2, c2, zv[i], s, w, d);
     zv[i] = w;
   }
-  float4 hd[3] = {s, w, d};
-  if (t == S - 1) apow_acc(sA + 9, Eb, hd);  // A^c
+  float4 hd[3] = {keep4(t <= tlast, s), keep4(t <= tlast, w), keep4(t <= tlast, d)};
+  if (t == tlast) apow_acc(sA + 9, Eb, hd);  // A^c
   scan_down<SW>(hd, sA, ls, lane);
   float4 ein[3];
 #pragma unroll
@@ -1138,7 +1140,7 @@ __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, fl
     __syncthreads();
     apow_acc(sA + 9 * (63 - ls), Kc, ein);
   }
-  if (t == S - 1) {
+  if (t == tlast) {
 #pragma unroll
     for (int r = 0; r < 3; r++) ein[r] = Eb[r];
   }
@@ -1395,17 +1397,22 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
   Tin fv[kC];
 #pragma unroll
   for (int i = 0; i < kC; i++) fv[i] = frow[min(x0 + i, g.W - 1)];
-  // threads past the row's positions (t >= Seff) load from position 0 and
-  // smooth zeros
+  // threads past the row's positions (t >= Seff) load from position 0.  The
+  // line ends with thread Seff - 1, so that what they smooth reaches no one
+  // (3 selects per pair instead of 4 kC).  16-bit input instead smooths zeros
+  // there and keeps the line at the whole group: at its register budget the
+  // other form spills one more register.
+  constexpr bool kZeroTail = std::is_same<Tin, uint16_t>::value;
   const bool tin = t < g.Seff;
   const int tq = tin ? t : 0;
+  const int tlast = kZeroTail ? S - 1 : g.Seff - 1;
   const size_t qstep = (size_t)g.Seff * qs;
   float4 zv[kC];
   {
     const int kl = kb + plane;
     const float4 *q = Z + (size_t)(kl < kend ? kl : 0) * g.Hz * g.Spos + z_index(g, y, tq);
 #pragma unroll
-    for (int i = 0; i < kC; i++, q += qstep) zv[i] = keep4(tin, *q);
+    for (int i = 0; i < kC; i++, q += qstep) zv[i] = kZeroTail ? keep4(tin, *q) : *q;
   }
   store_iir_lds(L, tr, tid);
   __syncthreads();
@@ -1425,9 +1432,9 @@ __device__ __forceinline__ void iir_h_accum_impl(const Tin *__restrict__ f, floa
     if (it > 0) {
       const float4 *q = Z + (size_t)(act ? kl : 0) * g.Hz * g.Spos + z_index(g, y, tq);
 #pragma unroll
-      for (int i = 0; i < kC; i++, q += qstep) zv[i] = keep4(tin, *q);
+      for (int i = 0; i < kC; i++, q += qstep) zv[i] = kZeroTail ? keep4(tin, *q) : *q;
     }
-    group_blur<S, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63);
+    group_blur<S, kC>(zv, a1, g2, c2, L, Apow, xw[grp], t, tid & 63, tlast);
     // eqs. (f1), (f2): weight by the phase at the output pixel
     if (act) {
       const int k = k0 + kl;
