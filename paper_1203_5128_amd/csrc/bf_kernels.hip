@@ -1087,7 +1087,10 @@ __device__ __forceinline__ void group_blur(float4 zv[kC], float a1, float g2, fl
     }
     __syncthreads();
     apow_acc(sA + 9 * ls, Kc, exc);
-    if (t == tlast) apow_acc(waveM, Kc, inc);
+    // the line's last thread also needs its inclusive state: the carry
+    // through its own chunk too (A^(c (ls + 1)); the wave matrix when it is
+    // a wave's last lane)
+    if (t == tlast) apow_acc(sA + 9 * (ls + 1), Kc, inc);
   }
   // true causal outputs.  In blocks of 16 samples: block b takes the carry
   // A^(16 b) exc, so that only the w rows of A^1..A^16 and A^16 itself are

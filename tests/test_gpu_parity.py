@@ -143,17 +143,21 @@ def test_widths_and_cross_wave_scan(width):
 
 
 @pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
-@pytest.mark.parametrize("width", [100, 1030, 1500, 2100])
-def test_row_ends_inside_the_row_group(width, dtype):
+@pytest.mark.parametrize("width,sigma_s", [(100, 2.5), (1030, 2.5), (1040, 8.0), (1500, 2.5), (2064, 8.0),
+                                           (2100, 2.5)])
+def test_row_ends_inside_the_row_group(width, sigma_s, dtype):
     """Rows shorter than their row group: the horizontal pass's line ends with
     the last thread holding positions (8-bit and float; 16-bit smooths zeros
     on the threads after it).  With 16 columns per thread: W = 100 ends inside
-    one 8-thread wave; W = 1030 at the first lane of the second wave of a
-    128-thread group; W = 1500 in the middle of that wave; W = 2100 in the
-    third wave of a 256-thread group, the fourth wave all past the row."""
+    one 8-thread wave; W = 1030 and 1040 at the first lane of the second wave
+    of a 128-thread group (1040 at the end of that lane's chunk, where the
+    boundary sees the previous wave's carry at full weight); W = 1500 in the
+    middle of that wave; W = 2064 at the first lane of the third wave of a
+    256-thread group and W = 2100 inside it, the fourth wave all past the
+    row."""
     img = gen_random(3 * width + len(dtype), 24, width, dtype=dtype)
     sc = 257.0 if dtype == "u16" else 1.0
-    compare(img, dtype, 2.5, 30.0 * sc, 1e-3, label=f"W={width} {dtype}")
+    compare(img, dtype, sigma_s, 30.0 * sc, 1e-3, label=f"W={width} ss={sigma_s} {dtype}")
 
 
 @pytest.mark.parametrize("shape", [(4097, 40), (6000, 64), (8192, 33), (24, 8192)])

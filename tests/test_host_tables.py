@@ -186,11 +186,14 @@ def _scan_down(v, S, SW, off, A):
     return v
 
 
-def model_blocked(x, C, off=0):
+def model_blocked(x, C, off=0, tail=None):
     """Both recursive-pass kernels on one line (a row, or a column): per-thread
     sweeps from rest, scans of the chunk states across each wave's row group
     (_scan_up, _scan_down), wave carries through LDS, corrections with the w
-    row of A^i."""
+    row of A^i.  tail=None: the line runs to the group's end (zero samples
+    after it).  tail=array: the line ends with the last thread holding
+    samples (as the horizontal pass for 8-bit and float rows) and the threads
+    after it take these samples instead of zeros, which must reach no one."""
     kC = C["kC"]
     W = len(x)
     S = 1
@@ -202,6 +205,10 @@ def model_blocked(x, C, off=0):
     off = off % 64 // SW * SW if SW < 64 else 0
     xp = np.zeros(S * kC)
     xp[:W] = x
+    tlast = S - 1
+    if tail is not None:
+        tlast = (W + kC - 1) // kC - 1
+        xp[(tlast + 1) * kC:] = tail[:(S - tlast - 1) * kC]
     a1, g2, c2 = C["a1"], C["g2"], C["c2"]
     A = C["lane"]
     zero3 = np.zeros(3)
@@ -221,18 +228,19 @@ def model_blocked(x, C, off=0):
             for w in range(wig):
                 Kc = tot[w] + C["wave"] @ Kc
             exc[t] = exc[t] + A[ls] @ Kc
-            if t == S - 1:
-                inc[t] = inc[t] + C["wave"] @ Kc
+            if t == tlast:  # the carry through its own chunk too
+                inc[t] = inc[t] + (A[ls + 1] if ls < 63 else C["wave"]) @ Kc
     for t in range(S):
         for i in range(kC):
             wt[t][i] += C["apow"][i + 1][1] @ exc[t]
-    Eb = C["mts"] @ inc[S - 1]
+    Eb = C["mts"] @ inc[tlast]
     zt, hd = [], []
     for t in range(S):
         z, st = _sweep(wt[t], zero3, a1, g2, c2, rev=True)
         zt.append(z)
         hd.append(st)
-    hd[S - 1] = hd[S - 1] + A[1] @ Eb
+    hd = [h if t <= tlast else np.zeros(3) for t, h in enumerate(hd)]
+    hd[tlast] = hd[tlast] + A[1] @ Eb
     hd = _scan_down(hd, S, SW, off, A)
     ein = [np.zeros(3) if t % SW == SW - 1 else hd[t + 1] for t in range(S)]
     if S > 64:
@@ -244,7 +252,7 @@ def model_blocked(x, C, off=0):
             for w in range(NW - 1, wig, -1):
                 Kc = tot[w] + C["wave"] @ Kc
             ein[t] = ein[t] + A[63 - ls] @ Kc
-    ein[S - 1] = Eb
+    ein[tlast] = Eb
     for t in range(S):
         for i in range(kC):
             zt[t][i] += C["apow"][kC - i][1] @ ein[t]
@@ -266,6 +274,29 @@ def test_blocked_model_matches_oracle(shim, c, sigma, n):
     for off in (0, 32, 48):  # where the row group sits in its wave
         got = model_blocked(x, C, off) * C["g1"] ** 2
         assert np.abs(got - ref).max() < 2e-5 * max(1.0, np.abs(ref).max()), off
+
+
+@pytest.mark.parametrize("c", [16, 32])
+@pytest.mark.parametrize("sigma", [3.0, 16.0])
+@pytest.mark.parametrize("n", [7, 100, 300, 1030, 1040, 1500, 2064, 2100, 4100])
+def test_blocked_model_line_end(shim, c, sigma, n):
+    """A line that ends before its row group, the threads after it holding
+    arbitrary samples: the oracle's recursive Gaussian, and the same outputs
+    whatever those samples are.  n = 1040 and 2064 (16-sample chunks) end
+    exactly at the first lane of a later wave, where the last thread's
+    inclusive state takes the previous waves' carry through its own chunk."""
+    if c == 16 and n > 16 * 256:
+        pytest.skip("lines longer than 4096 use the 32-sample chunk")
+    C = consts(shim, sigma, c)
+    rng = np.random.default_rng(2000 + n)
+    x = rng.uniform(-1, 1, n)
+    tail = rng.uniform(-50, 50, 256 * c)
+    ref = o.blur_1d(x, "iir", sigma)
+    for off in (0, 32):
+        got = model_blocked(x, C, off, tail=tail)
+        zero = model_blocked(x, C, off, tail=np.zeros_like(tail))
+        assert np.array_equal(got, zero), off
+        assert np.abs(got * C["g1"] ** 2 - ref).max() < 2e-5 * max(1.0, np.abs(ref).max()), off
 
 
 # ------------------------------------------------- polynomial range kernel
