@@ -23,8 +23,12 @@ def shim():
     os.makedirs(SHIM_DIR, exist_ok=True)
     srcs = [os.path.join(ROOT, "tests", "table_shim.cpp"),
             os.path.join(ROOT, "paper_1203_5128_amd", "csrc", "bf_tables.cpp")]
+    # built under a name of this process, then renamed, so that parallel
+    # test workers never load a half-written library
+    tmp = f"{SHIM}.{os.getpid()}"
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-I",
-                           os.path.join(ROOT, "include")] + srcs + ["-o", SHIM])
+                           os.path.join(ROOT, "include")] + srcs + ["-o", tmp])
+    os.replace(tmp, SHIM)
     L = ctypes.CDLL(SHIM)
     L.shim_order_N.argtypes = [ctypes.c_double, ctypes.c_double]
     L.shim_trunc_M.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
